@@ -1,0 +1,86 @@
+"""Plant plausible mistakes in a private copy of the oracle's C source and check the pins catch each.
+
+Every mutant is compiled on the CPU into a temporary library; the pins used
+here are the brute-force dense-matrix checks (explicit BLTT block matrices)
+and the dot-product identity.  A mutant that survives would mean the pins
+cannot tell that mistake from the paper's definition.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from bltt_dense import chain_matrix, to_time_major, from_time_major
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "s2w_oracle.c")
+
+MUTANTS = {
+    "eq1_dropped_last_lag": ("for (int64_t k = 0; k <= n; k++) acc += gk[k] * sj[n - k];",
+                             "for (int64_t k = 0; k < n; k++) acc += gk[k] * sj[n - k];"),
+    "dt_sign": ("vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) / dt;",
+                "vg[n] = (m[n] + (n > 0 ? m[n - 1] : 0.0)) / dt;"),
+    "dt_scale": ("vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) / dt;",
+                 "vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) * dt;"),
+    "dt_first_sample": ("vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) / dt;",
+                        "vg[n] = (m[n] - (n > 0 ? m[n - 1] : m[0])) / dt;"),
+    "eq2_wrong_index": ("for (int64_t k = 0; k <= n; k++) acc += fk[k] * vg[n - k];",
+                        "for (int64_t k = 0; k <= n; k++) acc += fk[n - k] * vg[n - k];"),
+    "eq2_transposed_F": ("const double* fk = F + (g * nobs + o) * nt;\n        const double* vg",
+                         "const double* fk = F + (o * nrows + g) * nt;\n        const double* vg"),
+    "adj_dropped_lag": ("for (int64_t k = 0; k + n < nt; k++) acc += fk[k] * ro[n + k];",
+                        "for (int64_t k = 0; k + n < nt - 1; k++) acc += fk[k] * ro[n + k];"),
+    "adj_dt_direction": ("wg[n] = (w[n] - (n + 1 < nt ? w[n + 1] : 0.0)) / dt;",
+                         "wg[n] = (w[n] - (n > 0 ? w[n - 1] : 0.0)) / dt;"),
+    "adj_convolution_not_correlation": ("for (int64_t k = 0; k + n < nt; k++) acc += gk[k] * wg[n + k];",
+                                        "for (int64_t k = 0; k <= n; k++) acc += gk[k] * wg[n - k];"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique in the oracle source"
+    path = tmp_path / f"{name}.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / f"lib_{name}.so"
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-std=c99", "-o", str(lib), str(path)], check=True)
+    L = ctypes.CDLL(str(lib))
+    i64, dbl, i32, vp = ctypes.c_int64, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p
+    L.s2w_oracle_forward_accum.argtypes = [i64, i64, i64, i64, dbl, i32, vp, vp, i64, vp, vp]
+    L.s2w_oracle_adjoint_accum.argtypes = [i64, i64, i64, i64, dbl, i32, vp, vp, i64, vp, vp]
+    return L
+
+
+def _pins_hold(L) -> bool:
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    rng = np.random.default_rng(3)
+    ngrid, nsub, nobs, nt, dt = 5, 3, 2, 8, 0.5
+    G = rng.standard_normal((ngrid, nsub, nt)); F = rng.standard_normal((ngrid, nobs, nt))
+    s = rng.standard_normal((1, nsub, nt)); r = rng.standard_normal((1, nobs, nt))
+    for diff in (0, 1):
+        A = chain_matrix(G, F, dt, diff)
+        y = np.zeros((1, nobs, nt)); gs = np.zeros((1, nsub, nt))
+        L.s2w_oracle_forward_accum(ngrid, nsub, nobs, nt, dt, diff, p(G), p(F), 1, p(s), p(y))
+        L.s2w_oracle_adjoint_accum(ngrid, nsub, nobs, nt, dt, diff, p(G), p(F), 1, p(r), p(gs))
+        if not np.allclose(y[0], from_time_major(A @ to_time_major(s[0]), nobs), rtol=1e-10, atol=1e-10):
+            return False
+        if not np.allclose(gs[0], from_time_major(A.T @ to_time_major(r[0]), nsub), rtol=1e-10, atol=1e-10):
+            return False
+        if abs(np.sum(y * r) - np.sum(s * gs)) > 1e-10 * np.linalg.norm(y) * np.linalg.norm(r):
+            return False
+    return True
+
+
+def test_unmutated_source_passes(tmp_path):
+    src = open(SRC).read()
+    L = _build(tmp_path, "clean", src[:40], src[:40])
+    assert _pins_hold(L)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    L = _build(tmp_path, name, old, new)
+    assert not _pins_hold(L), f"planted mistake '{name}' survived the pins"

@@ -1,0 +1,181 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each check is independent of the oracle's loop code: explicit block matrices
+built from the BLTT definition (Sec. II-B3), closed forms of geometric
+kernels, the Nt = 1 case that reduces to a plain matrix product, numpy's
+convolution for the composed kernel, and the defining invariants of a causal
+LTI map (Sec. II-A: linearity, causality, shift invariance, impulse response).
+"""
+import numpy as np
+import pytest
+
+from bltt_dense import chain_matrix, bltt_matrix, to_time_major, from_time_major
+
+DT = 0.5  # not 1, so a misplaced or missing 1/dt shows
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _dense(seed, ngrid, nsub, nobs, nt):
+    r = _rng(seed)
+    return (r.standard_normal((ngrid, nsub, nt)), r.standard_normal((ngrid, nobs, nt)))
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+@pytest.mark.parametrize("shape", [(5, 3, 2, 8), (4, 1, 1, 6), (1, 2, 3, 5), (3, 4, 2, 1)])
+def test_forward_matches_dense_bltt_chain(oracle_mod, diff, shape):
+    ngrid, nsub, nobs, nt = shape
+    G, F = _dense(11 + nt, ngrid, nsub, nobs, nt)
+    s = _rng(5).standard_normal((2, nsub, nt))
+    A = chain_matrix(G, F, DT, diff)
+    y = oracle_mod.forward(G, F, s, dt=DT, diff=diff)
+    for b in range(2):
+        yref = from_time_major(A @ to_time_major(s[b]), nobs)
+        np.testing.assert_allclose(y[b], yref, rtol=1e-12, atol=1e-12 * np.abs(yref).max())
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+@pytest.mark.parametrize("shape", [(5, 3, 2, 8), (2, 5, 3, 7)])
+def test_adjoint_matches_dense_transpose(oracle_mod, diff, shape):
+    ngrid, nsub, nobs, nt = shape
+    G, F = _dense(23 + nt, ngrid, nsub, nobs, nt)
+    r = _rng(6).standard_normal((3, nobs, nt))
+    A = chain_matrix(G, F, DT, diff)
+    gs = oracle_mod.adjoint(G, F, r, dt=DT, diff=diff)
+    for b in range(3):
+        ref = from_time_major(A.T @ to_time_major(r[b]), nsub)
+        np.testing.assert_allclose(gs[b], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_single_bltt_matches_dense(oracle_mod):
+    r = _rng(7)
+    K = r.standard_normal((3, 4, 6))          # [i][j][k] = [F_k]_{ij}
+    x = r.standard_normal((2, 4, 6))
+    M = bltt_matrix(np.transpose(K, (2, 0, 1)))
+    y = oracle_mod.bltt(K, x)
+    for b in range(2):
+        np.testing.assert_allclose(y[b], from_time_major(M @ to_time_major(x[b]), 3), rtol=1e-12, atol=1e-12)
+    yy = r.standard_normal((2, 3, 6))
+    xt = oracle_mod.bltt(K, yy, trans=True)
+    for b in range(2):
+        np.testing.assert_allclose(xt[b], from_time_major(M.T @ to_time_major(yy[b]), 4), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("a,b", [(0.9, 0.5), (-0.7, 0.3), (1.1, 0.95)])
+def test_closed_form_geometric_no_difference(oracle_mod, a, b):
+    # one subfault, one grid point, one observer; g_k = a^k, f_k = b^k, unit impulse at n = 0:
+    # y_n = sum_{k=0}^{n} a^k b^{n-k} = (a^{n+1} - b^{n+1}) / (a - b)
+    nt = 24
+    k = np.arange(nt)
+    G = (a ** k)[None, None, :]
+    F = (b ** k)[None, None, :]
+    s = np.zeros((1, nt)); s[0, 0] = 1.0
+    y = oracle_mod.forward(G, F, s, dt=1.0, diff=0)[0]
+    expect = (a ** (k + 1) - b ** (k + 1)) / (a - b)
+    np.testing.assert_allclose(y, expect, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("a,b,dt", [(0.9, 0.5, 1.0), (0.6, -0.8, 0.25)])
+def test_closed_form_geometric_backward_difference(oracle_mod, a, b, dt):
+    # m_n = a^n; v_0 = 1/dt, v_n = a^{n-1}(a - 1)/dt;
+    # y_n = [b^n + (a - 1)(a^n - b^n)/(a - b)] / dt
+    nt = 20
+    k = np.arange(nt)
+    G = (a ** k)[None, None, :]
+    F = (b ** k)[None, None, :]
+    s = np.zeros((1, nt)); s[0, 0] = 1.0
+    y = oracle_mod.forward(G, F, s, dt=dt, diff=1)[0]
+    expect = (b ** k + (a - 1) * (a ** k - b ** k) / (a - b)) / dt
+    np.testing.assert_allclose(y, expect, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+def test_single_step_is_matrix_product(oracle_mod, diff):
+    # Nt = 1: the BLTT operators are single blocks and D_t is 1/dt (or 1): y = F_q,0 F_G,0 s / dt
+    r = _rng(8)
+    G = r.standard_normal((7, 5, 1)); F = r.standard_normal((7, 3, 1)); s = r.standard_normal((4, 5, 1))
+    y = oracle_mod.forward(G, F, s, dt=DT, diff=diff)
+    scale = 1.0 / DT if diff else 1.0
+    expect = np.einsum("og,gj,bj->bo", F[:, :, 0].T, G[:, :, 0], s[:, :, 0]) * scale
+    np.testing.assert_allclose(y[:, :, 0], expect, rtol=1e-13)
+
+
+def _trunc_conv(a, b, nt):
+    return np.convolve(a, b)[:nt]
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+def test_impulse_returns_chain_and_composition(oracle_mod, diff):
+    # unit impulse at subfault j0, t = 0 returns sum_g f_{o,g} * D * g_{g,j0} (truncated), and the
+    # whole map equals one BLTT with kernel h_{o,j} = trunc(sum_g f_{o,g} * d * g_{g,j})
+    ngrid, nsub, nobs, nt = 4, 3, 2, 10
+    G, F = _dense(31, ngrid, nsub, nobs, nt)
+    d = np.zeros(nt); d[0] = 1.0 / DT
+    if diff:
+        d[1] = -1.0 / DT
+    else:
+        d[0] = 1.0
+    H = np.zeros((nobs, nsub, nt))
+    for o in range(nobs):
+        for j in range(nsub):
+            for g in range(ngrid):
+                H[o, j] += _trunc_conv(F[g, o], _trunc_conv(d, G[g, j], nt), nt)
+    for j0 in range(nsub):
+        s = np.zeros((nsub, nt)); s[j0, 0] = 1.0
+        y = oracle_mod.forward(G, F, s, dt=DT, diff=diff)
+        np.testing.assert_allclose(y, H[:, j0, :], rtol=1e-12, atol=1e-12)
+    s = _rng(9).standard_normal((nsub, nt))
+    y = oracle_mod.forward(G, F, s, dt=DT, diff=diff)
+    expect = np.array([sum(_trunc_conv(H[o, j], s[j], nt) for j in range(nsub)) for o in range(nobs)])
+    np.testing.assert_allclose(y, expect, rtol=1e-11, atol=1e-11)
+
+
+def test_linearity_causality_shift(oracle_mod):
+    ngrid, nsub, nobs, nt = 6, 4, 3, 16
+    G, F = _dense(41, ngrid, nsub, nobs, nt)
+    r = _rng(10)
+    s1, s2 = r.standard_normal((nsub, nt)), r.standard_normal((nsub, nt))
+    y1 = oracle_mod.forward(G, F, s1, dt=DT)
+    y2 = oracle_mod.forward(G, F, s2, dt=DT)
+    y12 = oracle_mod.forward(G, F, 2.5 * s1 - 0.75 * s2, dt=DT)
+    np.testing.assert_allclose(y12, 2.5 * y1 - 0.75 * y2, rtol=1e-12, atol=1e-12)
+    # causality: changing s at n >= n0 leaves y[:, :n0] bit-identical
+    n0 = 7
+    s3 = s1.copy(); s3[:, n0:] = r.standard_normal((nsub, nt - n0))
+    y3 = oracle_mod.forward(G, F, s3, dt=DT)
+    assert np.array_equal(y3[:, :n0], y1[:, :n0])
+    assert not np.allclose(y3[:, n0:], y1[:, n0:])
+    # time shift: s delayed by D gives y delayed by D, zeros before
+    D = 5
+    sd = np.zeros_like(s1); sd[:, D:] = s1[:, :nt - D]
+    yd = oracle_mod.forward(G, F, sd, dt=DT)
+    assert np.all(yd[:, :D] == 0)
+    np.testing.assert_allclose(yd[:, D:], y1[:, :nt - D], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+def test_dot_product_identity(oracle_mod, diff):
+    ngrid, nsub, nobs, nt = 9, 5, 3, 32
+    G, F = _dense(51, ngrid, nsub, nobs, nt)
+    r = _rng(12)
+    x = r.standard_normal((2, nsub, nt)); w = r.standard_normal((2, nobs, nt))
+    Ax = oracle_mod.forward(G, F, x, dt=DT, diff=diff)
+    ATw = oracle_mod.adjoint(G, F, w, dt=DT, diff=diff)
+    lhs, rhs = np.sum(Ax * w), np.sum(x * ATw)
+    assert abs(lhs - rhs) <= 1e-12 * np.linalg.norm(Ax) * np.linalg.norm(w)
+
+
+def test_chunked_rows_sum(oracle_mod, synth_mod):
+    # the map is a sum over grid rows (eq. 3 per share): row chunks accumulate to the whole
+    cfg = synth_mod.workload("small")
+    G = synth_mod.gen_G(cfg); F = synth_mod.gen_F(cfg); s = synth_mod.gen_slip(cfg, 3)
+    y_all = oracle_mod.forward(G, F, s)
+    y_chunk = oracle_mod.forward_synth(cfg, s, chunk_rows=100)
+    np.testing.assert_allclose(y_chunk, y_all, rtol=1e-13, atol=1e-16)
+    r = synth_mod.normals(1, "r", 0, (cfg.nobs, cfg.nt))
+    cols = np.array([0, 5, 15])
+    gs_all = oracle_mod.adjoint(G, F, r)
+    gs_sub = oracle_mod.adjoint_synth(cfg, r, cols=cols, chunk_rows=77)
+    np.testing.assert_allclose(gs_sub, gs_all[cols], rtol=1e-12, atol=1e-16)
