@@ -1,0 +1,155 @@
+/*
+ * s2w -- source-to-waveform map on one GPU's share of the seafloor grid.
+ *
+ * The map (paper Sec. II-B, eqs. 1-3) takes slip-rate histories s on Nsub
+ * fault subfaults to pressure waveforms q at Nobs observation points:
+ *
+ *   m_n = sum_{k=0}^{n} F_{G,k} s_{n-k}     elastic response, eq. (1)
+ *   v   = D_t m                             temporal difference per grid point
+ *   q_n = sum_{k=0}^{n} F_{q,k} v_{n-k}     waveform response, eq. (2)
+ *
+ * restricted to the Ngrid seafloor points of one share I_r (opposite row /
+ * column partitions, Sec. II-C): the result is one rank's term
+ * F_q^(r) D_t F_G^(r) s of eq. (3); the sum over ranks is the caller's.
+ * Both block lower-triangular Toeplitz products are evaluated by zero-padding
+ * the time axis and diagonalising it with a real FFT (Alg. 2), the seafloor
+ * field staying on the device between them (Alg. 1).
+ *
+ * D_t: the paper names only a "temporal-difference stencil".  S2W_DIFF_BACKWARD
+ * applies v_n = (m_n - m_{n-1})/dt with m_{-1} = 0 (causal, Toeplitz);
+ * S2W_DIFF_NONE makes D_t the identity.
+ *
+ * Conventions for every entry point:
+ *  - All device pointers must be 256-byte aligned and distinct.  The caller
+ *    allocates every byte of device memory (operator store, workspace, inputs,
+ *    outputs); the library never allocates device memory.
+ *  - Every call validates its arguments on the host before enqueuing
+ *    anything; an invalid call returns an error and enqueues nothing.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *    and is asynchronous: a call returns before the GPU finishes.  Forward
+ *    and adjoint allocate nothing and do not synchronise, so they may be
+ *    captured into a HIP graph.  One plan is used by one stream at a time.
+ *  - Failures never throw across this boundary; they return a status, and
+ *    s2w_last_error() gives the message of the plan's most recent failure.
+ *  - NaN or Inf in inputs or operators propagate; they are not checked.
+ */
+#ifndef S2W_H
+#define S2W_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define S2W_ABI_VERSION 1
+
+typedef struct s2w_plan s2w_plan;
+
+typedef enum s2w_status {
+  S2W_OK = 0,
+  S2W_EINVAL = 1,        /* bad argument: null/misaligned pointer, size, batch out of range */
+  S2W_ENOMEM = 2,        /* bound operator store or workspace smaller than s2w_query_sizes asks */
+  S2W_ESTATE = 3,        /* call out of order: memory not bound, operators not fully set */
+  S2W_EUNSUPPORTED = 4,  /* valid request this build does not implement (dtype, size limit) */
+  S2W_EHIP = 5           /* a HIP runtime call or kernel launch failed; see s2w_last_error */
+} s2w_status;
+
+typedef enum s2w_dtype {
+  S2W_F32 = 0,   /* complex64 spectra */
+  S2W_BF16 = 1,  /* bfloat16 real/imaginary parts with one float32 power-of-two scale per (grid row, bin) */
+  S2W_F16 = 2    /* float16 real/imaginary parts with one float32 power-of-two scale per (grid row, bin) */
+} s2w_dtype;
+
+typedef enum s2w_diff { S2W_DIFF_NONE = 0, S2W_DIFF_BACKWARD = 1 } s2w_diff;
+
+/* Problem description.  Limits of this build: 1 <= nt <= 512, 1 <= nsub <= 1024,
+ * 1 <= nobs <= 256, 1 <= ngrid, 0 <= max_batch <= 1024. */
+typedef struct s2w_desc {
+  int32_t nsub;       /* Nf: fault subfaults (columns of F_{G,k}) */
+  int32_t ngrid;      /* N_m^(r): seafloor points of this share (rows of F_{G,k}, columns of F_{q,k}) */
+  int32_t nobs;       /* N_q: observation points (rows of F_{q,k}) */
+  int32_t nt;         /* N_t: time steps */
+  int32_t max_batch;  /* largest number of ruptures per forward/adjoint call */
+  int32_t diff;       /* s2w_diff */
+  int32_t g_dtype;    /* s2w_dtype of the stored elastic spectra */
+  int32_t f_dtype;    /* s2w_dtype of the stored acoustic-gravity spectra */
+  double dt;          /* time step in seconds (> 0); enters only through D_t */
+} s2w_desc;
+
+/* Create a plan for `desc` on HIP device `device`.  Host-side only: no device
+ * memory is allocated.  *out receives the plan (NULL on failure). */
+s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out);
+
+/* Destroy a plan.  The caller must have synchronised the streams that used it.
+ * The bound memory is the caller's and is not freed.  NULL is a no-op. */
+s2w_status s2w_plan_destroy(s2w_plan* plan);
+
+/* Bytes of device memory the plan needs: the persistent operator store (the
+ * frequency-domain blocks of Alg. 2, resident between calls) and the scratch
+ * workspace used by set_operators, forward and adjoint at up to max_batch. */
+s2w_status s2w_query_sizes(const s2w_plan* plan, uint64_t* operator_bytes, uint64_t* workspace_bytes);
+
+/* Give the plan its memory.  Both regions stay owned by the caller and must
+ * outlive every call that uses the plan.  Sizes below s2w_query_sizes give
+ * S2W_ENOMEM.  Re-binding discards all operators set so far. */
+s2w_status s2w_bind_memory(s2w_plan* plan, void* operator_store, uint64_t operator_bytes, void* workspace,
+                           uint64_t workspace_bytes);
+
+/* One-time setup (excluded from the paper's timings, Sec. III-D): transform
+ * the time-domain blocks of grid rows [row0, row0+nrows) and keep their
+ * spectra in the operator store.  Device inputs, row-major float32:
+ *   G_chunk[r][j][k] = [F_{G,k}]_{row0+r, j}   shape [nrows][nsub][nt]   (eq. 1)
+ *   F_chunk[r][o][k] = [F_{q,k}]_{o, row0+r}   shape [nrows][nobs][nt]   (eq. 2)
+ * Chunks may arrive in any order and may overlap (later wins); the inputs may
+ * be freed once `stream` has passed this call.  Forward and adjoint require
+ * every row to have been set since the last bind. */
+s2w_status s2w_set_operators(s2w_plan* plan, const float* G_chunk, const float* F_chunk, int64_t row0, int64_t nrows,
+                             void* stream);
+
+/* Forward map for B ruptures (0 <= B <= max_batch; B = 0 enqueues nothing):
+ *   s[b][j][n]  slip rate, float32 [B][nsub][nt] (device)
+ *   y[b][o][n]  this share's partial waveforms F_q^(r) D_t F_G^(r) s, float32 [B][nobs][nt] (device, overwritten)
+ * Deterministic: identical inputs give bit-identical outputs. */
+s2w_status s2w_forward(s2w_plan* plan, const float* s, int32_t B, float* y, void* stream);
+
+/* Adjoint (transpose) of the forward map as a real linear operator, including
+ * the transpose of D_t: gs = A^T r, so that for L = 0.5 ||A s - y_obs||^2 the
+ * gradient is dL/ds = adjoint(A s - y_obs).
+ *   r[b][o][n]   float32 [B][nobs][nt] (device)
+ *   gs[b][j][n]  float32 [B][nsub][nt] (device, overwritten) */
+s2w_status s2w_adjoint(s2w_plan* plan, const float* r, int32_t B, float* gs, void* stream);
+
+/* Kernel-shape controls for the tuner.  Zero fields keep the library default. */
+typedef struct s2w_tuning {
+  int32_t fused_wg_per_cu;   /* single-rupture fused kernel: workgroups per compute unit (1..4) */
+  int32_t fused_rows;        /* single-rupture fused kernel: grid rows per tile (4 or 8) */
+  int32_t adj_slots;         /* single-rupture adjoint: frequency bins per workgroup (4 or 8) */
+  int32_t adj_splits;        /* single-rupture adjoint: grid splits of the transposed elastic stage */
+  int32_t batch_path_min_b;  /* smallest B that takes the batched matrix-core path */
+} s2w_tuning;
+
+s2w_status s2w_set_tuning(s2w_plan* plan, const s2w_tuning* t);
+s2w_status s2w_get_tuning(const s2w_plan* plan, s2w_tuning* t);
+
+/* Measurement hook: when both events are non-NULL (hipEvent_t), the next
+ * forward/adjoint calls record `begin` immediately before and `end` immediately
+ * after their dominant kernel (the one streaming the elastic spectra), on the
+ * call's stream.  Pass NULLs to stop.  Events are created and owned by the caller. */
+s2w_status s2w_set_profile_events(s2w_plan* plan, void* begin, void* end);
+
+/* Padded transform length L (a power of two >= 2*nt - 1, at least 32) and the
+ * number of stored complex values per spectrum, L/2 (bins 0 and L/2 are real
+ * and share one slot). */
+s2w_status s2w_transform_length(const s2w_plan* plan, int32_t* L);
+
+const char* s2w_status_string(s2w_status st);
+const char* s2w_last_error(const s2w_plan* plan);
+int32_t s2w_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S2W_H */

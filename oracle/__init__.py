@@ -33,7 +33,7 @@ DIFF_BACKWARD = 1
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle into ``libs2w_oracle.so`` (gcc, OpenMP, FP64)."""
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC]
+    cmd = ["gcc", "-O3", "-mavx2", "-mfma", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall", "-o", _LIB_PATH + ".tmp", _SRC]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -116,6 +116,37 @@ def _chunks(n: int, size: int):
         yield r0, min(size, n - r0)
 
 
+class _ChunkBuffers:
+    """Reusable host buffers for operator chunks (fresh allocations page-fault slowly)."""
+
+    def __init__(self):
+        self.bufs = {}
+
+    def get(self, key, shape, dtype):
+        b = self.bufs.get(key)
+        n = int(np.prod(shape))
+        if b is None or b.size < n or b.dtype != dtype:
+            b = np.empty(n, dtype=dtype)
+            self.bufs[key] = b
+        return b[:n].reshape(shape)
+
+
+_BUF = _ChunkBuffers()
+
+
+def _operator_chunk(cfg, r0, nr, cols):
+    import synth
+    g32 = _BUF.get("g32", (nr, len(cols), cfg.nt), np.float32)
+    f32 = _BUF.get("f32", (nr, cfg.nobs, cfg.nt), np.float32)
+    synth.gen_G(cfg, r0, nr, cols=cols, out=g32)
+    synth.gen_F(cfg, r0, nr, out=f32)
+    G = _BUF.get("g64", g32.shape, np.float64)
+    F = _BUF.get("f64", f32.shape, np.float64)
+    np.copyto(G, g32)
+    np.copyto(F, f32)
+    return G, F
+
+
 def forward_synth(cfg, s, dt: float | None = None, diff: int = DIFF_BACKWARD, chunk_rows: int = 512) -> np.ndarray:
     """Forward map over a whole synthetic share, operators regenerated in grid-row chunks.
 
@@ -136,8 +167,7 @@ def forward_synth(cfg, s, dt: float | None = None, diff: int = DIFF_BACKWARD, ch
     lib = _load()
     if len(cols):
         for r0, nr in _chunks(cfg.ngrid, chunk_rows):
-            G = _d(synth.gen_G(cfg, r0, nr, cols=cols))
-            F = _d(synth.gen_F(cfg, r0, nr))
+            G, F = _operator_chunk(cfg, r0, nr, cols)
             lib.s2w_oracle_forward_accum(nr, len(cols), cfg.nobs, cfg.nt, dt, diff, _p(G), _p(F), B, _p(sa), _p(y))
     return y[0] if squeeze else y
 
@@ -148,7 +178,6 @@ def adjoint_synth(cfg, r, cols=None, dt: float | None = None, diff: int = DIFF_B
 
     Returns gs[b][q][n] for j = cols[q].
     """
-    import synth
     r = _d(r)
     squeeze = r.ndim == 2
     if squeeze:
@@ -159,8 +188,7 @@ def adjoint_synth(cfg, r, cols=None, dt: float | None = None, diff: int = DIFF_B
     gs = np.zeros((B, len(cols), cfg.nt))
     lib = _load()
     for r0, nr in _chunks(cfg.ngrid, chunk_rows):
-        G = _d(synth.gen_G(cfg, r0, nr, cols=cols))
-        F = _d(synth.gen_F(cfg, r0, nr))
+        G, F = _operator_chunk(cfg, r0, nr, cols)
         lib.s2w_oracle_adjoint_accum(nr, len(cols), cfg.nobs, cfg.nt, dt, diff, _p(G), _p(F), B, _p(r), _p(gs))
     return gs[0] if squeeze else gs
 

@@ -44,10 +44,9 @@ static void seafloor_velocity(int64_t nrows, int64_t nsub, int64_t nt, double dt
       for (int64_t j = 0; j < nsub; j++) {
         const double* gk = G + (g * nsub + j) * nt;
         const double* sj = s + (b * nsub + j) * nt;
-        for (int64_t n = 0; n < nt; n++) {
-          double acc = 0.0;
-          for (int64_t k = 0; k <= n; k++) acc += gk[k] * sj[n - k];
-          m[n] += acc;
+        for (int64_t k = 0; k < nt; k++) {
+          const double gv = gk[k];
+          for (int64_t n = k; n < nt; n++) m[n] += gv * sj[n - k];
         }
       }
       /* D_t */
@@ -74,10 +73,9 @@ void s2w_oracle_forward_accum(int64_t nrows, int64_t nsub, int64_t nobs, int64_t
       for (int64_t g = 0; g < nrows; g++) {
         const double* fk = F + (g * nobs + o) * nt;
         const double* vg = v + (g * B + b) * nt;
-        for (int64_t n = 0; n < nt; n++) {
-          double acc = 0.0;
-          for (int64_t k = 0; k <= n; k++) acc += fk[k] * vg[n - k];
-          yo[n] += acc;
+        for (int64_t k = 0; k < nt; k++) {
+          const double fv = fk[k];
+          for (int64_t n = k; n < nt; n++) yo[n] += fv * vg[n - k];
         }
       }
     }
@@ -98,10 +96,9 @@ void s2w_oracle_adjoint_accum(int64_t nrows, int64_t nsub, int64_t nobs, int64_t
       for (int64_t o = 0; o < nobs; o++) {
         const double* fk = F + (g * nobs + o) * nt;
         const double* ro = r + (b * nobs + o) * nt;
-        for (int64_t n = 0; n < nt; n++) {
-          double acc = 0.0;
-          for (int64_t k = 0; k + n < nt; k++) acc += fk[k] * ro[n + k];
-          w[n] += acc;
+        for (int64_t k = 0; k < nt; k++) {
+          const double fv = fk[k];
+          for (int64_t n = 0; n + k < nt; n++) w[n] += fv * ro[n + k];
         }
       }
       /* D_t transposed */
@@ -121,10 +118,9 @@ void s2w_oracle_adjoint_accum(int64_t nrows, int64_t nsub, int64_t nobs, int64_t
       for (int64_t g = 0; g < nrows; g++) {
         const double* gk = G + (g * nsub + j) * nt;
         const double* wg = wp + (g * B + b) * nt;
-        for (int64_t n = 0; n < nt; n++) {
-          double acc = 0.0;
-          for (int64_t k = 0; k + n < nt; k++) acc += gk[k] * wg[n + k];
-          gj[n] += acc;
+        for (int64_t k = 0; k < nt; k++) {
+          const double gv = gk[k];
+          for (int64_t n = 0; n + k < nt; n++) gj[n] += gv * wg[n + k];
         }
       }
     }

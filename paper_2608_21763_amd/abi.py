@@ -1,0 +1,142 @@
+"""ctypes binding of the C-ABI in ``include/s2w.h`` (argument marshalling only).
+
+Every entry point maps one-to-one onto an ``s2w_*`` function.  Nothing here
+computes any part of the map; a missing library raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libs2w.so")
+
+DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+DIFF_NONE = 0
+DIFF_BACKWARD = 1
+
+STATUS = {0: "S2W_OK", 1: "S2W_EINVAL", 2: "S2W_ENOMEM", 3: "S2W_ESTATE", 4: "S2W_EUNSUPPORTED", 5: "S2W_EHIP"}
+
+
+class S2WError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"{where}: {self.code}" + (f" ({detail})" if detail else ""))
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("nsub", ctypes.c_int32), ("ngrid", ctypes.c_int32), ("nobs", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("diff", ctypes.c_int32),
+                ("g_dtype", ctypes.c_int32), ("f_dtype", ctypes.c_int32), ("dt", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_slots", ctypes.c_int32),
+                ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32)]
+
+
+EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_create", "s2w_plan_destroy",
+           "s2w_query_sizes", "s2w_bind_memory", "s2w_set_operators", "s2w_forward", "s2w_adjoint",
+           "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events"]
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load ``libs2w.so``; raises if it has not been built (no fallback path exists)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with paper_2608_21763_amd/build_lib.py (or __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    P, vp, i32, i64, u64 = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    plan_p = vp
+    lib.s2w_abi_version.restype = i32
+    lib.s2w_status_string.restype = ctypes.c_char_p
+    lib.s2w_status_string.argtypes = [i32]
+    lib.s2w_last_error.restype = ctypes.c_char_p
+    lib.s2w_last_error.argtypes = [plan_p]
+    lib.s2w_plan_create.argtypes = [P(Desc), i32, P(plan_p)]
+    lib.s2w_plan_destroy.argtypes = [plan_p]
+    lib.s2w_query_sizes.argtypes = [plan_p, P(u64), P(u64)]
+    lib.s2w_bind_memory.argtypes = [plan_p, vp, u64, vp, u64]
+    lib.s2w_set_operators.argtypes = [plan_p, vp, vp, i64, i64, vp]
+    lib.s2w_forward.argtypes = [plan_p, vp, i32, vp, vp]
+    lib.s2w_adjoint.argtypes = [plan_p, vp, i32, vp, vp]
+    lib.s2w_set_tuning.argtypes = [plan_p, P(Tuning)]
+    lib.s2w_get_tuning.argtypes = [plan_p, P(Tuning)]
+    lib.s2w_transform_length.argtypes = [plan_p, P(i32)]
+    lib.s2w_set_profile_events.argtypes = [plan_p, vp, vp]
+    for name in EXPORTS:
+        if name not in ("s2w_abi_version", "s2w_status_string", "s2w_last_error"):
+            getattr(lib, name).restype = i32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class Plan:
+    """Thin owner of an ``s2w_plan*``; methods mirror the C entry points."""
+
+    def __init__(self, nsub: int, ngrid: int, nobs: int, nt: int, max_batch: int = 1, dt: float = 1.0,
+                 diff: int = DIFF_BACKWARD, g_dtype: str = "f32", f_dtype: str = "f32", device: int = 0):
+        self.lib = load_library()
+        self.desc = Desc(nsub, ngrid, nobs, nt, max_batch, diff, DTYPES[g_dtype], DTYPES[f_dtype], dt)
+        self.handle = ctypes.c_void_p()
+        st = self.lib.s2w_plan_create(ctypes.byref(self.desc), device, ctypes.byref(self.handle))
+        if st != 0:
+            raise S2WError(st, "s2w_plan_create")
+
+    def _check(self, st: int, where: str):
+        if st != 0:
+            msg = self.lib.s2w_last_error(self.handle)
+            raise S2WError(st, where, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.s2w_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query_sizes(self):
+        op, ws = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self.lib.s2w_query_sizes(self.handle, ctypes.byref(op), ctypes.byref(ws)), "s2w_query_sizes")
+        return op.value, ws.value
+
+    def transform_length(self) -> int:
+        L = ctypes.c_int32()
+        self._check(self.lib.s2w_transform_length(self.handle, ctypes.byref(L)), "s2w_transform_length")
+        return L.value
+
+    def bind(self, op_ptr: int, op_bytes: int, ws_ptr: int, ws_bytes: int):
+        self._check(self.lib.s2w_bind_memory(self.handle, op_ptr, op_bytes, ws_ptr, ws_bytes), "s2w_bind_memory")
+
+    def set_operators(self, g_ptr: int, f_ptr: int, row0: int, nrows: int, stream: int = 0):
+        self._check(self.lib.s2w_set_operators(self.handle, g_ptr, f_ptr, row0, nrows, stream), "s2w_set_operators")
+
+    def forward(self, s_ptr: int, B: int, y_ptr: int, stream: int = 0):
+        self._check(self.lib.s2w_forward(self.handle, s_ptr, B, y_ptr, stream), "s2w_forward")
+
+    def adjoint(self, r_ptr: int, B: int, gs_ptr: int, stream: int = 0):
+        self._check(self.lib.s2w_adjoint(self.handle, r_ptr, B, gs_ptr, stream), "s2w_adjoint")
+
+    def set_profile_events(self, begin: int = 0, end: int = 0):
+        """hipEvent_t handles (ints) recorded around the dominant kernel of later calls; 0, 0 stops."""
+        self._check(self.lib.s2w_set_profile_events(self.handle, begin or None, end or None), "s2w_set_profile_events")
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.lib.s2w_get_tuning(self.handle, ctypes.byref(t)), "s2w_get_tuning")
+        return {n: getattr(t, n) for n, _ in Tuning._fields_}
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{n: int(kw.get(n, 0)) for n, _ in Tuning._fields_})
+        self._check(self.lib.s2w_set_tuning(self.handle, ctypes.byref(t)), "s2w_set_tuning")

@@ -1,0 +1,413 @@
+// C-ABI of the source-to-waveform library: plan, memory binding, setup and the
+// forward/adjoint entry points.  Host code only; kernels live in the *.hip files.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/s2w.h"
+#include "s2w_internal.h"
+
+using namespace s2w;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr int kMaxWgPerCu = 4;
+constexpr int kMaxSplits = 64;
+
+inline uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+inline int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Offsets of the regions carved out of the bound memory.
+struct Layout {
+  // operator store
+  uint64_t gh, fh, op_total;
+  // workspace
+  uint64_t sh, part, yh, rh, wp, part2, gsh, ws_total;
+};
+
+}  // namespace
+
+struct s2w_plan {
+  s2w_desc desc;
+  int device;
+  int ncu;
+  Geometry geo;
+  Layout lay;
+  s2w_tuning tune;
+  char* op = nullptr;
+  char* ws = nullptr;
+  uint64_t op_bytes = 0, ws_bytes = 0;
+  std::vector<uint8_t> row_set;  // one flag per grid row set since the last bind
+  int64_t rows_missing = 0;
+  std::string err;
+  hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+};
+
+namespace {
+
+s2w_status fail(s2w_plan* p, s2w_status st, const char* fmt, ...) {
+  if (p) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    p->err = buf;
+  }
+  return st;
+}
+
+s2w_status hip_fail(s2w_plan* p, hipError_t e, const char* what) {
+  return fail(p, S2W_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void* ptr) { return ((uintptr_t)ptr % kAlign) == 0; }
+
+std::mutex g_tw_mutex;
+std::vector<int> g_tw_done;
+
+hipError_t ensure_twiddles(int device) {
+  std::lock_guard<std::mutex> lk(g_tw_mutex);
+  if ((int)g_tw_done.size() <= device) g_tw_done.resize(device + 1, 0);
+  if (g_tw_done[device]) return hipSuccess;
+  hipError_t e = upload_twiddles(device);
+  if (e == hipSuccess) g_tw_done[device] = 1;
+  return e;
+}
+
+// Scoped switch to the plan's device.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+Layout make_layout(const s2w_desc& d, const Geometry& g, int ncu) {
+  Layout L{};
+  const uint64_t c8 = sizeof(float2);
+  uint64_t off = 0;
+  L.gh = off;
+  off = round_up(off + (uint64_t)g.ngrid * g.M * g.nsp * c8, kAlign);
+  L.fh = off;
+  off = round_up(off + (uint64_t)g.ngrid * g.M * g.nop * c8, kAlign);
+  L.op_total = off;
+
+  off = 0;
+  const int nwg_max = ncu * kMaxWgPerCu;
+  L.sh = off;
+  off = round_up(off + (uint64_t)g.M * g.nsp * c8, kAlign);
+  L.part = off;
+  const uint64_t part_fwd = (uint64_t)nwg_max * g.M * g.nop * c8;
+  const uint64_t part_split = (uint64_t)kMaxSplits * g.M * std::max(g.nsp, g.nop) * c8;
+  off = round_up(off + std::max(part_fwd, part_split), kAlign);
+  L.yh = off;
+  off = round_up(off + (uint64_t)std::max(g.nobs, g.nsub) * g.M * c8, kAlign);
+  L.rh = off;
+  off = round_up(off + (uint64_t)g.M * g.nop * c8, kAlign);
+  L.wp = off;
+  off = round_up(off + (uint64_t)g.ngrid * g.M * c8, kAlign);
+  L.part2 = L.part;  // the adjoint reuses the partial region
+  L.gsh = L.yh;
+  L.ws_total = off;
+  (void)d;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t s2w_abi_version(void) { return S2W_ABI_VERSION; }
+
+const char* s2w_status_string(s2w_status st) {
+  switch (st) {
+    case S2W_OK: return "ok";
+    case S2W_EINVAL: return "invalid argument";
+    case S2W_ENOMEM: return "bound memory too small";
+    case S2W_ESTATE: return "call out of order";
+    case S2W_EUNSUPPORTED: return "unsupported";
+    case S2W_EHIP: return "HIP error";
+  }
+  return "unknown status";
+}
+
+const char* s2w_last_error(const s2w_plan* plan) { return plan ? plan->err.c_str() : ""; }
+
+s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out) {
+  if (!out) return S2W_EINVAL;
+  *out = nullptr;
+  if (!desc) return S2W_EINVAL;
+  const s2w_desc& d = *desc;
+  if (d.nsub < 1 || d.nsub > 1024 || d.nobs < 1 || d.nobs > 256 || d.nt < 1 || d.nt > 512 || d.ngrid < 1 ||
+      d.max_batch < 0 || d.max_batch > 1024 || !(d.dt > 0.0) || (d.diff != S2W_DIFF_NONE && d.diff != S2W_DIFF_BACKWARD))
+    return S2W_EINVAL;
+  if (d.g_dtype < S2W_F32 || d.g_dtype > S2W_F16 || d.f_dtype < S2W_F32 || d.f_dtype > S2W_F16) return S2W_EINVAL;
+  if (d.g_dtype != S2W_F32 || d.f_dtype != S2W_F32) return S2W_EUNSUPPORTED;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return S2W_EINVAL;
+
+  s2w_plan* p = new (std::nothrow) s2w_plan();
+  if (!p) return S2W_ENOMEM;
+  p->desc = d;
+  p->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu <= 0) ncu = 256;
+  p->ncu = ncu;
+  Geometry& g = p->geo;
+  g.nsub = d.nsub;
+  g.ngrid = d.ngrid;
+  g.nobs = d.nobs;
+  g.nt = d.nt;
+  g.L = std::max(32, next_pow2(2 * d.nt - 1));
+  g.M = g.L / 2;
+  g.logM = ilog2(g.M);
+  g.nsp = (d.nsub + 1) / 2 * 2;
+  g.nop = (d.nobs + 1) / 2 * 2;
+  g.nsp4 = g.nsp / 2;
+  g.nop4 = g.nop / 2;
+  g.diff = d.diff;
+  g.dt = (float)d.dt;
+  p->lay = make_layout(d, g, ncu);
+  p->tune.fused_wg_per_cu = 1;
+  p->tune.fused_rows = 8;
+  p->tune.adj_slots = 8;
+  p->tune.adj_splits = 16;
+  p->tune.batch_path_min_b = 1 << 30;
+  p->row_set.assign((size_t)d.ngrid, 0);
+  p->rows_missing = d.ngrid;
+  {
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+      delete p;
+      return S2W_EHIP;
+    }
+    if (ensure_twiddles(device) != hipSuccess) {
+      delete p;
+      return S2W_EHIP;
+    }
+  }
+  *out = p;
+  return S2W_OK;
+}
+
+s2w_status s2w_plan_destroy(s2w_plan* plan) {
+  delete plan;
+  return S2W_OK;
+}
+
+s2w_status s2w_query_sizes(const s2w_plan* p, uint64_t* operator_bytes, uint64_t* workspace_bytes) {
+  if (!p) return S2W_EINVAL;
+  if (operator_bytes) *operator_bytes = p->lay.op_total;
+  if (workspace_bytes) *workspace_bytes = p->lay.ws_total;
+  return S2W_OK;
+}
+
+s2w_status s2w_transform_length(const s2w_plan* p, int32_t* L) {
+  if (!p || !L) return S2W_EINVAL;
+  *L = p->geo.L;
+  return S2W_OK;
+}
+
+s2w_status s2w_bind_memory(s2w_plan* p, void* operator_store, uint64_t operator_bytes, void* workspace,
+                           uint64_t workspace_bytes) {
+  if (!p) return S2W_EINVAL;
+  if (!operator_store || !workspace) return fail(p, S2W_EINVAL, "bind: null pointer");
+  if (!aligned(operator_store) || !aligned(workspace)) return fail(p, S2W_EINVAL, "bind: pointers must be 256-byte aligned");
+  if (operator_bytes < p->lay.op_total)
+    return fail(p, S2W_ENOMEM, "bind: operator store %llu bytes < required %llu", (unsigned long long)operator_bytes,
+                (unsigned long long)p->lay.op_total);
+  if (workspace_bytes < p->lay.ws_total)
+    return fail(p, S2W_ENOMEM, "bind: workspace %llu bytes < required %llu", (unsigned long long)workspace_bytes,
+                (unsigned long long)p->lay.ws_total);
+  p->op = (char*)operator_store;
+  p->ws = (char*)workspace;
+  p->op_bytes = operator_bytes;
+  p->ws_bytes = workspace_bytes;
+  std::fill(p->row_set.begin(), p->row_set.end(), 0);
+  p->rows_missing = p->desc.ngrid;
+  return S2W_OK;
+}
+
+s2w_status s2w_set_profile_events(s2w_plan* p, void* begin, void* end) {
+  if (!p) return S2W_EINVAL;
+  if ((begin == nullptr) != (end == nullptr)) return fail(p, S2W_EINVAL, "profile events: pass both or neither");
+  p->ev_begin = (hipEvent_t)begin;
+  p->ev_end = (hipEvent_t)end;
+  return S2W_OK;
+}
+
+static hipError_t mark(hipEvent_t ev, hipStream_t st) { return ev ? hipEventRecord(ev, st) : hipSuccess; }
+
+s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
+  if (!p || !t) return S2W_EINVAL;
+  s2w_tuning n = p->tune;
+  if (t->fused_wg_per_cu) {
+    if (t->fused_wg_per_cu < 1 || t->fused_wg_per_cu > kMaxWgPerCu) return fail(p, S2W_EINVAL, "tuning: fused_wg_per_cu");
+    n.fused_wg_per_cu = t->fused_wg_per_cu;
+  }
+  if (t->fused_rows) {
+    if (t->fused_rows != 4 && t->fused_rows != 8) return fail(p, S2W_EINVAL, "tuning: fused_rows must be 4 or 8");
+    n.fused_rows = t->fused_rows;
+  }
+  if (t->adj_slots) {
+    if (t->adj_slots != 4 && t->adj_slots != 8) return fail(p, S2W_EINVAL, "tuning: adj_slots must be 4 or 8");
+    n.adj_slots = t->adj_slots;
+  }
+  if (t->adj_splits) {
+    if (t->adj_splits < 1 || t->adj_splits > kMaxSplits) return fail(p, S2W_EINVAL, "tuning: adj_splits");
+    n.adj_splits = t->adj_splits;
+  }
+  if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
+  p->tune = n;
+  return S2W_OK;
+}
+
+s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
+  if (!p || !t) return S2W_EINVAL;
+  *t = p->tune;
+  return S2W_OK;
+}
+
+s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_chunk, int64_t row0, int64_t nrows,
+                             void* stream) {
+  if (!p) return S2W_EINVAL;
+  if (!p->op) return fail(p, S2W_ESTATE, "set_operators: memory not bound");
+  if (!G_chunk || !F_chunk) return fail(p, S2W_EINVAL, "set_operators: null chunk pointer");
+  if (!aligned(G_chunk) || !aligned(F_chunk)) return fail(p, S2W_EINVAL, "set_operators: chunk pointers must be 256-byte aligned");
+  if (row0 < 0 || nrows < 0 || row0 + nrows > p->desc.ngrid)
+    return fail(p, S2W_EINVAL, "set_operators: rows [%lld, %lld) outside [0, %d)", (long long)row0,
+                (long long)(row0 + nrows), p->desc.ngrid);
+  if (nrows == 0) return S2W_OK;
+  const Geometry& g = p->geo;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(p, S2W_EHIP, "set_operators: cannot select device %d", p->device);
+  hipStream_t st = (hipStream_t)stream;
+  float2* Gh = (float2*)(p->op + p->lay.gh);
+  float2* Fh = (float2*)(p->op + p->lay.fh);
+  hipError_t e = launch_rfft_rows(G_chunk, nrows, g.nsub, g.nsp, Gh + row0 * g.M * g.nsp, (int64_t)g.M * g.nsp, 1,
+                                  g.nsp, g, 1.0f, st);
+  if (e != hipSuccess) return hip_fail(p, e, "set_operators: elastic transform");
+  e = launch_rfft_rows(F_chunk, nrows, g.nobs, g.nop, Fh + row0 * g.M * g.nop, (int64_t)g.M * g.nop, 1, g.nop, g,
+                       1.0f, st);
+  if (e != hipSuccess) return hip_fail(p, e, "set_operators: acoustic transform");
+  for (int64_t r = row0; r < row0 + nrows; ++r) {
+    if (!p->row_set[(size_t)r]) {
+      p->row_set[(size_t)r] = 1;
+      --p->rows_missing;
+    }
+  }
+  return S2W_OK;
+}
+
+static s2w_status check_call(s2w_plan* p, const void* in, int32_t B, const void* out, const char* who) {
+  if (!p) return S2W_EINVAL;
+  if (B < 0 || B > p->desc.max_batch) return fail(p, S2W_EINVAL, "%s: B=%d outside [0, %d]", who, B, p->desc.max_batch);
+  if (B == 0) return S2W_OK;
+  if (!in || !out) return fail(p, S2W_EINVAL, "%s: null pointer", who);
+  if (!aligned(in) || !aligned(out)) return fail(p, S2W_EINVAL, "%s: pointers must be 256-byte aligned", who);
+  if (in == out) return fail(p, S2W_EINVAL, "%s: input and output must be distinct", who);
+  if (!p->op) return fail(p, S2W_ESTATE, "%s: memory not bound", who);
+  if (p->rows_missing > 0)
+    return fail(p, S2W_ESTATE, "%s: %lld grid rows have no operators yet", who, (long long)p->rows_missing);
+  return S2W_OK;
+}
+
+s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
+  s2w_status cs = check_call(p, s, B, y, "forward");
+  if (cs != S2W_OK || B == 0) return cs;
+  const Geometry& g = p->geo;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(p, S2W_EHIP, "forward: cannot select device %d", p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const float2* Gh = (const float2*)(p->op + p->lay.gh);
+  const float2* Fh = (const float2*)(p->op + p->lay.fh);
+  float2* Sh = (float2*)(p->ws + p->lay.sh);
+  float2* part = (float2*)(p->ws + p->lay.part);
+  float2* yh = (float2*)(p->ws + p->lay.yh);
+  float2* Vh = (float2*)(p->ws + p->lay.wp);
+  const bool fused = (int64_t)g.M * g.nop4 <= FUSED_MAX_ITEMS;
+  const int nwg = p->ncu * p->tune.fused_wg_per_cu;
+  const float inv_l = 1.0f / (float)g.L;
+  for (int b = 0; b < B; ++b) {
+    const float* sb = s + (int64_t)b * g.nsub * g.nt;
+    float* yb = y + (int64_t)b * g.nobs * g.nt;
+    hipError_t e = launch_rfft_rows(sb, 1, g.nsub, g.nsp, Sh, 0, 1, g.nsp, g, 1.0f, st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
+    int nparts;
+    e = mark(p->ev_begin, st);
+    if (fused) {
+      if (e == hipSuccess) e = launch_fused_forward(Gh, Fh, Sh, part, nwg, p->tune.fused_rows, g, st);
+      if (e == hipSuccess) e = mark(p->ev_end, st);
+      nparts = nwg;
+    } else {
+      if (e == hipSuccess) e = launch_forward_rows(Gh, Sh, Vh, nwg, g, st);
+      if (e == hipSuccess) e = mark(p->ev_end, st);
+      if (e == hipSuccess) e = launch_rows_acoustic(Fh, Vh, part, p->tune.adj_slots, p->tune.adj_splits, g, st);
+      nparts = p->tune.adj_splits;
+    }
+    if (e != hipSuccess) return hip_fail(p, e, "forward: contraction");
+    e = launch_reduce_partials(part, nparts, (int64_t)g.M * g.nop4, g.M, g.nop, g.nobs, yh, st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: partial sum");
+    e = launch_irfft_rows(yh, g.nobs, g.M, 1, yb, g.nt, g, inv_l, st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: output transform");
+  }
+  return S2W_OK;
+}
+
+s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* stream) {
+  s2w_status cs = check_call(p, r, B, gs, "adjoint");
+  if (cs != S2W_OK || B == 0) return cs;
+  const Geometry& g = p->geo;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(p, S2W_EHIP, "adjoint: cannot select device %d", p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const float2* Gh = (const float2*)(p->op + p->lay.gh);
+  const float2* Fh = (const float2*)(p->op + p->lay.fh);
+  float2* Rh = (float2*)(p->ws + p->lay.rh);
+  float2* Wp = (float2*)(p->ws + p->lay.wp);
+  float2* part = (float2*)(p->ws + p->lay.part2);
+  float2* gsh = (float2*)(p->ws + p->lay.gsh);
+  const int nwg = p->ncu * p->tune.fused_wg_per_cu;
+  const float inv_l = 1.0f / (float)g.L;
+  for (int b = 0; b < B; ++b) {
+    const float* rb = r + (int64_t)b * g.nobs * g.nt;
+    float* gb = gs + (int64_t)b * g.nsub * g.nt;
+    hipError_t e = launch_rfft_rows(rb, 1, g.nobs, g.nop, Rh, 0, 1, g.nop, g, 1.0f, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
+    e = launch_adjoint_rows(Fh, Rh, Wp, nwg, p->tune.fused_rows, g, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic stage");
+    e = mark(p->ev_begin, st);
+    if (e == hipSuccess) e = launch_adjoint_elastic(Gh, Wp, part, p->tune.adj_slots, p->tune.adj_splits, g, st);
+    if (e == hipSuccess) e = mark(p->ev_end, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: elastic stage");
+    e = launch_reduce_partials(part, p->tune.adj_splits, (int64_t)g.M * g.nsp4, g.M, g.nsp, g.nsub, gsh, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: partial sum");
+    e = launch_irfft_rows(gsh, g.nsub, g.M, 1, gb, g.nt, g, inv_l, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: output transform");
+  }
+  return S2W_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,198 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C-ABI.
+
+Tolerance: rel-L2 <= 1e-5 per rupture for the float32 path (the bound the
+method is held to); the FFT chain's own rounding is ~1e-6 at these sizes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import log_case, make_operator, to_dev
+from paper_2608_21763_amd import S2WError, S2WOperator
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _skip_without_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    _skip_without_gpu()
+
+
+def _oracle_ops(cfg):
+    return synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+def test_impulse_operators_give_the_difference(diff):
+    # one subfault, one grid point, one observer, G = F = unit impulse at lag 0:
+    # the map reduces to D_t (backward difference / dt) or the identity
+    nt, dt = 256, 0.5
+    log_case("impulse", diff=diff, nt=nt)
+    op = S2WOperator(1, 1, 1, nt, max_batch=4, dt=dt, diff=diff)
+    G = torch.zeros((1, 1, nt), device="cuda:0"); G[0, 0, 0] = 1.0
+    F = torch.zeros((1, 1, nt), device="cuda:0"); F[0, 0, 0] = 1.0
+    keep = op.set_operators(G, F, 0)
+    s = np.random.default_rng(1).standard_normal((4, 1, nt))
+    y = op.forward(to_dev(s)).cpu().numpy().astype(np.float64)
+    del keep
+    expect = (s - np.concatenate([np.zeros((4, 1, 1)), s[:, :, :-1]], axis=2)) / dt if diff else s
+    assert np.max(np.abs(y - expect)) <= 1e-5 * np.max(np.abs(expect))
+
+
+@pytest.mark.parametrize("diff,dt", [(1, 0.5), (0, 1.0), (1, 1.0)])
+def test_dense_iid_small(diff, dt):
+    # iid operators at every lag: late-time content wraps if the mid-chain truncation is missing
+    cfg = synth.workload("small_dense")
+    log_case("dense_small", diff=diff, dt=dt)
+    op = make_operator(cfg, max_batch=3, diff=diff, dt=dt)
+    s = synth.gen_slip_batch(cfg, 0, 3)
+    y = op.forward(to_dev(s)).cpu().numpy()
+    G, F = _oracle_ops(cfg)
+    yr = oracle.forward(G, F, s, dt=dt, diff=diff)
+    errs = oracle.rel_l2_per_rupture(y, yr)
+    print("rel-L2", errs)
+    assert errs.max() <= TOL
+
+
+def test_small_physical():
+    cfg = synth.workload("small")
+    log_case("small_physical")
+    op = make_operator(cfg, max_batch=2)
+    s = synth.gen_slip_batch(cfg, 0, 2)
+    y = op.forward(to_dev(s)).cpu().numpy()
+    G, F = _oracle_ops(cfg)
+    errs = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s))
+    print("rel-L2", errs)
+    assert errs.max() <= TOL
+
+
+RAGGED = [
+    # nsub, ngrid, nobs, nt
+    (7, 37, 3, 20),
+    (1, 1, 1, 1),
+    (129, 300, 5, 64),
+    (33, 45, 66, 33),
+    (5, 50, 200, 256),     # accumulator too large for the fused kernel: unfused path
+    (300, 70, 2, 100),
+    (1024, 20, 64, 256),   # largest subfault count
+    (16, 9, 4, 512),       # longest series (L = 1024)
+]
+
+
+@pytest.mark.parametrize("shape", RAGGED, ids=[f"{a}x{b}x{c}x{d}" for a, b, c, d in RAGGED])
+def test_ragged_shapes_forward_adjoint(shape):
+    nsub, ngrid, nobs, nt = shape
+    cfg = synth.SynthConfig(nsub=nsub, ngrid=ngrid, nobs=nobs, nt=nt, seed=77, slip_seed=78, op_kind="dense",
+                            slip_mode="dense")
+    log_case("ragged", shape=shape)
+    dt = 0.75
+    op = make_operator(cfg, max_batch=2, dt=dt, chunk_rows=17)
+    s = synth.gen_slip_batch(cfg, 0, 2)
+    r = synth.normals(5, "r", 0, (2, nobs, nt))
+    y = op.forward(to_dev(s)).cpu().numpy()
+    gs = op.adjoint(to_dev(r)).cpu().numpy()
+    G, F = _oracle_ops(cfg)
+    ey = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s, dt=dt))
+    eg = oracle.rel_l2_per_rupture(gs, oracle.adjoint(G, F, r, dt=dt))
+    print("forward", ey, "adjoint", eg)
+    assert ey.max() <= TOL and eg.max() <= TOL
+
+
+@pytest.mark.parametrize("diff", [0, 1])
+def test_adjoint_and_dot_product(diff):
+    cfg = synth.workload("small_dense")
+    log_case("adjoint_dot", diff=diff)
+    dt = 0.5
+    op = make_operator(cfg, max_batch=4, diff=diff, dt=dt)
+    x = synth.normals(11, "x", 0, (4, cfg.nsub, cfg.nt))
+    w = synth.normals(11, "y", 0, (4, cfg.nobs, cfg.nt))
+    Ax = op.forward(to_dev(x)).cpu().numpy().astype(np.float64)
+    ATw = op.adjoint(to_dev(w)).cpu().numpy().astype(np.float64)
+    G, F = _oracle_ops(cfg)
+    assert oracle.rel_l2_per_rupture(ATw, oracle.adjoint(G, F, w, dt=dt, diff=diff)).max() <= TOL
+    for b in range(4):
+        lhs, rhs = np.sum(Ax[b] * w[b]), np.sum(x[b] * ATw[b])
+        assert abs(lhs - rhs) <= 1e-6 * np.linalg.norm(Ax[b]) * np.linalg.norm(w[b])
+
+
+def test_autograd_gradient_matches_adjoint_and_fd():
+    from paper_2608_21763_amd import source_to_waveform
+    cfg = synth.workload("small")
+    log_case("autograd")
+    op = make_operator(cfg, max_batch=2)
+    s_np = synth.gen_slip_batch(cfg, 0, 2)
+    G, F = _oracle_ops(cfg)
+    y_obs = oracle.forward(G, F, synth.gen_slip_batch(cfg, 50, 2))
+    s = to_dev(s_np).requires_grad_(True)
+    y = source_to_waveform(s, op)
+    loss = 0.5 * ((y.double() - torch.tensor(y_obs, device="cuda:0")) ** 2).sum()
+    loss.backward()
+    g = s.grad.cpu().numpy().astype(np.float64)
+    g_ref = oracle.adjoint(G, F, oracle.forward(G, F, s_np) - y_obs)
+    assert oracle.rel_l2(g, g_ref) <= TOL
+    # central differences of the exactly quadratic loss, FP64 loss on the oracle's forward of GPU results
+    rng = np.random.default_rng(4)
+    h = 0.5
+    gmax = np.abs(g).max()
+    for _ in range(10):
+        b, j, n = rng.integers(2), rng.integers(cfg.nsub), rng.integers(cfg.nt)
+        sp = s_np.copy(); sp[b, j, n] += h
+        sm = s_np.copy(); sm[b, j, n] -= h
+        lp = 0.5 * np.sum((op.forward(to_dev(sp)).cpu().numpy().astype(np.float64) - y_obs) ** 2)
+        lm = 0.5 * np.sum((op.forward(to_dev(sm)).cpu().numpy().astype(np.float64) - y_obs) ** 2)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[b, j, n]) <= 1e-3 * abs(g[b, j, n]) + 1e-6 * gmax, (b, j, n, fd, g[b, j, n])
+
+
+def test_determinism_and_empty_batch():
+    cfg = synth.workload("small_dense")
+    log_case("determinism")
+    op = make_operator(cfg, max_batch=2)
+    s = to_dev(synth.gen_slip_batch(cfg, 0, 2))
+    y1 = op.forward(s).clone()
+    y2 = op.forward(s).clone()
+    assert torch.equal(y1, y2)
+    empty = torch.empty((0, cfg.nsub, cfg.nt), device="cuda:0")
+    assert op.forward(empty).shape == (0, cfg.nobs, cfg.nt)
+
+
+def test_error_paths():
+    cfg = synth.workload("small")
+    log_case("errors")
+    op = S2WOperator(cfg.nsub, cfg.ngrid, cfg.nobs, cfg.nt, max_batch=2)
+    s = to_dev(synth.gen_slip_batch(cfg, 0, 2))
+    with pytest.raises(S2WError) as e:
+        op.forward(s)               # operators not set
+    assert e.value.code == "S2W_ESTATE"
+    G = torch.zeros((cfg.ngrid, cfg.nsub, cfg.nt), device="cuda:0")
+    F = torch.zeros((cfg.ngrid, cfg.nobs, cfg.nt), device="cuda:0")
+    op.set_operators(G[:100], F[:100], 0)
+    with pytest.raises(S2WError) as e:
+        op.forward(s)               # rows 100.. missing
+    assert e.value.code == "S2W_ESTATE"
+    with pytest.raises(S2WError) as e:
+        op.set_operators(G[:10], F[:10], cfg.ngrid - 5)   # out of range
+    assert e.value.code == "S2W_EINVAL"
+    op.set_operators(G, F, 0)
+    torch.cuda.synchronize()
+    with pytest.raises(S2WError) as e:
+        op.forward(to_dev(synth.gen_slip_batch(cfg, 0, 3)))   # B > max_batch
+    assert e.value.code == "S2W_EINVAL"
+    plan = op.plan
+    buf = torch.empty(4096, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(S2WError) as e:
+        plan.forward(buf.data_ptr() + 4, 1, buf.data_ptr() + 1024, 0)   # misaligned
+    assert e.value.code == "S2W_EINVAL"
+    op_bytes, ws_bytes = plan.query_sizes()
+    with pytest.raises(S2WError) as e:
+        plan.bind(op.op_store.data_ptr(), op_bytes - 1, op.workspace.data_ptr(), ws_bytes)
+    assert e.value.code == "S2W_ENOMEM"

@@ -18,24 +18,26 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "s2w_oracle.c")
 
 MUTANTS = {
-    "eq1_dropped_last_lag": ("for (int64_t k = 0; k <= n; k++) acc += gk[k] * sj[n - k];",
-                             "for (int64_t k = 0; k < n; k++) acc += gk[k] * sj[n - k];"),
+    "eq1_dropped_last_lag": ("for (int64_t n = k; n < nt; n++) m[n] += gv * sj[n - k];",
+                             "for (int64_t n = k + 1; n < nt; n++) m[n] += gv * sj[n - k];"),
+    "eq1_shifted_lag": ("for (int64_t n = k; n < nt; n++) m[n] += gv * sj[n - k];",
+                        "for (int64_t n = k; n + 1 < nt; n++) m[n + 1] += gv * sj[n - k];"),
     "dt_sign": ("vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) / dt;",
                 "vg[n] = (m[n] + (n > 0 ? m[n - 1] : 0.0)) / dt;"),
     "dt_scale": ("vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) / dt;",
                  "vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) * dt;"),
     "dt_first_sample": ("vg[n] = (m[n] - (n > 0 ? m[n - 1] : 0.0)) / dt;",
                         "vg[n] = (m[n] - (n > 0 ? m[n - 1] : m[0])) / dt;"),
-    "eq2_wrong_index": ("for (int64_t k = 0; k <= n; k++) acc += fk[k] * vg[n - k];",
-                        "for (int64_t k = 0; k <= n; k++) acc += fk[n - k] * vg[n - k];"),
+    "eq2_wrong_index": ("for (int64_t n = k; n < nt; n++) yo[n] += fv * vg[n - k];",
+                        "for (int64_t n = k; n < nt; n++) yo[n] += fv * vg[n];"),
     "eq2_transposed_F": ("const double* fk = F + (g * nobs + o) * nt;\n        const double* vg",
                          "const double* fk = F + (o * nrows + g) * nt;\n        const double* vg"),
-    "adj_dropped_lag": ("for (int64_t k = 0; k + n < nt; k++) acc += fk[k] * ro[n + k];",
-                        "for (int64_t k = 0; k + n < nt - 1; k++) acc += fk[k] * ro[n + k];"),
+    "adj_dropped_lag": ("for (int64_t n = 0; n + k < nt; n++) w[n] += fv * ro[n + k];",
+                        "for (int64_t n = 0; n + k < nt - 1; n++) w[n] += fv * ro[n + k];"),
     "adj_dt_direction": ("wg[n] = (w[n] - (n + 1 < nt ? w[n + 1] : 0.0)) / dt;",
                          "wg[n] = (w[n] - (n > 0 ? w[n - 1] : 0.0)) / dt;"),
-    "adj_convolution_not_correlation": ("for (int64_t k = 0; k + n < nt; k++) acc += gk[k] * wg[n + k];",
-                                        "for (int64_t k = 0; k <= n; k++) acc += gk[k] * wg[n - k];"),
+    "adj_convolution_not_correlation": ("for (int64_t n = 0; n + k < nt; n++) gj[n] += gv * wg[n + k];",
+                                        "for (int64_t n = k; n < nt; n++) gj[n] += gv * wg[n - k];"),
 }
 
 
