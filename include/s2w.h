@@ -125,7 +125,7 @@ s2w_status s2w_adjoint(s2w_plan* plan, const float* r, int32_t B, float* gs, voi
 typedef struct s2w_tuning {
   int32_t fused_wg_per_cu;   /* single-rupture fused kernel: workgroups per compute unit (1..4) */
   int32_t fused_rows;        /* single-rupture fused kernel: grid rows per tile (4 or 8) */
-  int32_t adj_slots;         /* single-rupture adjoint: frequency bins per workgroup (4 or 8) */
+  int32_t adj_cols;          /* grid-row contractions (adjoint elastic stage): columns per thread (8 or 16) */
   int32_t adj_splits;        /* single-rupture adjoint: grid splits of the transposed elastic stage */
   int32_t batch_path_min_b;  /* smallest B that takes the batched matrix-core path */
 } s2w_tuning;

@@ -32,7 +32,7 @@ class Desc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_slots", ctypes.c_int32),
+    _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_cols", ctypes.c_int32),
                 ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32)]
 
 

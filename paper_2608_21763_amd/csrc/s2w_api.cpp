@@ -119,11 +119,11 @@ Layout make_layout(const s2w_desc& d, const Geometry& g, int ncu) {
   L.sh = off;
   off = round_up(off + (uint64_t)g.M * g.nsp * c8, kAlign);
   L.part = off;
-  const uint64_t part_fwd = (uint64_t)nwg_max * g.M * g.nop * c8;
+  const uint64_t part_fwd = (uint64_t)nwg_max * g.M * g.nop * c8;  // [nwg][nop][M]
   const uint64_t part_split = (uint64_t)kMaxSplits * g.M * std::max(g.nsp, g.nop) * c8;
   off = round_up(off + std::max(part_fwd, part_split), kAlign);
   L.yh = off;
-  off = round_up(off + (uint64_t)std::max(g.nobs, g.nsub) * g.M * c8, kAlign);
+  off = round_up(off + (uint64_t)std::max(g.nop, g.nsp) * g.M * c8, kAlign);
   L.rh = off;
   off = round_up(off + (uint64_t)g.M * g.nop * c8, kAlign);
   L.wp = off;
@@ -192,7 +192,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->lay = make_layout(d, g, ncu);
   p->tune.fused_wg_per_cu = 1;
   p->tune.fused_rows = 8;
-  p->tune.adj_slots = 8;
+  p->tune.adj_cols = 16;
   p->tune.adj_splits = 16;
   p->tune.batch_path_min_b = 1 << 30;
   p->row_set.assign((size_t)d.ngrid, 0);
@@ -271,9 +271,9 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     if (t->fused_rows != 4 && t->fused_rows != 8) return fail(p, S2W_EINVAL, "tuning: fused_rows must be 4 or 8");
     n.fused_rows = t->fused_rows;
   }
-  if (t->adj_slots) {
-    if (t->adj_slots != 4 && t->adj_slots != 8) return fail(p, S2W_EINVAL, "tuning: adj_slots must be 4 or 8");
-    n.adj_slots = t->adj_slots;
+  if (t->adj_cols) {
+    if (t->adj_cols != 8 && t->adj_cols != 16) return fail(p, S2W_EINVAL, "tuning: adj_cols must be 8 or 16");
+    n.adj_cols = t->adj_cols;
   }
   if (t->adj_splits) {
     if (t->adj_splits < 1 || t->adj_splits > kMaxSplits) return fail(p, S2W_EINVAL, "tuning: adj_splits");
@@ -306,10 +306,11 @@ s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_c
   hipStream_t st = (hipStream_t)stream;
   float2* Gh = (float2*)(p->op + p->lay.gh);
   float2* Fh = (float2*)(p->op + p->lay.fh);
-  hipError_t e = launch_rfft_rows(G_chunk, nrows, g.nsub, g.nsp, Gh + row0 * g.M * g.nsp, (int64_t)g.M * g.nsp, 1,
-                                  g.nsp, g, 1.0f, st);
+  // spectra of row (g, column c) land at [g][c][0..M)
+  hipError_t e = launch_rfft_rows(G_chunk, nrows, g.nsub, g.nsp, Gh + row0 * g.M * g.nsp, (int64_t)g.M * g.nsp, g.M,
+                                  1, g, 1.0f, st);
   if (e != hipSuccess) return hip_fail(p, e, "set_operators: elastic transform");
-  e = launch_rfft_rows(F_chunk, nrows, g.nobs, g.nop, Fh + row0 * g.M * g.nop, (int64_t)g.M * g.nop, 1, g.nop, g,
+  e = launch_rfft_rows(F_chunk, nrows, g.nobs, g.nop, Fh + row0 * g.M * g.nop, (int64_t)g.M * g.nop, g.M, 1, g,
                        1.0f, st);
   if (e != hipSuccess) return hip_fail(p, e, "set_operators: acoustic transform");
   for (int64_t r = row0; r < row0 + nrows; ++r) {
@@ -347,13 +348,13 @@ s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* s
   float2* part = (float2*)(p->ws + p->lay.part);
   float2* yh = (float2*)(p->ws + p->lay.yh);
   float2* Vh = (float2*)(p->ws + p->lay.wp);
-  const bool fused = (int64_t)g.M * g.nop4 <= FUSED_MAX_ITEMS;
+  const bool fused = fused_forward_opt(g) <= 32;
   const int nwg = p->ncu * p->tune.fused_wg_per_cu;
   const float inv_l = 1.0f / (float)g.L;
   for (int b = 0; b < B; ++b) {
     const float* sb = s + (int64_t)b * g.nsub * g.nt;
     float* yb = y + (int64_t)b * g.nobs * g.nt;
-    hipError_t e = launch_rfft_rows(sb, 1, g.nsub, g.nsp, Sh, 0, 1, g.nsp, g, 1.0f, st);
+    hipError_t e = launch_rfft_rows(sb, 1, g.nsub, g.nsp, Sh, 0, g.M, 1, g, 1.0f, st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
     int nparts;
     e = mark(p->ev_begin, st);
@@ -364,11 +365,11 @@ s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* s
     } else {
       if (e == hipSuccess) e = launch_forward_rows(Gh, Sh, Vh, nwg, g, st);
       if (e == hipSuccess) e = mark(p->ev_end, st);
-      if (e == hipSuccess) e = launch_rows_acoustic(Fh, Vh, part, p->tune.adj_slots, p->tune.adj_splits, g, st);
+      if (e == hipSuccess) e = launch_rows_acoustic(Fh, Vh, part, p->tune.adj_cols, p->tune.adj_splits, g, st);
       nparts = p->tune.adj_splits;
     }
     if (e != hipSuccess) return hip_fail(p, e, "forward: contraction");
-    e = launch_reduce_partials(part, nparts, (int64_t)g.M * g.nop4, g.M, g.nop, g.nobs, yh, st);
+    e = launch_sum_parts(part, nparts, (int64_t)g.nop * g.M, yh, st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: partial sum");
     e = launch_irfft_rows(yh, g.nobs, g.M, 1, yb, g.nt, g, inv_l, st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: output transform");
@@ -394,15 +395,15 @@ s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* 
   for (int b = 0; b < B; ++b) {
     const float* rb = r + (int64_t)b * g.nobs * g.nt;
     float* gb = gs + (int64_t)b * g.nsub * g.nt;
-    hipError_t e = launch_rfft_rows(rb, 1, g.nobs, g.nop, Rh, 0, 1, g.nop, g, 1.0f, st);
+    hipError_t e = launch_rfft_rows(rb, 1, g.nobs, g.nop, Rh, 0, g.M, 1, g, 1.0f, st);
     if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
     e = launch_adjoint_rows(Fh, Rh, Wp, nwg, p->tune.fused_rows, g, st);
     if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic stage");
     e = mark(p->ev_begin, st);
-    if (e == hipSuccess) e = launch_adjoint_elastic(Gh, Wp, part, p->tune.adj_slots, p->tune.adj_splits, g, st);
+    if (e == hipSuccess) e = launch_adjoint_elastic(Gh, Wp, part, p->tune.adj_cols, p->tune.adj_splits, g, st);
     if (e == hipSuccess) e = mark(p->ev_end, st);
     if (e != hipSuccess) return hip_fail(p, e, "adjoint: elastic stage");
-    e = launch_reduce_partials(part, p->tune.adj_splits, (int64_t)g.M * g.nsp4, g.M, g.nsp, g.nsub, gsh, st);
+    e = launch_sum_parts(part, p->tune.adj_splits, (int64_t)g.nsp * g.M, gsh, st);
     if (e != hipSuccess) return hip_fail(p, e, "adjoint: partial sum");
     e = launch_irfft_rows(gsh, g.nsub, g.M, 1, gb, g.nt, g, inv_l, st);
     if (e != hipSuccess) return hip_fail(p, e, "adjoint: output transform");

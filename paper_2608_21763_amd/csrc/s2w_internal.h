@@ -33,32 +33,31 @@ hipError_t launch_irfft_rows(const float2* in, int64_t nrows, int64_t in_row, in
 
 // Single-rupture fused forward: every workgroup contracts its grid rows against the
 // source spectrum, runs the mid-chain round trip in LDS and accumulates its partial
-// observation spectra; part receives [nwg][M][nop] complex.
+// observation spectra; part receives [nwg][nop][M] complex.
 hipError_t launch_fused_forward(const float2* Gh, const float2* Fh, const float2* Sh, float2* part, int nwg,
                                 int tile_rows, const Geometry& g, hipStream_t st);
 
-// Sum the partials over workgroups in a fixed order: out[o][slot] (complex, row stride M).
-hipError_t launch_reduce_partials(const float2* part, int nparts, int64_t items, int M, int nop, int nvalid_cols,
-                                  float2* out, hipStream_t st);
+// Fixed-order sum of partial spectra: out[i] = sum_p part[p][i], i < items_c (complex values).
+hipError_t launch_sum_parts(const float2* part, int nparts, int64_t items_c, float2* out, hipStream_t st);
+
+// Observers per thread the fused forward needs (it supports up to 32).
+int fused_forward_opt(const Geometry& g);
 
 // Single-rupture adjoint, stage 1: per grid row, conj-transposed acoustic contraction,
 // mid-chain round trip with the transposed difference; Wp[g][slot] (complex).
 hipError_t launch_adjoint_rows(const float2* Fh, const float2* Rh, float2* Wp, int nwg, int tile_rows,
                                const Geometry& g, hipStream_t st);
 
-// Single-rupture adjoint, stage 2: part[split][slot][j] = sum over the split's grid rows of
-// conj(Gh[g][slot][j]) * Wp[g][slot].
-hipError_t launch_adjoint_elastic(const float2* Gh, const float2* Wp, float2* part, int slots_per_wg, int splits,
+// Single-rupture adjoint, stage 2: part[split][j][slot] = sum over the split's grid rows of
+// conj(Gh[g][j][slot]) * Wp[g][slot].
+hipError_t launch_adjoint_elastic(const float2* Gh, const float2* Wp, float2* part, int cols_per_thread, int splits,
                                   const Geometry& g, hipStream_t st);
 
 // Unfused forward: stage 1 writes the per-row mid-chain output Vh[g][l]; stage 2
 // contracts it with the acoustic store per bin, split over grid rows.
 hipError_t launch_forward_rows(const float2* Gh, const float2* Sh, float2* Vh, int nwg, const Geometry& g,
                                hipStream_t st);
-hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part, int slots_per_wg, int splits,
+hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part, int cols_per_thread, int splits,
                                 const Geometry& g, hipStream_t st);
-
-// Largest F-stage item count per thread the fused kernel supports (items = M * nop/2).
-constexpr int FUSED_MAX_ITEMS = 32 * 256;
 
 }  // namespace s2w

@@ -8,10 +8,24 @@ import os
 _hip = None
 
 
+def _loaded_hip_runtime():
+    """Path of the HIP runtime already mapped into this process (PyTorch's), if any."""
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                p = line.split()[-1]
+                if "libamdhip64.so" in os.path.basename(p):
+                    return p
+    except OSError:
+        pass
+    return None
+
+
 def _lib():
     global _hip
     if _hip is None:
-        for cand in ("/opt/rocm/lib/libamdhip64.so", ctypes.util.find_library("amdhip64") or ""):
+        for cand in (_loaded_hip_runtime() or "", "/opt/rocm/lib/libamdhip64.so",
+                     ctypes.util.find_library("amdhip64") or ""):
             if cand and os.path.exists(cand):
                 _hip = ctypes.CDLL(cand)
                 break
