@@ -306,18 +306,40 @@ hipError_t launch_fused_forward(const float2* Gh, const float2* Fh, const float2
 
 // ---------------------------------------------------------------------------------------------
 // Fixed-order sum of partial spectra: out[i] = sum_p part[p][i] for i < items (float4 units).
+// QP threads share an item: thread q sums parts p = q, q + QP, ... (eight loads in flight),
+// then the QP partial sums are added in the fixed order q = 0..QP-1.  Deterministic.
+constexpr int QP = 8;
 __global__ __launch_bounds__(256) void k_sum_parts(const v4f* __restrict__ part, int nparts, int64_t items,
                                                    v4f* __restrict__ out) {
-  const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (it >= items) return;
+  __shared__ v4f sh[256];
+  const int q = threadIdx.x % QP;
+  const int64_t it = (int64_t)blockIdx.x * (256 / QP) + threadIdx.x / QP;
   v4f s = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * items + it];
-  out[it] = s;
+  if (it < items) {
+    int p = q;
+    for (; p + 7 * QP < nparts; p += 8 * QP) {
+      v4f a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = part[(int64_t)(p + u * QP) * items + it];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += a[u];
+    }
+    for (; p < nparts; p += QP) s += part[(int64_t)p * items + it];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (q == 0 && it < items) {
+    v4f t = sh[threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < QP; ++k) t += sh[threadIdx.x + k];
+    out[it] = t;
+  }
 }
 
 hipError_t launch_sum_parts(const float2* part, int nparts, int64_t items_c, float2* out, hipStream_t st) {
   const int64_t items = items_c / 2;
-  const int64_t nblk = (items + 255) / 256;
+  const int64_t per_blk = 256 / QP;
+  const int64_t nblk = (items + per_blk - 1) / per_blk;
   hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)nblk), dim3(256), 0, st, (const v4f*)part, nparts, items,
                      (v4f*)out);
   return hipGetLastError();
