@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ruptures/s on 963×37,760×64×256 share, batched bf16 vs plain fp32, stated rel-L2"
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK = {"bf16": 2500.0, "f16": 2500.0}  # dense matrix-core TFLOP/s
 
 
 def log(*a):
@@ -90,6 +91,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
     ap.add_argument("--paths", default="fp32,half")
+    ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngrid", type=int, default=None, help="override the share size (testing only)")
     args = ap.parse_args()
@@ -112,67 +114,119 @@ def main():
     dev = torch.device("cuda:0")
     result = {}
     src_hash = kernel_source_hash()
+    cores = len(os.sched_getaffinity(0))
+    omp = int(os.environ.get("OMP_NUM_THREADS", cores))
 
     # ---------------- fp32 single-rupture path ----------------
-    op = S2WOperator(cfg.nsub, cfg.ngrid, cfg.nobs, cfg.nt, max_batch=1, dt=cfg.dt, device=0)
-    t = time.perf_counter()
-    op.load_operators(*host_generators(cfg), chunk_rows=1024)
-    setup_s = time.perf_counter() - t
-    log(f"fp32 operators set in {setup_s:.1f} s")
-    nrup = max(args.steps, args.warmup, 1)
-    s_host = synth.gen_slip_batch(cfg, 0, nrup)
-    s_dev = torch.tensor(s_host, device=dev).reshape(nrup, 1, cfg.nsub, cfg.nt)
-    total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, 1)
-    ms_step = total_ms / args.steps
-    abytes = algorithmic_bytes(cfg.nsub, cfg.nobs, cfg.ngrid, cfg.nt, 4)
-    kmean = float(np.mean(kern_ms))
-    fp32 = {"ruptures_per_s": 1000.0 / ms_step, "ms_per_step": ms_step, "B": 1, "kernel": "k_fused_forward",
-            "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)), "algorithmic_bytes": abytes,
-            "achieved_GBs": abytes / (kmean * 1e6), "setup_s": setup_s}
-    log(f"fp32: {ms_step:.3f} ms/rupture, kernel {kmean:.3f} ms, {fp32['achieved_GBs']:.0f} GB/s")
-    y0 = op.forward(s_dev[0, 0]).cpu().numpy().astype(np.float64)
-    result["fp32"] = fp32
-
-    # ---------------- CPU baseline: the FP64 oracle on one rupture ----------------
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
+    if "fp32" in paths:
+        op = S2WOperator(cfg.nsub, cfg.ngrid, cfg.nobs, cfg.nt, max_batch=1, dt=cfg.dt, device=0)
         t = time.perf_counter()
-        y_ref = oracle.forward_synth(cfg, s_host[0])
-        cpu_s = time.perf_counter() - t
-        cores = len(os.sched_getaffinity(0))
-        omp = int(os.environ.get("OMP_NUM_THREADS", cores))
-        fp32["rel_l2"] = oracle.rel_l2(y0, y_ref)
-        cpu = {"value": 1.0 / cpu_s, "unit": "ruptures/s", "cores": min(cores, omp), "kind": "oracle",
-               "sample": f"1 rupture (index 0) over the whole {cfg.ngrid}-row share, FP64 direct time-domain, "
-                         f"operators regenerated in chunks, {cpu_s:.1f} s"}
-        log(f"oracle: {cpu_s:.1f} s/rupture, fp32 rel-L2 {fp32['rel_l2']:.2e}")
-    del op
-    torch.cuda.empty_cache()
+        op.load_operators(*host_generators(cfg), chunk_rows=1024)
+        setup_s = time.perf_counter() - t
+        log(f"fp32 operators set in {setup_s:.1f} s")
+        nrup = max(args.steps, args.warmup, 1)
+        s_host = synth.gen_slip_batch(cfg, 0, nrup)
+        s_dev = torch.tensor(s_host, device=dev).reshape(nrup, 1, cfg.nsub, cfg.nt)
+        total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, 1)
+        ms_step = total_ms / args.steps
+        abytes = algorithmic_bytes(cfg.nsub, cfg.nobs, cfg.ngrid, cfg.nt, 4)
+        kmean = float(np.mean(kern_ms))
+        fp32 = {"ruptures_per_s": 1000.0 / ms_step, "ms_per_step": ms_step, "B": 1, "kernel": "k_fused_forward",
+                "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)), "algorithmic_bytes": abytes,
+                "achieved_GBs": abytes / (kmean * 1e6), "hbm_frac": abytes / (kmean * 1e6) / HBM_PEAK_GBS,
+                "setup_s": setup_s}
+        log(f"fp32: {ms_step:.3f} ms/rupture, kernel {kmean:.3f} ms, {fp32['achieved_GBs']:.0f} GB/s")
+        y0 = op.forward(s_dev[0, 0]).cpu().numpy().astype(np.float64)
+        result["fp32"] = fp32
+        if not args.no_cpu_baseline:
+            import oracle
+            t = time.perf_counter()
+            y_ref = oracle.forward_synth(cfg, s_host[0])
+            cpu_s = time.perf_counter() - t
+            fp32["rel_l2"] = oracle.rel_l2(y0, y_ref)
+            result["cpu_baseline"] = {
+                "value": 1.0 / cpu_s, "unit": "ruptures/s", "cores": min(cores, omp), "kind": "oracle",
+                "sample": f"1 rupture (index 0) over the whole {cfg.ngrid}-row share, FP64 direct time-domain "
+                          f"convolution, operators regenerated in chunks, {cpu_s:.1f} s"}
+            log(f"oracle: {cpu_s:.1f} s/rupture, fp32 rel-L2 {fp32['rel_l2']:.2e}")
+        del op
+        torch.cuda.empty_cache()
 
-    headline = fp32
+    # ---------------- batched half-precision path ----------------
+    if "half" in paths:
+        B = args.batch
+        gdt, fdt = args.half_dtype.split("/") if "/" in args.half_dtype else (args.half_dtype, args.half_dtype)
+        bcfg = synth.workload("cascadia_batch")
+        if args.ngrid:
+            bcfg = bcfg.replace(ngrid=args.ngrid)
+        op = S2WOperator(bcfg.nsub, bcfg.ngrid, bcfg.nobs, bcfg.nt, max_batch=B, dt=bcfg.dt, device=0,
+                         g_dtype=gdt, f_dtype=fdt)
+        t = time.perf_counter()
+        op.load_operators(*host_generators(bcfg), chunk_rows=1024)
+        setup_s = time.perf_counter() - t
+        log(f"{gdt}/{fdt} operators set in {setup_s:.1f} s")
+        nb = 2
+        s_host = synth.gen_slip_batch(bcfg, 0, nb * B)
+        s_dev = torch.tensor(s_host, device=dev).reshape(nb, B, bcfg.nsub, bcfg.nt)
+        total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, B)
+        ms_step = total_ms / args.steps
+        kmean = float(np.mean(kern_ms))
+        flops_g = 8.0 * bcfg.ngrid * bcfg.nsub * (bcfg.nt) * B      # complex MACs of the elastic stage per call
+        hbytes = algorithmic_bytes(bcfg.nsub, bcfg.nobs, bcfg.ngrid, bcfg.nt, 2)
+        half = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{fdt}",
+                "kernel": "k_gemm_g", "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)),
+                "algorithmic_flops": flops_g, "achieved_TFLOPs": flops_g / (kmean * 1e9),
+                "issued_TFLOPs": 2.0 * flops_g / (kmean * 1e9), "algorithmic_bytes": hbytes, "setup_s": setup_s}
+        log(f"half {gdt}/{fdt} B={B}: {ms_step:.3f} ms/call, {half['ruptures_per_s']:.0f} ruptures/s, "
+            f"elastic GEMM {kmean:.3f} ms = {half['achieved_TFLOPs']:.0f} TFLOP/s algorithmic")
+        if not args.no_cpu_baseline:
+            import oracle
+            y = op.forward(s_dev[0]).cpu().numpy().astype(np.float64)
+            act = [int(np.count_nonzero(np.any(s_host[b] != 0, axis=1))) for b in range(B)]
+            pick = sorted({int(np.argmin(act)), int(np.argmax(act)), 0, 1})
+            y_ref = oracle.forward_synth(bcfg, s_host[pick])
+            errs = [oracle.rel_l2(y[b], y_ref[i]) for i, b in enumerate(pick)]
+            half["rel_l2_sampled"] = {str(b): e for b, e in zip(pick, errs)}
+            half["rel_l2"] = max(errs)
+            log(f"half rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
+        result["half"] = half
+        del op
+        torch.cuda.empty_cache()
+
+    fp32 = result.get("fp32")
+    half = result.get("half")
+    head = half or fp32
+    if half:
+        roof = {"bound": "mfma", "achieved": half["achieved_TFLOPs"], "peak": MFMA_PEAK[half["dtypes"].split("/")[0]],
+                "unit": "TFLOP/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = traffic_for("k_gemm_g", src_hash, 1)
+        workload = (f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, batched {half['dtypes']} "
+                    f"B={half['B']} (vs fp32 single rupture)")
+    else:
+        roof = {"bound": "hbm", "achieved": fp32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": fp32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic_for("k_fused_forward", src_hash, 1)}
+        workload = f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, fp32 single rupture"
     out = {
         "metric": METRIC,
-        "value": headline["ruptures_per_s"],
+        "value": head["ruptures_per_s"],
         "unit": "ruptures/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": headline["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": (half["dtypes"].split("/")[0] if half else "f32"),
         "data": "synthetic",
-        "config": {"workload": f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, fp32 single rupture",
-                   "nsub": cfg.nsub, "ngrid": cfg.ngrid, "nobs": cfg.nobs, "nt": cfg.nt, "batch": 1,
-                   "parallelism": "single GPU share"},
-        "roofline": {"bound": "hbm", "achieved": fp32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fp32["achieved_GBs"] / HBM_PEAK_GBS,
-                     "traffic": traffic_for("k_fused_forward", src_hash, 1)},
-        "cpu_baseline": cpu,
-        "rel_l2": fp32.get("rel_l2"),
-        "paths": result,
+        "config": {"workload": workload, "nsub": cfg.nsub, "ngrid": cfg.ngrid, "nobs": cfg.nobs, "nt": cfg.nt,
+                   "batch": head["B"], "parallelism": "single GPU share"},
+        "roofline": roof,
+        "cpu_baseline": result.get("cpu_baseline"),
+        "rel_l2": head.get("rel_l2"),
+        "speedup_vs_fp32": (half["ruptures_per_s"] / fp32["ruptures_per_s"]) if (half and fp32) else None,
+        "paths": {k: v for k, v in result.items() if k != "cpu_baseline"},
         "source_hash": src_hash,
     }
     print(json.dumps(out))

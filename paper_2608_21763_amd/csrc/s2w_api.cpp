@@ -35,10 +35,27 @@ inline int ilog2(int v) {
 
 // Offsets of the regions carved out of the bound memory.
 struct Layout {
-  // operator store
-  uint64_t gh, fh, op_total;
-  // workspace
-  uint64_t sh, part, yh, rh, wp, part2, gsh, ws_total;
+  // operator store (float32 path)
+  uint64_t gh, fh;
+  // operator store (half-precision path)
+  uint64_t gq, sg, fq, sf;
+  uint64_t op_total;
+  // workspace (float32 single-rupture path)
+  uint64_t sh, part, yh, rh, wp, part2, gsh;
+  // workspace (batched half-precision path)
+  uint64_t staging, S, sig_up, sig_down, bop, U, tau_up, tau_down, part_f, yhb;
+  uint64_t ws_total;
+};
+
+// Extra geometry of the batched half-precision path.
+struct HalfGeo {
+  bool on = false;
+  int ht_g = 1, ht_f = 1;     // 1 = bf16, 2 = f16
+  int hterms_g = 2, hterms_f = 2;
+  int nsq, noq, ngq, nks;     // padded subfaults (x16), observers (16 * 2^k), grid rows (x16); K steps
+  int bp;                     // max_batch padded to a multiple of 8
+  int splits_max;
+  int rs;                     // setup rows per staging pass
 };
 
 }  // namespace
@@ -48,12 +65,14 @@ struct s2w_plan {
   int device;
   int ncu;
   Geometry geo;
+  HalfGeo hg;
   Layout lay;
   s2w_tuning tune;
   char* op = nullptr;
   char* ws = nullptr;
   uint64_t op_bytes = 0, ws_bytes = 0;
   std::vector<uint8_t> row_set;  // one flag per grid row set since the last bind
+  bool pad_zeroed = false;       // half path: padding columns of the acoustic store cleared
   int64_t rows_missing = 0;
   std::string err;
   hipEvent_t ev_begin = nullptr, ev_end = nullptr;
@@ -104,32 +123,68 @@ struct DeviceGuard {
   }
 };
 
-Layout make_layout(const s2w_desc& d, const Geometry& g, int ncu) {
+Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, int ncu) {
   Layout L{};
   const uint64_t c8 = sizeof(float2);
   uint64_t off = 0;
-  L.gh = off;
-  off = round_up(off + (uint64_t)g.ngrid * g.M * g.nsp * c8, kAlign);
-  L.fh = off;
-  off = round_up(off + (uint64_t)g.ngrid * g.M * g.nop * c8, kAlign);
+  if (!h.on) {
+    L.gh = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * g.nsp * c8, kAlign);
+    L.fh = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * g.nop * c8, kAlign);
+  } else {
+    L.gq = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * h.nsq * 4, kAlign);
+    L.sg = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * 4, kAlign);
+    L.fq = off;
+    off = round_up(off + (uint64_t)g.M * h.noq * h.ngq * 4, kAlign);
+    L.sf = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * 4, kAlign);
+  }
   L.op_total = off;
 
   off = 0;
-  const int nwg_max = ncu * kMaxWgPerCu;
-  L.sh = off;
-  off = round_up(off + (uint64_t)g.M * g.nsp * c8, kAlign);
-  L.part = off;
-  const uint64_t part_fwd = (uint64_t)nwg_max * g.M * g.nop * c8;  // [nwg][nop][M]
-  const uint64_t part_split = (uint64_t)kMaxSplits * g.M * std::max(g.nsp, g.nop) * c8;
-  off = round_up(off + std::max(part_fwd, part_split), kAlign);
-  L.yh = off;
-  off = round_up(off + (uint64_t)std::max(g.nop, g.nsp) * g.M * c8, kAlign);
-  L.rh = off;
-  off = round_up(off + (uint64_t)g.M * g.nop * c8, kAlign);
-  L.wp = off;
-  off = round_up(off + (uint64_t)g.ngrid * g.M * c8, kAlign);
-  L.part2 = L.part;  // the adjoint reuses the partial region
-  L.gsh = L.yh;
+  if (!h.on) {
+    const int nwg_max = ncu * kMaxWgPerCu;
+    L.sh = off;
+    off = round_up(off + (uint64_t)g.M * g.nsp * c8, kAlign);
+    L.part = off;
+    const uint64_t part_fwd = (uint64_t)nwg_max * g.M * g.nop * c8;  // [nwg][nop][M]
+    const uint64_t part_split = (uint64_t)kMaxSplits * g.M * std::max(g.nsp, g.nop) * c8;
+    off = round_up(off + std::max(part_fwd, part_split), kAlign);
+    L.yh = off;
+    off = round_up(off + (uint64_t)std::max(g.nop, g.nsp) * g.M * c8, kAlign);
+    L.rh = off;
+    off = round_up(off + (uint64_t)g.M * g.nop * c8, kAlign);
+    L.wp = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * c8, kAlign);
+    L.part2 = L.part;  // the adjoint reuses the partial region
+    L.gsh = L.yh;
+  } else {
+    const uint64_t bp = (uint64_t)h.bp;
+    const uint64_t ncb = bp / 8;
+    L.staging = off;
+    off = round_up(off + (uint64_t)h.rs * g.M * std::max(h.nsq, h.noq) * c8, kAlign);
+    L.S = off;
+    off = round_up(off + (uint64_t)g.M * h.nsq * bp * c8, kAlign);
+    L.sig_up = off;
+    off = round_up(off + (uint64_t)g.M * bp * 4, kAlign);
+    L.sig_down = off;
+    off = round_up(off + (uint64_t)g.M * bp * 4, kAlign);
+    L.bop = off;
+    off = round_up(off + (uint64_t)g.M * h.nks * ncb * h.hterms_g * 1024, kAlign);
+    L.U = off;
+    off = round_up(off + (uint64_t)g.M * g.ngrid * bp * c8, kAlign);
+    L.tau_up = off;
+    off = round_up(off + (uint64_t)g.M * bp * 4, kAlign);
+    L.tau_down = off;
+    off = round_up(off + (uint64_t)g.M * bp * 4, kAlign);
+    L.part_f = off;
+    off = round_up(off + (uint64_t)h.splits_max * g.M * h.noq * 2 * bp * 4, kAlign);
+    L.yhb = off;
+    off = round_up(off + bp * g.nobs * g.M * c8, kAlign);
+  }
   L.ws_total = off;
   (void)d;
   return L;
@@ -164,7 +219,8 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
       d.max_batch < 0 || d.max_batch > 1024 || !(d.dt > 0.0) || (d.diff != S2W_DIFF_NONE && d.diff != S2W_DIFF_BACKWARD))
     return S2W_EINVAL;
   if (d.g_dtype < S2W_F32 || d.g_dtype > S2W_F16 || d.f_dtype < S2W_F32 || d.f_dtype > S2W_F16) return S2W_EINVAL;
-  if (d.g_dtype != S2W_F32 || d.f_dtype != S2W_F32) return S2W_EUNSUPPORTED;
+  const bool half = d.g_dtype != S2W_F32 || d.f_dtype != S2W_F32;
+  if (half && (d.g_dtype == S2W_F32 || d.f_dtype == S2W_F32)) return S2W_EUNSUPPORTED;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return S2W_EINVAL;
 
@@ -189,12 +245,29 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   g.nop4 = g.nop / 2;
   g.diff = d.diff;
   g.dt = (float)d.dt;
-  p->lay = make_layout(d, g, ncu);
+  HalfGeo& h = p->hg;
+  if (half) {
+    h.on = true;
+    h.ht_g = d.g_dtype == S2W_BF16 ? 1 : 2;
+    h.ht_f = d.f_dtype == S2W_BF16 ? 1 : 2;
+    h.hterms_g = 2;
+    h.hterms_f = 2;
+    h.nsq = (d.nsub + 15) / 16 * 16;
+    h.noq = 16 * next_pow2((d.nobs + 15) / 16);
+    h.ngq = (d.ngrid + 15) / 16 * 16;
+    h.nks = h.nsq / 16;
+    h.bp = (std::max(d.max_batch, 1) + 7) / 8 * 8;
+    h.splits_max = 16;
+    h.rs = 16;
+  }
+  p->lay = make_layout(d, g, h, ncu);
   p->tune.fused_wg_per_cu = 1;
   p->tune.fused_rows = 8;
   p->tune.adj_cols = 16;
   p->tune.adj_splits = 16;
   p->tune.batch_path_min_b = 1 << 30;
+  p->tune.gemm_cfg = -1;
+  p->tune.fgemm_splits = 0;
   p->row_set.assign((size_t)d.ngrid, 0);
   p->rows_missing = d.ngrid;
   {
@@ -247,6 +320,7 @@ s2w_status s2w_bind_memory(s2w_plan* p, void* operator_store, uint64_t operator_
   p->ws_bytes = workspace_bytes;
   std::fill(p->row_set.begin(), p->row_set.end(), 0);
   p->rows_missing = p->desc.ngrid;
+  p->pad_zeroed = false;
   return S2W_OK;
 }
 
@@ -280,6 +354,14 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.adj_splits = t->adj_splits;
   }
   if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
+  if (t->gemm_cfg) {
+    if (t->gemm_cfg < -1 || t->gemm_cfg > 4) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
+  }
+  if (t->fgemm_splits) {
+    if (t->fgemm_splits < 0 || t->fgemm_splits > 16) return fail(p, S2W_EINVAL, "tuning: fgemm_splits");
+    n.fgemm_splits = t->fgemm_splits;
+  }
   p->tune = n;
   return S2W_OK;
 }
@@ -287,6 +369,40 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
 s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   if (!p || !t) return S2W_EINVAL;
   *t = p->tune;
+  return S2W_OK;
+}
+
+// Half-precision setup: per staging pass of rs rows, transform to float32 spectra in the
+// workspace, then quantize with one power-of-two scale per (grid row, bin).
+static s2w_status set_operators_half(s2w_plan* p, const float* G_chunk, const float* F_chunk, int64_t row0,
+                                     int64_t nrows, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const HalfGeo& h = p->hg;
+  float2* stg = (float2*)(p->ws + p->lay.staging);
+  uint32_t* Gq = (uint32_t*)(p->op + p->lay.gq);
+  uint32_t* Fq = (uint32_t*)(p->op + p->lay.fq);
+  float* sG = (float*)(p->op + p->lay.sg);
+  float* sF = (float*)(p->op + p->lay.sf);
+  hipError_t e = hipSuccess;
+  if (!p->pad_zeroed) {
+    e = launch_zero_strided(Fq + g.ngrid, (int64_t)g.M * h.noq, h.ngq, h.ngq - g.ngrid, st);
+    if (e != hipSuccess) return hip_fail(p, e, "set_operators: clear padding");
+    p->pad_zeroed = true;
+  }
+  for (int64_t r = 0; r < nrows; r += h.rs) {
+    const int64_t n = std::min<int64_t>(h.rs, nrows - r);
+    e = launch_rfft_rows(G_chunk + r * g.nsub * g.nt, n, g.nsub, h.nsq, stg, (int64_t)g.M * h.nsq, 1, h.nsq, g, 1.0f,
+                         st);
+    if (e == hipSuccess)
+      e = launch_quant_rows(h.ht_g, stg, n, g.M, g.nsub, h.nsq, Gq, row0 + r, (int64_t)g.M * h.nsq, h.nsq, 1, sG, st);
+    if (e != hipSuccess) return hip_fail(p, e, "set_operators: elastic transform/quantize");
+    e = launch_rfft_rows(F_chunk + r * g.nobs * g.nt, n, g.nobs, h.noq, stg, (int64_t)g.M * h.noq, 1, h.noq, g, 1.0f,
+                         st);
+    if (e == hipSuccess)
+      e = launch_quant_rows(h.ht_f, stg, n, g.M, g.nobs, h.noq, Fq, row0 + r, 1, (int64_t)h.noq * h.ngq, h.ngq, sF,
+                            st);
+    if (e != hipSuccess) return hip_fail(p, e, "set_operators: acoustic transform/quantize");
+  }
   return S2W_OK;
 }
 
@@ -304,6 +420,17 @@ s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_c
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "set_operators: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
+  if (p->hg.on) {
+    s2w_status hs = set_operators_half(p, G_chunk, F_chunk, row0, nrows, st);
+    if (hs != S2W_OK) return hs;
+    for (int64_t r = row0; r < row0 + nrows; ++r) {
+      if (!p->row_set[(size_t)r]) {
+        p->row_set[(size_t)r] = 1;
+        --p->rows_missing;
+      }
+    }
+    return S2W_OK;
+  }
   float2* Gh = (float2*)(p->op + p->lay.gh);
   float2* Fh = (float2*)(p->op + p->lay.fh);
   // spectra of row (g, column c) land at [g][c][0..M)
@@ -335,6 +462,59 @@ static s2w_status check_call(s2w_plan* p, const void* in, int32_t B, const void*
   return S2W_OK;
 }
 
+// Batched forward on the matrix cores (half-precision stores).
+static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const HalfGeo& h = p->hg;
+  const Layout& L = p->lay;
+  float2* S = (float2*)(p->ws + L.S);
+  float* sig_up = (float*)(p->ws + L.sig_up);
+  float* sig_down = (float*)(p->ws + L.sig_down);
+  uint4* Bop = (uint4*)(p->ws + L.bop);
+  float2* U = (float2*)(p->ws + L.U);
+  float* tau_up = (float*)(p->ws + L.tau_up);
+  float* tau_down = (float*)(p->ws + L.tau_down);
+  float* part = (float*)(p->ws + L.part_f);
+  float2* yh = (float2*)(p->ws + L.yhb);
+  const uint4* Gq = (const uint4*)(p->op + L.gq);
+  const float* sG = (const float*)(p->op + L.sg);
+  const uint4* Fq = (const uint4*)(p->op + L.fq);
+  const float* sF = (const float*)(p->op + L.sf);
+  const int bp = h.bp;
+  const int ncb = (2 * B + 15) / 16;
+  int cfg = p->tune.gemm_cfg;
+  if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 3);
+  const int zt = (ncb + 7) / 8;
+  int splits = p->tune.fgemm_splits;
+  if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
+  splits = std::min(splits, h.splits_max);
+  hipError_t e = launch_rfft_rows(s, B, g.nsub, h.nsq, S, 1, bp, (int64_t)h.nsq * bp, g, 1.0f, st);
+  if (e == hipSuccess)
+    e = launch_prep_act(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, ncb, Bop, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
+  e = mark(p->ev_begin, st);
+  if (e == hipSuccess)
+    e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, p->ncu * p->tune.fused_wg_per_cu,
+                      g.ngrid, g.M, h.nks, ncb, B, bp, st);
+  if (e == hipSuccess) e = mark(p->ev_end, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
+  e = launch_mid_batch(U, sF, B, bp, false, g, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
+  const bool fscale = h.ht_f == 2;
+  if (fscale) {
+    e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
+  }
+  e = launch_gemm_f(h.ht_f, h.hterms_f, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, ncb,
+                    splits, st);
+  if (e == hipSuccess)
+    e = launch_sum_f(part, splits, g.M, h.noq, g.nobs, B, bp, fscale ? tau_down : nullptr, yh, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");
+  e = launch_irfft_rows(yh, (int64_t)B * g.nobs, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: output transform");
+  return S2W_OK;
+}
+
 s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
   s2w_status cs = check_call(p, s, B, y, "forward");
   if (cs != S2W_OK || B == 0) return cs;
@@ -342,6 +522,7 @@ s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* s
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "forward: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
+  if (p->hg.on) return forward_half(p, s, B, y, st);
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
   float2* Sh = (float2*)(p->ws + p->lay.sh);
@@ -384,6 +565,7 @@ s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* 
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "adjoint: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
+  if (p->hg.on) return fail(p, S2W_EUNSUPPORTED, "adjoint: not available for half-precision stores in this build");
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
   float2* Rh = (float2*)(p->ws + p->lay.rh);

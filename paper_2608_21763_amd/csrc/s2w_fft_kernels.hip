@@ -459,4 +459,52 @@ hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part
   return rows_contract_t<false>(Fh, Vh, part, cols_per_thread, splits, g.nobs, g.nop, g, st);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Batched mid-chain round trip, in place on U[l][g][b] (complex, b < bp): for grid row g and
+// ruptures b0 .. b0+R-1, gather all M slots, run inverse FFT -> truncate -> D_t -> zero-pad ->
+// FFT in LDS (Alg. 1 line 3; Alg. 2 steps 4-5 and 1-2), multiply by the acoustic store's
+// scale sF[g][l] (if given) and write back.
+template <int R>
+__global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
+                                                   int B, int bp, int M, int logM, int nt, int mode, float mscale) {
+  extern __shared__ float2 smem[];
+  float2* X = smem;
+  float2* BA = X + R * M;
+  float2* BB = BA + R * M;
+  const int nbb = (B + R - 1) / R;
+  const int g = blockIdx.x / nbb;
+  const int b0 = (blockIdx.x % nbb) * R;
+  for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
+    const int l = i / R, r = i % R;
+    const int b = b0 + r;
+    X[r * M + l] = b < B ? U[((int64_t)l * ngrid + g) * bp + b] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_midchain(X, X, BA, BB, R, M, logM, nt, mode, mscale);
+  for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
+    const int l = i / R, r = i % R;
+    const int b = b0 + r;
+    if (b < B) {
+      float2 v = X[r * M + l];
+      if (sF) {
+        const float f = sF[(int64_t)g * M + l];
+        v.x *= f;
+        v.y *= f;
+      }
+      U[((int64_t)l * ngrid + g) * bp + b] = v;
+    }
+  }
+}
+
+hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, const Geometry& g,
+                            hipStream_t st) {
+  constexpr int R = 8;
+  const int mode = g.diff ? (adjoint ? MID_BACKWARD_T : MID_BACKWARD) : MID_NONE;
+  const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
+  const int64_t nblk = (int64_t)g.ngrid * ((B + R - 1) / R);
+  hipLaunchKernelGGL(k_mid_batch<R>, dim3((unsigned)nblk), dim3(256), 3 * (size_t)R * g.M * sizeof(float2), st, U, sF,
+                     g.ngrid, B, bp, g.M, g.logM, g.nt, mode, mscale);
+  return hipGetLastError();
+}
+
 }  // namespace s2w

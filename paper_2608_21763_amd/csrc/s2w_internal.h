@@ -60,4 +60,22 @@ hipError_t launch_forward_rows(const float2* Gh, const float2* Sh, float2* Vh, i
 hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part, int cols_per_thread, int splits,
                                 const Geometry& g, hipStream_t st);
 
+// ---- batched path (matrix cores, half-precision stores); ht: 1 = bf16, 2 = f16 ----
+hipError_t launch_quant_rows(int ht, const float2* staging, int64_t nrows, int M, int nc, int ncp, uint32_t* out,
+                             int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, hipStream_t st);
+hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
+                           int nsq, int B, int bp, int nks, int ncb, uint4* Bop, hipStream_t st);
+hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
+                         const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
+                         hipStream_t st);
+hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, const Geometry& g,
+                            hipStream_t st);
+hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
+                            hipStream_t st);
+hipError_t launch_gemm_f(int ht, int hterms, const uint4* Fq, const float2* V, const float* tau_up, float* part,
+                         int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st);
+hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs, int B, int bp, const float* tau_down,
+                        float2* yh, hipStream_t st);
+hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st);
+
 }  // namespace s2w

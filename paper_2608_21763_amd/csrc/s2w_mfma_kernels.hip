@@ -1,0 +1,523 @@
+// Batched path on the matrix cores: per-bin complex GEMMs with half-precision operators.
+//
+// Half-precision stores (HT = 1: bfloat16, HT = 2: float16), one 32-bit word per complex
+// value (low half = real part, high half = imaginary part):
+//   Gq[g][l][j]   elastic spectra, j padded to nsq (a multiple of 16, zeros)
+//   Fq[l][o][g]   acoustic spectra, o padded to noq (multiple of 16), g padded to ngq (multiple of 16)
+//   sG[g][l], sF[g][l]  float32 power-of-two scales: true value = scale * stored value
+//
+// A complex product sum_k A_k B_k is carried on real matrix cores by embedding each complex
+// operand value a = ar + i ai as the two K entries (ar, ai) and each complex activation value
+// b = br + i bi as the 2x2 block [[br, bi], [-bi, br]] (rows: K entries ar, ai; columns: real
+// and imaginary output).  Slot 0 packs the two real bins (0 and L/2) and uses
+// [[b0, 0], [0, bN]] instead.  Activations are split into a high and a low half-precision
+// term (H = 2) so that their rounding stays below the operator's; products accumulate in
+// float32.
+//
+// MFMA v_mfma_f32_16x16x32 (bf16/f16) fragments, lane l of 64:
+//   A (16 x 32): row l%16, K entries 8*(l/16) .. +7      (16 bytes, 4 complex operand values)
+//   B (32 x 16): column l%16, K entries 8*(l/16) .. +7
+//   D (16 x 16): column l%16, rows 4*(l/16) .. +3        (4 floats)
+#include <hip/hip_bf16.h>
+
+#include "s2w_internal.h"
+
+namespace s2w {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// streaming 16-byte load that bypasses cache retention
+__device__ __forceinline__ uint4 ntload(const uint4* p) {
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// float -> half bits, round to nearest even
+template <int HT>
+__device__ __forceinline__ uint32_t to_half_bits(float v);
+template <>
+__device__ __forceinline__ uint32_t to_half_bits<1>(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+template <>
+__device__ __forceinline__ uint32_t to_half_bits<2>(float v) {
+  _Float16 h = (_Float16)v;
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
+}
+template <int HT>
+__device__ __forceinline__ float from_half_bits(uint32_t b);
+template <>
+__device__ __forceinline__ float from_half_bits<1>(uint32_t b) {
+  return __uint_as_float(b << 16);
+}
+template <>
+__device__ __forceinline__ float from_half_bits<2>(uint32_t b) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+}
+
+template <int HT>
+__device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
+  if constexpr (HT == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
+                                                  0, 0);
+}
+
+// power-of-two scale that maps a row maximum mx into [2^14, 2^15); returns the multiplier
+// applied before rounding (`up`) and its inverse (`down`)
+__device__ __forceinline__ void pow2_scale(float mx, float& up, float& down) {
+  if (!(mx > 0.f) || !isfinite(mx)) {
+    up = 1.f;
+    down = 1.f;
+    return;
+  }
+  int ex;
+  frexpf(mx, &ex);  // mx = f * 2^ex, f in [0.5, 1)
+  // rows whose largest entry is below 2^-111 keep the multiplier finite (<= 2^126); their
+  // scaled values then sit below 2^15 without filling the range, which is harmless
+  ex = ex < -111 ? -111 : ex;
+  up = ldexpf(1.f, 15 - ex);
+  down = ldexpf(1.f, ex - 15);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Setup: quantize rows of float32 spectra.  staging[r][l][c] (complex, c < ncp stored, c < nc
+// valid) -> out + (row0 + r)*sg + l*sl + c*sc (32-bit words), scale[(row0 + r)*M + l].
+// One block per (r, l): the scale is a power of two mapping the row's largest |re|, |im| into
+// [2^14, 2^15).
+template <int HT>
+__global__ __launch_bounds__(256) void k_quant_rows(const float2* __restrict__ staging, int M, int nc, int ncp,
+                                                    uint32_t* __restrict__ out, int64_t row0, int64_t sg, int64_t sl,
+                                                    int64_t sc, float* __restrict__ scale) {
+  __shared__ float red[256];
+  const int r = blockIdx.x / M, l = blockIdx.x % M;
+  const float2* row = staging + ((int64_t)r * M + l) * ncp;
+  float mx = 0.f;
+  for (int c = threadIdx.x; c < nc; c += 256) {
+    const float2 v = row[c];
+    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  float up, down;
+  pow2_scale(red[0], up, down);
+  const int64_t g = row0 + r;
+  if (threadIdx.x == 0) scale[g * M + l] = down;
+  uint32_t* o = out + g * sg + (int64_t)l * sl;
+  for (int c = threadIdx.x; c < ncp; c += 256) {
+    const float2 v = c < nc ? row[c] : make_float2(0.f, 0.f);
+    o[(int64_t)c * sc] = to_half_bits<HT>(v.x * up) | (to_half_bits<HT>(v.y * up) << 16);
+  }
+}
+
+hipError_t launch_quant_rows(int ht, const float2* staging, int64_t nrows, int M, int nc, int ncp, uint32_t* out,
+                             int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, hipStream_t st) {
+  if (nrows == 0) return hipSuccess;
+  dim3 grid((unsigned)(nrows * M));
+  if (ht == 1)
+    hipLaunchKernelGGL(k_quant_rows<1>, grid, dim3(256), 0, st, staging, M, nc, ncp, out, row0, sg, sl, sc, scale);
+  else
+    hipLaunchKernelGGL(k_quant_rows<2>, grid, dim3(256), 0, st, staging, M, nc, ncp, out, row0, sg, sl, sc, scale);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Activation scales: sig[l][b] = power of two mapping max_j |S[l][j][b]| (re, im) into
+// [2^14, 2^15) (the inverse is applied to the GEMM result).  S is [l][nsq][bp] complex.
+__global__ __launch_bounds__(256) void k_act_scale(const float2* __restrict__ S, int M, int nsub, int nsq, int B,
+                                                   int bp, float* __restrict__ sig_up, float* __restrict__ sig_down) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)M * bp) return;
+  const int l = (int)(i / bp), b = (int)(i - (int64_t)l * bp);
+  float mx = 0.f;
+  if (b < B)
+    for (int j = 0; j < nsub; ++j) {
+      const float2 v = S[((int64_t)l * nsq + j) * bp + b];
+      mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+  float up, down;
+  pow2_scale(mx, up, down);
+  sig_up[i] = up;
+  sig_down[i] = down;
+}
+
+// B operand of the elastic GEMM in fragment order: Bop[l][ks][cb][h][lane] (16 bytes each).
+// Column n = 16*cb + lane%16 is output (rupture n/2, real part if n even, imaginary if odd);
+// K entry k = 8*(lane/16) + e covers subfault j = 16*ks + k/2, component k&1.
+template <int HT, int H>
+__global__ __launch_bounds__(256) void k_prep_act(const float2* __restrict__ S, const float* __restrict__ sig_up,
+                                                  int M, int nsub, int nsq, int B, int bp, int nks, int ncb,
+                                                  uint4* __restrict__ Bop) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)M * nks * ncb * 64;
+  if (i >= total) return;
+  const int lane = (int)(i & 63);
+  int64_t q = i >> 6;
+  const int cb = (int)(q % ncb);
+  q /= ncb;
+  const int ks = (int)(q % nks);
+  const int l = (int)(q / nks);
+  const int n = 16 * cb + (lane & 15);
+  const int b = n >> 1, c = n & 1;
+  const bool dc = (l == 0);
+  uint32_t hi[4], lo[4];
+#pragma unroll
+  for (int e2 = 0; e2 < 4; ++e2) {
+    const int j = 16 * ks + 4 * (lane >> 4) + e2;
+    float2 s = make_float2(0.f, 0.f);
+    if (b < B && j < nsub) {
+      s = S[((int64_t)l * nsq + j) * bp + b];
+      const float u = sig_up[(int64_t)l * bp + b];
+      s.x *= u;
+      s.y *= u;
+    }
+    // K entries (re component a = 0, im component a = 1) for this output column
+    float v0, v1;
+    if (dc) {
+      v0 = c == 0 ? s.x : 0.f;
+      v1 = c == 0 ? 0.f : s.y;
+    } else {
+      v0 = c == 0 ? s.x : s.y;
+      v1 = c == 0 ? -s.y : s.x;
+    }
+    const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
+    hi[e2] = h0 | (h1 << 16);
+    if (H == 2) {
+      const uint32_t l0 = to_half_bits<HT>(v0 - from_half_bits<HT>(h0));
+      const uint32_t l1 = to_half_bits<HT>(v1 - from_half_bits<HT>(h1));
+      lo[e2] = l0 | (l1 << 16);
+    }
+  }
+  uint4* dst = Bop + (((int64_t)l * nks + ks) * ncb + cb) * H * 64 + lane;
+  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+}
+
+hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
+                           int nsq, int B, int bp, int nks, int ncb, uint4* Bop, hipStream_t st) {
+  const int64_t ns = (int64_t)M * bp;
+  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp, sig_up,
+                     sig_down);
+  const int64_t total = (int64_t)M * nks * ncb * 64;
+  dim3 grid((unsigned)((total + 255) / 256));
+#define S2W_PREP(HT_, H_) \
+  hipLaunchKernelGGL((k_prep_act<HT_, H_>), grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, ncb, Bop)
+  if (ht == 1) {
+    if (hterms == 2) S2W_PREP(1, 2); else S2W_PREP(1, 1);
+  } else {
+    if (hterms == 2) S2W_PREP(2, 2); else S2W_PREP(2, 1);
+  }
+#undef S2W_PREP
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Elastic GEMM per bin (eq. 1, Alg. 2 step 3, batched):
+//   U[l][g][b] = sG[g][l] * sig_down[l][b] * sum_j Gq[g][l][j] (x) Sq[l][j][b]
+// Persistent and XCD-aware: workgroup w runs on XCD w % 8 (round-robin dispatch) and takes the
+// tiles of bins l = w % 8 (mod 8), so the 32 workgroups of an XCD share one bin's activation
+// in that XCD's L2.  Tile: MG = MW*WR grid rows x NG = NW*WC output columns; wave (wr, wc)
+// owns MW x NW.
+template <int HT, int H, int MW, int NW, int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restrict__ Gq, const float* __restrict__ sG,
+                                                            const uint4* __restrict__ Bop,
+                                                            const float* __restrict__ sig_down, float* __restrict__ U,
+                                                            int ngrid, int M, int nks, int ncb, int B, int bp, int nrb,
+                                                            int nct) {
+  constexpr int MF = MW / 16, NF = NW / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int nwg = gridDim.x, w = blockIdx.x;
+  const int nx = 8 < M ? 8 : M;  // bins are dealt to XCDs round-robin
+  const int x = w % nx, wi = w / nx, nwx = (nwg - x + nx - 1) / nx;
+  const int slots_x = (M - x + nx - 1) / nx;
+  const int64_t per_slot = (int64_t)nrb * nct;
+  const int64_t items = (int64_t)slots_x * per_slot;
+  const int64_t row_u4 = (int64_t)nks * 4;  // uint4 per (g, l) row of Gq
+  for (int64_t it = wi; it < items; it += nwx) {
+    const int l = x + nx * (int)(it / per_slot);
+    const int64_t rem = it % per_slot;
+    const int rb = (int)(rem / nct), ct = (int)(rem % nct);
+    const int g0 = rb * MW * WR + wr * MW;
+    const int cb0 = ct * NF * WC + wc * NF;
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const uint4* arow[MF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a) {
+      const int g = min(g0 + 16 * a + (lane & 15), ngrid - 1);
+      arow[a] = Gq + ((int64_t)g * M + l) * row_u4 + (lane >> 4);
+    }
+    const uint4* bb = Bop + (int64_t)l * nks * ncb * H * 64 + lane;
+    const bool colok = cb0 < ncb;
+#pragma unroll 2
+    for (int ks = 0; ks < nks; ++ks) {
+      uint4 av[MF], bv[NF][H];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) av[a] = ntload(arow[a] + 4 * ks);
+#pragma unroll
+      for (int b = 0; b < NF; ++b)
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const int cb = min(cb0 + b, ncb - 1);
+          bv[b][h] = bb[(((int64_t)ks * ncb + cb) * H + h) * 64];
+        }
+#pragma unroll
+      for (int a = 0; a < MF; ++a)
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+#pragma unroll
+          for (int h = 0; h < H; ++h) acc[a][b] = mfma16<HT>(av[a], bv[b][h], acc[a][b]);
+    }
+    if (!colok) continue;
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + 16 * a + 4 * (lane >> 4) + r;
+        if (g >= ngrid) continue;
+        const float sg = sG[(int64_t)g * M + l];
+#pragma unroll
+        for (int b = 0; b < NF; ++b) {
+          const int n = 16 * (cb0 + b) + (lane & 15);
+          const int rup = n >> 1;
+          if (cb0 + b < ncb && rup < B)
+            U[(((int64_t)l * ngrid + g) * bp + rup) * 2 + (n & 1)] =
+                acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+        }
+      }
+  }
+}
+
+template <int HT, int H>
+static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint4* Bop, const float* sig_down,
+                           float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp, hipStream_t st) {
+#define S2W_GG(MW_, NW_, WR_, WC_)                                                                                 \
+  do {                                                                                                              \
+    const int nrb = (ngrid + MW_ * WR_ - 1) / (MW_ * WR_);                                                          \
+    const int nct = (ncb + (NW_ / 16) * WC_ - 1) / ((NW_ / 16) * WC_);                                              \
+    hipLaunchKernelGGL((k_gemm_g<HT, H, MW_, NW_, WR_, WC_>), dim3(nwg), dim3(64 * WR_ * WC_), 0, st, Gq, sG, Bop, \
+                       sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);                                           \
+  } while (0)
+  switch (cfg) {
+    case 0: S2W_GG(64, 16, 4, 1); break;   // narrow batches (B <= 8)
+    case 1: S2W_GG(64, 64, 2, 2); break;   // 128 x 128
+    case 2: S2W_GG(32, 128, 1, 4); break;  // 32 x 512
+    case 3: S2W_GG(64, 128, 1, 4); break;  // 64 x 512
+    default: return hipErrorInvalidValue;
+  }
+#undef S2W_GG
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
+                         const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
+                         hipStream_t st) {
+  if (ht == 1)
+    return hterms == 2 ? gemm_g_h<1, 2>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st)
+                       : gemm_g_h<1, 1>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
+  return hterms == 2 ? gemm_g_h<2, 2>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st)
+                     : gemm_g_h<2, 1>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Acoustic GEMM per bin (eq. 2, Alg. 2 step 3, batched), split over grid rows:
+//   part[split][l][o][n] = sum_{g in split} Fq[l][o][g] (x) V[l][g][b]   (n = 2b + re/im)
+// V (float32, [l][g][bp] complex, already multiplied by sF[g][l] and by tau_up[l][b]) is
+// converted to half precision (H terms) in registers.  Workgroup (l, split, column tile):
+// rows = all observers (nof fragments of 16), NW output columns per wave.
+template <int HT, int H, int NF, int MF>
+__global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, const float2* __restrict__ V,
+                                                const float* __restrict__ tau_up, float* __restrict__ part, int ngrid,
+                                                int ngq, int M, int noq, int B, int bp, int ncb) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l = blockIdx.x;
+  const int split = blockIdx.y, splits = gridDim.y;
+  const int cb0 = (blockIdx.z * 4 + wave) * NF;
+  const int kst0 = (int)((int64_t)(ngq / 16) * split / splits), kst1 = (int)((int64_t)(ngq / 16) * (split + 1) / splits);
+  const bool dc = (l == 0);
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // B fragment column of this lane, per column block
+  int rup[NF], cim[NF];
+  float tu[NF];
+#pragma unroll
+  for (int b = 0; b < NF; ++b) {
+    const int n = 16 * (cb0 + b) + (lane & 15);
+    rup[b] = min(n >> 1, bp - 1);
+    cim[b] = n & 1;
+    tu[b] = tau_up ? tau_up[(int64_t)l * bp + rup[b]] : 1.f;
+  }
+  const int64_t frow = (int64_t)ngq / 4;  // uint4 per (l, o) row of Fq
+  const uint4* fa = Fq + (int64_t)l * noq * frow + (lane >> 4);
+  const float2* vb = V + (int64_t)l * ngrid * bp;
+  for (int ks = kst0; ks < kst1; ++ks) {
+    uint4 av[MF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a) av[a] = ntload(fa + (int64_t)(16 * a + (lane & 15)) * frow + 4 * ks);
+    const int gb = 16 * ks + 4 * (lane >> 4);
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+      uint32_t hi[4], lo[4];
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        const int g = gb + e2;
+        float2 v = g < ngrid ? vb[(int64_t)g * bp + rup[b]] : make_float2(0.f, 0.f);
+        v.x *= tu[b];
+        v.y *= tu[b];
+        float v0, v1;
+        if (dc) {
+          v0 = cim[b] == 0 ? v.x : 0.f;
+          v1 = cim[b] == 0 ? 0.f : v.y;
+        } else {
+          v0 = cim[b] == 0 ? v.x : v.y;
+          v1 = cim[b] == 0 ? -v.y : v.x;
+        }
+        const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
+        hi[e2] = h0 | (h1 << 16);
+        if (H == 2)
+          lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) | (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
+      }
+      const uint4 bh = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+#pragma unroll
+      for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bh, acc[a][b]);
+      if (H == 2) {
+        const uint4 bl = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+#pragma unroll
+        for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bl, acc[a][b]);
+      }
+    }
+  }
+  // part[split][l][o][n], n < 2*bp
+  float* pw = part + ((int64_t)split * M + l) * noq * (2 * bp);
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 16 * a + 4 * (lane >> 4) + r;
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        const int n = 16 * (cb0 + b) + (lane & 15);
+        if (cb0 + b < ncb && n < 2 * bp) pw[(int64_t)o * (2 * bp) + n] = acc[a][b][r];
+      }
+    }
+}
+
+hipError_t launch_gemm_f(int ht, int hterms, const uint4* Fq, const float2* V, const float* tau_up, float* part,
+                         int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st) {
+  constexpr int NF = 2;  // column blocks per wave
+  dim3 grid(M, splits, (ncb + 4 * NF - 1) / (4 * NF));
+  const int mf = noq / 16;
+#define S2W_GF(HT_, H_, MF_)                                                                                     \
+  hipLaunchKernelGGL((k_gemm_f<HT_, H_, NF, MF_>), grid, dim3(256), 0, st, Fq, V, tau_up, part, ngrid, ngq, M, noq, \
+                     B, bp, ncb)
+#define S2W_GF_M(HT_, H_)                   \
+  do {                                      \
+    if (mf == 1) S2W_GF(HT_, H_, 1);        \
+    else if (mf == 2) S2W_GF(HT_, H_, 2);   \
+    else if (mf == 4) S2W_GF(HT_, H_, 4);   \
+    else if (mf == 8) S2W_GF(HT_, H_, 8);   \
+    else if (mf == 16) S2W_GF(HT_, H_, 16); \
+    else return hipErrorInvalidValue;       \
+  } while (0)
+  if (ht == 1) {
+    if (hterms == 2) S2W_GF_M(1, 2); else S2W_GF_M(1, 1);
+  } else {
+    if (hterms == 2) S2W_GF_M(2, 2); else S2W_GF_M(2, 1);
+  }
+#undef S2W_GF_M
+#undef S2W_GF
+  return hipGetLastError();
+}
+
+// Column scales of the acoustic GEMM's activation (float16 operands only): for each (l, b),
+// a power of two mapping max_g |V[l][g][b]| into [2^14, 2^15).
+__global__ __launch_bounds__(256) void k_col_scale(const float2* __restrict__ V, int ngrid, int M, int B, int bp,
+                                                   float* __restrict__ tau_up, float* __restrict__ tau_down) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)M * bp) return;
+  const int l = (int)(i / bp), b = (int)(i - (int64_t)l * bp);
+  float mx = 0.f;
+  if (b < B) {
+    const float2* v = V + (int64_t)l * ngrid * bp + b;
+    for (int g = 0; g < ngrid; ++g) {
+      const float2 x = v[(int64_t)g * bp];
+      mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)));
+    }
+  }
+  float up, down;
+  pow2_scale(mx, up, down);
+  tau_up[i] = up;
+  tau_down[i] = down;
+}
+
+hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
+                            hipStream_t st) {
+  const int64_t n = (int64_t)M * bp;
+  hipLaunchKernelGGL(k_col_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ngrid, M, B, bp, tau_up,
+                     tau_down);
+  return hipGetLastError();
+}
+
+// Zero 32-bit words: out[i * stride + k] for i < n, k < width.
+__global__ __launch_bounds__(256) void k_zero_strided(uint32_t* __restrict__ out, int64_t n, int64_t stride, int width) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * width) return;
+  const int64_t r = i / width;
+  out[r * stride + (i - r * width)] = 0u;
+}
+
+hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st) {
+  const int64_t tot = n * width;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_strided, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, out, n, stride, width);
+  return hipGetLastError();
+}
+
+// Sum the acoustic partials over splits, undo the activation scale, and lay the result out
+// as rows yh[b][o][l] (complex) for the inverse transform.
+__global__ __launch_bounds__(256) void k_sum_f(const float* __restrict__ part, int splits, int M, int noq, int nobs,
+                                               int B, int bp, const float* __restrict__ tau_down, float2* __restrict__ yh) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;  // over (l, o, b)
+  const int64_t total = (int64_t)M * nobs * B;
+  if (i >= total) return;
+  const int b = (int)(i % B);
+  const int64_t q = i / B;
+  const int o = (int)(q % nobs), l = (int)(q / nobs);
+  float re = 0.f, im = 0.f;
+  for (int s = 0; s < splits; ++s) {
+    const float* p = part + (((int64_t)s * M + l) * noq + o) * (2 * bp) + 2 * b;
+    re += p[0];
+    im += p[1];
+  }
+  const float td = tau_down ? tau_down[(int64_t)l * bp + b] : 1.f;
+  yh[((int64_t)b * nobs + o) * M + l] = make_float2(re * td, im * td);
+}
+
+hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs, int B, int bp, const float* tau_down,
+                        float2* yh, hipStream_t st) {
+  const int64_t total = (int64_t)M * nobs * B;
+  hipLaunchKernelGGL(k_sum_f, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, splits, M, noq, nobs, B,
+                     bp, tau_down, yh);
+  return hipGetLastError();
+}
+
+}  // namespace s2w
