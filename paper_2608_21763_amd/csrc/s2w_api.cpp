@@ -355,7 +355,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
   }
   if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
   if (t->gemm_cfg) {
-    if (t->gemm_cfg < -1 || t->gemm_cfg > 4) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    if (t->gemm_cfg < -1 || t->gemm_cfg > 6) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_splits) {
@@ -483,8 +483,8 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int bp = h.bp;
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
-  if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 3);
-  const int zt = (ncb + 7) / 8;
+  if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 5);
+  const int zt = (ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8;
   int splits = p->tune.fgemm_splits;
   if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
   splits = std::min(splits, h.splits_max);
@@ -498,15 +498,16 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
                       g.ngrid, g.M, h.nks, ncb, B, bp, st);
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
-  e = launch_mid_batch(U, sF, B, bp, false, g, st);
-  if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   const bool fscale = h.ht_f == 2;
+  const bool packed = h.ht_f == 1 && h.hterms_f == 2;
+  e = launch_mid_batch(U, sF, B, bp, false, packed, g, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
     e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
   }
-  e = launch_gemm_f(h.ht_f, h.hterms_f, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, ncb,
-                    splits, st);
+  e = launch_gemm_f(h.ht_f, h.hterms_f, packed, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq, B,
+                    bp, ncb, splits, st);
   if (e == hipSuccess)
     e = launch_sum_f(part, splits, g.M, h.noq, g.nobs, B, bp, fscale ? tau_down : nullptr, yh, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");

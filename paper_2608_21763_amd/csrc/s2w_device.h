@@ -27,33 +27,84 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 
-// exp(-2 pi i k / L) for 0 <= k < L/2, L a power of two <= TWN
+// exp(-2 pi i k / L) for 0 <= k < L/2, L a power of two <= TWN (from the constant table)
 __device__ __forceinline__ float2 twiddle(int k, int L) { return c_tw[k * (TWN / L)]; }
+
+// Per-workgroup twiddle tables in LDS for transforms of M complex points (real length L = 2M):
+//   tw.c[k] = exp(-2 pi i k / M), k < M    (complex FFT, full circle)
+//   tw.r[k] = exp(-2 pi i k / L), k < M    (real-FFT pre/post step)
+struct Twiddles {
+  float2* c;
+  float2* r;
+};
+
+// Fill the tables (2*M float2 of LDS at `buf`); all threads call it; ends with a barrier.
+__device__ __forceinline__ Twiddles lds_twiddles(float2* buf, int M) {
+  Twiddles t{buf, buf + M};
+  const int half = M >> 1;
+  for (int k = threadIdx.x; k < M; k += blockDim.x) {
+    float2 w = c_tw[(k < half ? k : k - half) * (TWN / M)];
+    if (k >= half) w = make_float2(-w.x, -w.y);  // exp(-2 pi i (k - M/2)/M) * exp(-pi i)
+    t.c[k] = w;
+    t.r[k] = c_tw[k * (TWN / (2 * M))];
+  }
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ float2 cmul_dir(float2 a, float2 w, int dir) {
+  // a * w (dir < 0) or a * conj(w) (dir > 0)
+  return dir < 0 ? cmul(a, w) : cmul(a, cconj(w));
+}
 
 // Complex FFT of R rows of length M (power of two, 2 <= M <= TWN/2) held row-major in LDS
 // buffer `a`; `b` is scratch of the same size.  dir < 0: exp(-2 pi i nk/M) (forward);
-// dir > 0: exp(+2 pi i nk/M) (inverse, unnormalised).  Stockham autosort, radix 2.
-// Every thread of the block must call it; returns the buffer holding the result,
-// after a barrier.
-__device__ __forceinline__ float2* lds_cfft(float2* a, float2* b, int R, int M, int logM, int dir) {
-  const int half = M >> 1;
-  const int total = R * half;
-  for (int st = 0; st < logM; ++st) {
-    const int s = 1 << st;
-    const int l = half >> st;
+// dir > 0: exp(+2 pi i nk/M) (inverse, unnormalised).  Stockham autosort: radix-4 stages,
+// then one radix-2 stage when log2(M) is odd.  Every thread of the block must call it;
+// returns the buffer holding the result, after a barrier.
+__device__ __forceinline__ float2* lds_cfft(float2* a, float2* b, int R, int M, int logM, int dir, const float2* tw) {
+  int s = 1, lgs = 0;
+  while (s * 4 <= M) {
+    const int l = M / (4 * s);
+    const int quarter = M >> 2;
+    const int total = R * quarter;
+    for (int i = threadIdx.x; i < total; i += blockDim.x) {
+      const int r = i >> (logM - 2);
+      const int bi = i & (quarter - 1);
+      const int p = bi >> lgs, q = bi & (s - 1);
+      const float2* ar = a + r * M + q + s * p;
+      const float2 x0 = ar[0], x1 = ar[s * l], x2 = ar[2 * s * l], x3 = ar[3 * s * l];
+      const float2 a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3);
+      const float2 d = csub(x1, x3);
+      // (x1 - x3) * exp(dir * i pi / 2): forward multiplies by -i, inverse by +i
+      const float2 a3 = dir < 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+      const int e = p * s;
+      float2* br = b + r * M + q + s * 4 * p;
+      br[0] = cadd(a0, a2);
+      br[s] = cmul_dir(cadd(a1, a3), tw[e], dir);
+      br[2 * s] = cmul_dir(csub(a0, a2), tw[2 * e], dir);
+      br[3 * s] = cmul_dir(csub(a1, a3), tw[3 * e], dir);
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+    s <<= 2;
+    lgs += 2;
+  }
+  if (s < M) {
+    const int half = M >> 1;
+    const int total = R * half;
     for (int i = threadIdx.x; i < total; i += blockDim.x) {
       const int r = i >> (logM - 1);
       const int bi = i & (half - 1);
-      const int p = bi >> st;
-      const int q = bi & (s - 1);
+      const int p = bi >> lgs, q = bi & (s - 1);
       const float2* ar = a + r * M;
       const float2 x0 = ar[q + s * p];
-      const float2 x1 = ar[q + s * (p + l)];
-      float2 w = twiddle(p * s, M);
-      if (dir > 0) w.y = -w.y;
+      const float2 x1 = ar[q + s * (p + 1)];
       float2* br = b + r * M;
       br[q + 2 * s * p] = cadd(x0, x1);
-      br[q + 2 * s * p + s] = cmul(csub(x0, x1), w);
+      br[q + 2 * s * p + s] = cmul_dir(csub(x0, x1), tw[p * s], dir);
     }
     __syncthreads();
     float2* t = a;
@@ -64,8 +115,8 @@ __device__ __forceinline__ float2* lds_cfft(float2* a, float2* b, int R, int M, 
 }
 
 // Pre-step of the inverse real FFT: packed spectrum X (M slots, real length L = 2M)
-// -> Z with z = IFFT_M(Z) giving L*x[2n] + i L*x[2n+1].
-__device__ __forceinline__ float2 irfft_pre(const float2* X, int k, int M) {
+// -> Z with z = IFFT_M(Z) giving L*x[2n] + i L*x[2n+1].  tr = Twiddles::r.
+__device__ __forceinline__ float2 irfft_pre(const float2* X, int k, int M, const float2* tr) {
   if (k == 0) {
     const float2 x0 = X[0];
     return make_float2(x0.x + x0.y, x0.x - x0.y);
@@ -73,12 +124,12 @@ __device__ __forceinline__ float2 irfft_pre(const float2* X, int k, int M) {
   const float2 xk = X[k];
   const float2 xc = cconj(X[M - k]);
   const float2 e = cadd(xk, xc);
-  const float2 o = cmul(csub(xk, xc), cconj(twiddle(k, 2 * M)));
+  const float2 o = cmul(csub(xk, xc), cconj(tr[k]));
   return make_float2(e.x - o.y, e.y + o.x);  // e + i o
 }
 
 // Post-step of the forward real FFT: Z = FFT_M(x[2n] + i x[2n+1]) -> packed slot k.
-__device__ __forceinline__ float2 rfft_post(const float2* Z, int k, int M) {
+__device__ __forceinline__ float2 rfft_post(const float2* Z, int k, int M, const float2* tr) {
   if (k == 0) {
     const float2 z0 = Z[0];
     return make_float2(z0.x + z0.y, z0.x - z0.y);
@@ -88,7 +139,7 @@ __device__ __forceinline__ float2 rfft_post(const float2* Z, int k, int M) {
   const float2 e = cscale(cadd(zk, zc), 0.5f);
   const float2 d = csub(zk, zc);
   const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
-  return cadd(e, cmul(twiddle(k, 2 * M), o));
+  return cadd(e, cmul(tr[k], o));
 }
 
 // Real time sample m (0 <= m < L) from the inverse-FFT output z (pairs).
@@ -101,21 +152,21 @@ __device__ __forceinline__ float zsample(const float2* z, int m) {
 enum MidMode { MID_NONE = 0, MID_BACKWARD = 1, MID_BACKWARD_T = 2 };
 
 // Mid-chain round trip for R rows (Alg. 2 steps 4-5 of the first product, D_t, and
-// steps 1-2 of the second): packed spectra `U` [R][M] (LDS) -> inverse real FFT ->
-// keep samples n < nt -> temporal difference -> zero-pad -> forward real FFT ->
-// packed spectra written to `V` [R][M] (LDS, may alias U).  `scale` multiplies the
-// time series (it carries 1/L of the inverse transform and 1/dt of D_t).
-// bufA and bufB are [R][M] scratch.  All threads of the block call it.
-__device__ __forceinline__ void lds_midchain(const float2* U, float2* V, float2* bufA, float2* bufB, int R, int M,
-                                             int logM, int nt, int mode, float scale) {
+// steps 1-2 of the second): packed spectra in `X` [R][M] (LDS) -> inverse real FFT ->
+// keep samples n < nt -> temporal difference -> zero-pad -> forward real FFT -> packed
+// spectra.  `scale` multiplies the time series (it carries 1/L of the inverse transform
+// and 1/dt of D_t).  `Y` is [R][M] LDS scratch.  Returns the buffer (X or Y) holding the
+// result.  All threads of the block call it; it ends after a barrier.
+__device__ __forceinline__ float2* lds_midchain2(float2* X, float2* Y, int R, int M, int logM, int nt, int mode,
+                                                 float scale, const Twiddles& tw) {
   const int n = R * M;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int r = i >> logM, k = i & (M - 1);
-    bufA[i] = irfft_pre(U + r * M, k, M);
+    Y[i] = irfft_pre(X + r * M, k, M, tw.r);
   }
   __syncthreads();
-  float2* z = lds_cfft(bufA, bufB, R, M, logM, +1);
-  float2* zz = (z == bufA) ? bufB : bufA;
+  float2* z = lds_cfft(Y, X, R, M, logM, +1, tw.c);
+  float2* zz = (z == Y) ? X : Y;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int r = i >> logM, p = i & (M - 1);
     const float2* zr = z + r * M;
@@ -139,10 +190,173 @@ __device__ __forceinline__ void lds_midchain(const float2* U, float2* V, float2*
     zz[i] = make_float2(v[0], v[1]);
   }
   __syncthreads();
-  float2* Z = lds_cfft(zz, z, R, M, logM, -1);
+  float2* Z = lds_cfft(zz, z, R, M, logM, -1, tw.c);
+  float2* V = (Z == X) ? Y : X;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int r = i >> logM, k = i & (M - 1);
-    V[i] = rfft_post(Z + r * M, k, M);
+    V[i] = rfft_post(Z + r * M, k, M, tw.r);
+  }
+  __syncthreads();
+  return V;
+}
+
+// Three-buffer form: result written to V (may alias U); bufA, bufB scratch.
+__device__ __forceinline__ void lds_midchain(const float2* U, float2* V, float2* bufA, float2* bufB, int R, int M,
+                                             int logM, int nt, int mode, float scale, const Twiddles& tw) {
+  const int n = R * M;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) bufA[i] = U[i];
+  __syncthreads();
+  float2* res = lds_midchain2(bufA, bufB, R, M, logM, nt, mode, scale, tw);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) V[i] = res[i];
+  __syncthreads();
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// 256-point transforms in registers (the paper's L = 512: 256 packed slots), four-step form
+// 256 = 16 x 16: index n = 16 n1 + n2, k = k1 + 16 k2,
+//   X[k1 + 16 k2] = sum_{n2} W16^{n2 k2} W256^{n2 k1} sum_{n1} x[16 n1 + n2] W16^{n1 k1}.
+// A thread owns one n2 (pass A) or one k1 (pass B) and holds 16 values.
+
+// exp(-2 pi i m / 16), m < 16
+__device__ __forceinline__ float2 w16(int m) {
+  constexpr float C[16] = {1.0f,                  0.92387953251128674f,  0.70710678118654752f,  0.38268343236508977f,
+                           0.0f,                 -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                           -1.0f,                -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                           0.0f,                  0.38268343236508977f,  0.70710678118654752f,  0.92387953251128674f};
+  return make_float2(C[m & 15], -C[(m + 12) & 15]);  // (cos, -sin)
+}
+
+// in-register radix-4 DFT of (x0, x1, x2, x3); DIR < 0 forward, DIR > 0 inverse
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  const float2 a0 = cadd(x0, x2), a1 = csub(x0, x2), a2 = cadd(x1, x3);
+  const float2 d = csub(x1, x3);
+  const float2 a3 = DIR < 0 ? make_float2(d.y, -d.x) : make_float2(-d.y, d.x);
+  x0 = cadd(a0, a2);
+  x1 = cadd(a1, a3);
+  x2 = csub(a0, a2);
+  x3 = csub(a1, a3);
+}
+
+// in-register 16-point DFT, natural order in and out (v[k] = sum_n v[n] W16^{DIR nk})
+template <int DIR>
+__device__ __forceinline__ void dft16(float2 (&v)[16]) {
+  // n = 4 m1 + m2: DFT over m1 for each m2
+#pragma unroll
+  for (int m2 = 0; m2 < 4; ++m2) dft4<DIR>(v[m2], v[4 + m2], v[8 + m2], v[12 + m2]);
+  // now v[4 k1 + m2] holds stage-1 output (k1, m2); twiddle W16^{m2 k1}
+#pragma unroll
+  for (int k1 = 1; k1 < 4; ++k1)
+#pragma unroll
+    for (int m2 = 1; m2 < 4; ++m2) {
+      float2 w = w16(m2 * k1);
+      if (DIR > 0) w.y = -w.y;
+      v[4 * k1 + m2] = cmul(v[4 * k1 + m2], w);
+    }
+  // DFT over m2 for each k1: output index k1 + 4 k2
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<DIR>(v[4 * k1 + 0], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+  // v[4 k1 + k2] holds X[k1 + 4 k2]: transpose the 4 x 4 index to natural order
+  float2 t[16];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) t[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+// Pass A of a 256-point transform for column n2 = c: v[n1] = x[16 n1 + c] in, out
+// v[k1] = W256^{DIR c k1} * sum_{n1} x[16 n1 + c] W16^{DIR n1 k1}.
+template <int DIR>
+__device__ __forceinline__ void fft256_passA(float2 (&v)[16], int c, const float2* twc) {
+  dft16<DIR>(v);
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) {
+    float2 w = twc[c * k1];
+    if (DIR > 0) w.y = -w.y;
+    v[k1] = cmul(v[k1], w);
+  }
+}
+
+// Mid-chain round trip for R rows with M = 256, 16 threads per row: thread tid handles row
+// r = tid / 16 and column c = tid % 16.  X (row stride ldx >= 256) holds the packed input
+// spectra and is overwritten; T (LDS, at least R*16*17 values) receives the packed output
+// spectra with row stride ldt (256 <= ldt <= 272).
+// Same arithmetic as lds_midchain2 (inverse real FFT, truncate to nt, D_t, zero-pad, forward
+// real FFT), with the complex transforms done as two 16-point passes in registers.
+__device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int mode, float scale,
+                                       const Twiddles& tw, int ldx = 256, int ldt = 256) {
+  constexpr int M = 256;
+  const int tid = threadIdx.x;
+  const int r = tid >> 4, c = tid & 15;
+  const bool act = r < R;
+  float2* Xr = X + r * ldx;
+  float2* Tr = T + r * (16 * 17);
+  float2 v[16];
+  // inverse real FFT: pre-step fused into pass A (element 16 n1 + c)
+  if (act) {
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = irfft_pre(Xr, 16 * n1 + c, M, tw.r);
+    fft256_passA<+1>(v, c, tw.c);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Tr[k1 * 17 + c] = v[k1];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) v[n2] = Tr[c * 17 + n2];
+    dft16<+1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) Xr[c + 16 * k2] = v[k2];  // z[n] = L (x[2n] + i x[2n+1])
+  }
+  __syncthreads();
+  // time step (truncate, D_t, scale) fused into pass A of the forward FFT
+  if (act) {
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) {
+      const int n = 16 * n1 + c;
+      const float2 z = Xr[n];
+      const int m0 = 2 * n, m1 = m0 + 1;
+      float a = 0.f, b = 0.f;
+      if (mode == MID_BACKWARD) {
+        const float xm1 = n > 0 ? Xr[n - 1].y : 0.f;
+        a = m0 < nt ? z.x - xm1 : 0.f;
+        b = m1 < nt ? z.y - z.x : 0.f;
+      } else if (mode == MID_BACKWARD_T) {
+        const float xp2 = (n + 1 < M && m1 + 1 < nt) ? Xr[n + 1].x : 0.f;
+        a = m0 < nt ? z.x - (m1 < nt ? z.y : 0.f) : 0.f;
+        b = m1 < nt ? z.y - xp2 : 0.f;
+      } else {
+        a = m0 < nt ? z.x : 0.f;
+        b = m1 < nt ? z.y : 0.f;
+      }
+      v[n1] = make_float2(a * scale, b * scale);
+    }
+    fft256_passA<-1>(v, c, tw.c);
+  }
+  __syncthreads();  // all reads of X done before pass B below overwrites it
+  if (act) {
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Tr[k1 * 17 + c] = v[k1];
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) v[n2] = Tr[c * 17 + n2];
+    dft16<-1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) Xr[c + 16 * k2] = v[k2];
+  }
+  __syncthreads();
+  // post-step of the forward real FFT, written row-major to T
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int k = c + 16 * j;
+      T[r * ldt + k] = rfft_post(Xr, k, M, tw.r);
+    }
   }
   __syncthreads();
 }

@@ -9,6 +9,8 @@
 // run of M complex values.
 #include <math.h>
 
+#include <algorithm>
+
 #include "s2w_device.h"
 #include "s2w_internal.h"
 
@@ -37,6 +39,7 @@ __global__ __launch_bounds__(256) void k_rfft_rows(const float* __restrict__ in,
   extern __shared__ float2 smem[];
   float2* A = smem;
   float2* Bf = smem + R * M;
+  const Twiddles tw = lds_twiddles(smem + 2 * R * M, M);
   const int64_t row0 = (int64_t)blockIdx.x * R;
   for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
     const int r = i >> logM, p = i & (M - 1);
@@ -55,14 +58,14 @@ __global__ __launch_bounds__(256) void k_rfft_rows(const float* __restrict__ in,
     A[i] = v;
   }
   __syncthreads();
-  float2* Z = lds_cfft(A, Bf, R, M, logM, -1);
+  float2* Z = lds_cfft(A, Bf, R, M, logM, -1, tw.c);
   for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
     const int r = i % R, k = i / R;
     const int64_t row = row0 + r;
     if (row < nrows) {
       const int64_t o = row / ninner_pad;
       const int inn = (int)(row - o * ninner_pad);
-      out[o * out_outer + inn * out_inner + k * out_slot] = rfft_post(Z + r * M, k, M);
+      out[o * out_outer + inn * out_inner + k * out_slot] = rfft_post(Z + r * M, k, M, tw.r);
     }
   }
 }
@@ -74,7 +77,7 @@ hipError_t launch_rfft_rows(const float* in, int64_t nouter, int ninner, int nin
   const int64_t nrows = nouter * ninner_pad;
   if (nrows == 0) return hipSuccess;
   const int64_t nblk = (nrows + R - 1) / R;
-  hipLaunchKernelGGL(k_rfft_rows, dim3((unsigned)nblk), dim3(256), 2 * R * g.M * sizeof(float2), st, in, nrows,
+  hipLaunchKernelGGL(k_rfft_rows, dim3((unsigned)nblk), dim3(256), (2 * R + 2) * g.M * sizeof(float2), st, in, nrows,
                      ninner, ninner_pad, out, out_outer, out_inner, out_slot, g.nt, g.M, g.logM, R, scale);
   return hipGetLastError();
 }
@@ -87,6 +90,7 @@ __global__ __launch_bounds__(256) void k_irfft_rows(const float2* __restrict__ i
   float2* X = smem;
   float2* A = smem + R * M;
   float2* Bf = smem + 2 * R * M;
+  const Twiddles tw = lds_twiddles(smem + 3 * R * M, M);
   const int64_t row0 = (int64_t)blockIdx.x * R;
   for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
     const int r = i % R, k = i / R;
@@ -96,10 +100,10 @@ __global__ __launch_bounds__(256) void k_irfft_rows(const float2* __restrict__ i
   __syncthreads();
   for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
     const int r = i >> logM, k = i & (M - 1);
-    A[i] = irfft_pre(X + r * M, k, M);
+    A[i] = irfft_pre(X + r * M, k, M, tw.r);
   }
   __syncthreads();
-  float2* z = lds_cfft(A, Bf, R, M, logM, +1);
+  float2* z = lds_cfft(A, Bf, R, M, logM, +1, tw.c);
   for (int i = threadIdx.x; i < R * nt; i += blockDim.x) {
     const int r = i / nt, m = i - r * nt;
     const int64_t row = row0 + r;
@@ -112,7 +116,7 @@ hipError_t launch_irfft_rows(const float2* in, int64_t nrows, int64_t in_row, in
   if (nrows == 0) return hipSuccess;
   const int R = rows_per_block(g.M);
   const int64_t nblk = (nrows + R - 1) / R;
-  hipLaunchKernelGGL(k_irfft_rows, dim3((unsigned)nblk), dim3(256), 3 * R * g.M * sizeof(float2), st, in, nrows,
+  hipLaunchKernelGGL(k_irfft_rows, dim3((unsigned)nblk), dim3(256), (3 * R + 2) * g.M * sizeof(float2), st, in, nrows,
                      in_row, in_slot, out, out_row, g.nt, g.M, g.logM, R, scale);
   return hipGetLastError();
 }
@@ -224,8 +228,8 @@ __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict_
   extern __shared__ float2 smem[];
   float2* U = smem;
   float2* BA = U + T * M;
-  float2* BB = BA + T * M;
-  v4f* red = reinterpret_cast<v4f*>(BB + T * M);
+  v4f* red = reinterpret_cast<v4f*>(BA + T * M);
+  const Twiddles tw = lds_twiddles(reinterpret_cast<float2*>(red + 256 * T), M);
   const int tid = threadIdx.x;
   const int NP = M >> 1, OG = 256 / NP;
   const int p = tid % NP, og = tid / NP;
@@ -239,10 +243,10 @@ __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict_
   for (int g0 = r0; g0 < r1; g0 += T) {
     const int tr = min(T, r1 - g0);
     contract_cols<T, false>(Gh, Sh, g0, tr, nsub, nsp, M, U, red);
-    lds_midchain(U, U, BA, BB, T, M, logM, nt, mode, mscale);
+    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw);
     const v4f* fb = Fh + (int64_t)g0 * frow + p;
     for (int t = 0; t < tr; ++t) {
-      const float2 va = U[t * M + 2 * p], vb = U[t * M + 2 * p + 1];
+      const float2 va = Vt[t * M + 2 * p], vb = Vt[t * M + 2 * p + 1];
       const Coef ka = make_coef(va, dc, false), kb = make_coef(vb, false, false);
       const v4f* ft = fb + t * frow;
       // observer rows past the store repeat its last (zero-padding or valid) row; their
@@ -269,7 +273,9 @@ static inline int next_pow2(int v) {
   return p;
 }
 
-static inline size_t tile_lds(int T, int M) { return 3 * (size_t)T * M * sizeof(float2) + 256 * (size_t)T * 16; }
+static inline size_t tile_lds(int T, int M) {
+  return 2 * (size_t)T * M * sizeof(float2) + 256 * (size_t)T * 16 + 2 * (size_t)M * sizeof(float2);
+}
 
 int fused_forward_opt(const Geometry& g) {
   const int OG = 256 / (g.M / 2);
@@ -357,15 +363,15 @@ __global__ __launch_bounds__(256) void k_rows_mid(const v4f* __restrict__ X, con
   extern __shared__ float2 smem[];
   float2* U = smem;
   float2* BA = U + T * M;
-  float2* BB = BA + T * M;
-  v4f* red = reinterpret_cast<v4f*>(BB + T * M);
+  v4f* red = reinterpret_cast<v4f*>(BA + T * M);
+  const Twiddles tw = lds_twiddles(reinterpret_cast<float2*>(red + 256 * T), M);
   const int wg = blockIdx.x, nwg = gridDim.x;
   const int r0 = (int)((int64_t)ngrid * wg / nwg), r1 = (int)((int64_t)ngrid * (wg + 1) / nwg);
   for (int g0 = r0; g0 < r1; g0 += T) {
     const int tr = min(T, r1 - g0);
     contract_cols<T, CONJ>(X, Y, g0, tr, nc, ncp, M, U, red);
-    lds_midchain(U, U, BA, BB, T, M, logM, nt, mode, mscale);
-    for (int i = threadIdx.x; i < tr * M; i += blockDim.x) Out[(int64_t)g0 * M + i] = U[i];
+    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw);
+    for (int i = threadIdx.x; i < tr * M; i += blockDim.x) Out[(int64_t)g0 * M + i] = Vt[i];
     __syncthreads();
   }
 }
@@ -460,50 +466,154 @@ hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part
 }
 
 // ---------------------------------------------------------------------------------------------
-// Batched mid-chain round trip, in place on U[l][g][b] (complex, b < bp): for grid row g and
-// ruptures b0 .. b0+R-1, gather all M slots, run inverse FFT -> truncate -> D_t -> zero-pad ->
-// FFT in LDS (Alg. 1 line 3; Alg. 2 steps 4-5 and 1-2), multiply by the acoustic store's
-// scale sF[g][l] (if given) and write back.
-template <int R>
-__global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
-                                                   int B, int bp, int M, int logM, int nt, int mode, float mscale) {
-  extern __shared__ float2 smem[];
-  float2* X = smem;
-  float2* BA = X + R * M;
-  float2* BB = BA + R * M;
-  const int nbb = (B + R - 1) / R;
-  const int g = blockIdx.x / nbb;
-  const int b0 = (blockIdx.x % nbb) * R;
-  for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
-    const int l = i / R, r = i % R;
-    const int b = b0 + r;
-    X[r * M + l] = b < B ? U[((int64_t)l * ngrid + g) * bp + b] : make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  lds_midchain(X, X, BA, BB, R, M, logM, nt, mode, mscale);
-  for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
-    const int l = i / R, r = i % R;
-    const int b = b0 + r;
-    if (b < B) {
-      float2 v = X[r * M + l];
-      if (sF) {
-        const float f = sF[(int64_t)g * M + l];
-        v.x *= f;
-        v.y *= f;
-      }
-      U[((int64_t)l * ngrid + g) * bp + b] = v;
-    }
+// Batched mid-chain round trip on U[g][l][b] (complex, b < bp): for grid row g and ruptures
+// b0 .. b0+R-1, gather all M slots, run inverse FFT -> truncate -> D_t -> zero-pad -> FFT in
+// LDS (Alg. 1 line 3; Alg. 2 steps 4-5 and 1-2), multiply by the acoustic store's scale
+// sF[g][l] and write the result back in place: as complex64 (PACK = 0), or as bfloat16
+// high/low terms of the real and imaginary parts packed in two 32-bit words (PACK = 1), the
+// acoustic GEMM's operand format.
+__device__ __forceinline__ uint32_t bf16_rne_bits(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+template <int PACK>
+__device__ __forceinline__ void store_v(float2* dst, float2 v, float f) {
+  v.x *= f;
+  v.y *= f;
+  if (PACK) {
+    const uint32_t hr = bf16_rne_bits(v.x), hi = bf16_rne_bits(v.y);
+    const uint32_t lr = bf16_rne_bits(v.x - __uint_as_float(hr << 16));
+    const uint32_t li = bf16_rne_bits(v.y - __uint_as_float(hi << 16));
+    *reinterpret_cast<uint2*>(dst) = make_uint2(hr | (hi << 16), lr | (li << 16));
+  } else {
+    *dst = v;
   }
 }
 
-hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, const Geometry& g,
-                            hipStream_t st) {
-  constexpr int R = 8;
+// General M: rows staged through a padded transposition buffer, generic LDS transforms.
+template <int R, int PACK>
+__global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
+                                                   int B, int bp, int M, int logM, int nt, int mode, float mscale) {
+  extern __shared__ float2 smem[];
+  // two buffers of M*(R+1) values: each serves as the row-major FFT buffer [R][M] and, while
+  // free, as the padded transposition buffer [M][R+1] (conflict-free in both directions)
+  const int BUF = M * (R + 1);
+  float2* X = smem;
+  float2* Y = X + BUF;
+  const Twiddles tw = lds_twiddles(Y + BUF, M);
+  const int nbb = (B + R - 1) / R;
+  const int64_t units = (int64_t)ngrid * nbb;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int g = (int)(u / nbb);
+    const int b0 = (int)(u % nbb) * R;
+    const float2* src = U + (int64_t)g * M * bp + b0;
+    for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
+      const int l = i / R, r = i % R;
+      Y[l * (R + 1) + r] = b0 + r < B ? src[(int64_t)l * bp + r] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
+      const int r = i >> logM, l = i & (M - 1);
+      X[i] = Y[l * (R + 1) + r];
+    }
+    __syncthreads();
+    const float2* V = lds_midchain2(X, Y, R, M, logM, nt, mode, mscale, tw);
+    float2* Tp = (V == X) ? Y : X;
+    for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
+      const int r = i >> logM, l = i & (M - 1);
+      Tp[l * (R + 1) + r] = V[i];
+    }
+    __syncthreads();
+    float2* dst = U + (int64_t)g * M * bp + b0;
+    for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
+      const int l = i / R, r = i % R;
+      if (b0 + r < B) store_v<PACK>(dst + (int64_t)l * bp + r, Tp[l * (R + 1) + r], sF ? sF[(int64_t)g * M + l] : 1.f);
+    }
+    __syncthreads();
+  }
+}
+
+// M = 256: 16 ruptures of one grid row per unit, the next unit's rows prefetched into
+// registers while the current one is transformed; rows kept with a padded stride (257) so
+// that the strided LDS writes and reads of the gather and scatter are conflict-free.
+template <int PACK>
+__global__ __launch_bounds__(256) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
+                                                      int B, int bp, int nt, int mode, float mscale) {
+  constexpr int M = 256, R = 16, LD = 257;
+  __shared__ float2 X[R * LD];
+  __shared__ float2 T[R * 16 * 17];
+  __shared__ float2 twb[2 * M];
+  const Twiddles tw = lds_twiddles(twb, M);
+  const int tid = threadIdx.x;
+  const int r = tid & 15, lq = tid >> 4;  // gather/scatter: rupture r, slots lq + 16 k
+  const int nbb = (B + R - 1) / R;
+  const int64_t units = (int64_t)ngrid * nbb;
+  float2 pre[16];
+  float fs[16];
+  auto fetch = [&](int64_t u) {
+    const int g = (int)(u / nbb);
+    const int b = (int)(u % nbb) * R + r;
+    const float2* src = U + (int64_t)g * M * bp + b;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int l = lq + 16 * k;
+      pre[k] = b < B ? src[(int64_t)l * bp] : make_float2(0.f, 0.f);
+      fs[k] = sF ? sF[(int64_t)g * M + l] : 1.f;
+    }
+  };
+  int64_t u = blockIdx.x;
+  if (u < units) fetch(u);
+  for (; u < units; u += gridDim.x) {
+    const int g = (int)(u / nbb);
+    const int b = (int)(u % nbb) * R + r;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) X[r * LD + lq + 16 * k] = pre[k];
+    float f[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) f[k] = fs[k];
+    __syncthreads();
+    if (u + gridDim.x < units) fetch(u + gridDim.x);
+    mid256(X, T, R, nt, mode, mscale, tw, LD, LD);
+    float2* dst = U + (int64_t)g * M * bp + b;
+    if (b < B) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int l = lq + 16 * k;
+        store_v<PACK>(dst + (int64_t)l * bp, T[r * LD + l], f[k]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
+                            const Geometry& g, hipStream_t st) {
+  constexpr int R = 16;
   const int mode = g.diff ? (adjoint ? MID_BACKWARD_T : MID_BACKWARD) : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
-  const int64_t nblk = (int64_t)g.ngrid * ((B + R - 1) / R);
-  hipLaunchKernelGGL(k_mid_batch<R>, dim3((unsigned)nblk), dim3(256), 3 * (size_t)R * g.M * sizeof(float2), st, U, sF,
-                     g.ngrid, B, bp, g.M, g.logM, g.nt, mode, mscale);
+  const int64_t units = (int64_t)g.ngrid * ((B + R - 1) / R);
+  const int64_t nblk = std::min<int64_t>(units, 256 * 8);
+  if (g.M == 256) {
+    const int64_t units256 = (int64_t)g.ngrid * ((B + 15) / 16);
+    const int64_t nb256 = std::min<int64_t>(units256, 256 * 8);
+    if (pack_bf16)
+      hipLaunchKernelGGL((k_mid_batch256<1>), dim3((unsigned)nb256), dim3(256), 0, st, U, sF, g.ngrid, B, bp, g.nt, mode,
+                         mscale);
+    else
+      hipLaunchKernelGGL((k_mid_batch256<0>), dim3((unsigned)nb256), dim3(256), 0, st, U, sF, g.ngrid, B, bp, g.nt, mode,
+                         mscale);
+    return hipGetLastError();
+  }
+  const size_t lds = (2 * (size_t)g.M * (R + 1) + 2 * (size_t)g.M) * sizeof(float2);
+  if (pack_bf16)
+    hipLaunchKernelGGL((k_mid_batch<R, 1>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M,
+                       g.logM, g.nt, mode, mscale);
+  else
+    hipLaunchKernelGGL((k_mid_batch<R, 0>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M,
+                       g.logM, g.nt, mode, mscale);
   return hipGetLastError();
 }
 

@@ -68,12 +68,13 @@ hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, f
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
                          hipStream_t st);
-hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, const Geometry& g,
-                            hipStream_t st);
+hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
+                            const Geometry& g, hipStream_t st);
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
                             hipStream_t st);
-hipError_t launch_gemm_f(int ht, int hterms, const uint4* Fq, const float2* V, const float* tau_up, float* part,
-                         int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st);
+hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,
+                         float* part, int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits,
+                         hipStream_t st);
 hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs, int B, int bp, const float* tau_down,
                         float2* yh, hipStream_t st);
 hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st);

@@ -225,7 +225,7 @@ hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, f
 
 // ---------------------------------------------------------------------------------------------
 // Elastic GEMM per bin (eq. 1, Alg. 2 step 3, batched):
-//   U[l][g][b] = sG[g][l] * sig_down[l][b] * sum_j Gq[g][l][j] (x) Sq[l][j][b]
+//   U[g][l][b] = sG[g][l] * sig_down[l][b] * sum_j Gq[g][l][j] (x) Sq[l][j][b]
 // Persistent and XCD-aware: workgroup w runs on XCD w % 8 (round-robin dispatch) and takes the
 // tiles of bins l = w % 8 (mod 8), so the 32 workgroups of an XCD share one bin's activation
 // in that XCD's L2.  Tile: MG = MW*WR grid rows x NG = NW*WC output columns; wave (wr, wc)
@@ -297,7 +297,131 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
           const int n = 16 * (cb0 + b) + (lane & 15);
           const int rup = n >> 1;
           if (cb0 + b < ncb && rup < B)
-            U[(((int64_t)l * ngrid + g) * bp + rup) * 2 + (n & 1)] =
+            U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
+                acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+        }
+      }
+  }
+}
+
+// Elastic GEMM, LDS-staged variant for wide batches.  Eight waves (2 row groups x 4 column
+// groups); workgroup tile 2*MW grid rows x 4*NW output columns.  Per K step (16 subfaults)
+// the workgroup copies the operator tile (2*MW rows x 64 bytes) and the activation tile
+// (4*NW/16 column blocks x H fragments) from global memory into one of two LDS buffers
+// while the matrix cores consume the other; each operator and activation fragment is read
+// from HBM/L2 once per workgroup and shared by four (resp. two) waves through LDS.
+// LDS slot of 16-byte chunk c (0..3) of operator-tile row r: the chunk index is XORed with
+// bits 1-2 of the row so that the eight rows read together by a quarter wave fall into
+// eight distinct 16-byte bank groups.
+__device__ __forceinline__ int swz(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
+
+template <int HT, int H, int MW, int NW>
+__global__ __launch_bounds__(512, 1) void k_gemm_g2(const uint4* __restrict__ Gq, const float* __restrict__ sG,
+                                                    const uint4* __restrict__ Bop, const float* __restrict__ sig_down,
+                                                    float* __restrict__ U, int ngrid, int M, int nks, int ncb, int B,
+                                                    int bp, int nrb, int nct) {
+  constexpr int MF = MW / 16, NF = NW / 16;
+  constexpr int RT = 2 * MW;                 // rows per tile
+  constexpr int CBT = 4 * NF;                // column blocks per tile
+  constexpr int A_U4 = RT * 4;               // uint4 of the operator tile per K step
+  constexpr int B_U4 = CBT * H * 64;         // uint4 of the activation tile per K step
+  constexpr int T_U4 = A_U4 + B_U4;
+  constexpr int PER_T = (T_U4 + 511) / 512;  // uint4 each thread copies per K step
+  __shared__ uint4 lds[2][T_U4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int nwg = gridDim.x, w = blockIdx.x;
+  const int nx = 8 < M ? 8 : M;
+  const int x = w % nx, wi = w / nx, nwx = (nwg - x + nx - 1) / nx;
+  const int slots_x = (M - x + nx - 1) / nx;
+  const int64_t per_slot = (int64_t)nrb * nct;
+  const int64_t items = (int64_t)slots_x * per_slot;
+  const int64_t row_u4 = (int64_t)nks * 4;
+  for (int64_t it = wi; it < items; it += nwx) {
+    const int l = x + nx * (int)(it / per_slot);
+    const int64_t rem = it % per_slot;
+    const int rb = (int)(rem / nct), ct = (int)(rem % nct);
+    const int g0 = rb * RT;
+    const int cbt0 = ct * CBT;
+    // global sources of this thread's copy slots: operator rows (clamped) or activation blocks
+    const uint4* src[PER_T];
+    int64_t sstep[PER_T];
+    bool valid[PER_T];
+    int dst[PER_T];
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k) {
+      const int i = tid + 512 * k;
+      valid[k] = i < T_U4;
+      dst[k] = i;
+      if (i < A_U4) {
+        const int r = i >> 2, c = i & 3;
+        const int g = min(g0 + r, ngrid - 1);
+        src[k] = Gq + ((int64_t)g * M + l) * row_u4 + c;
+        sstep[k] = 4;
+        dst[k] = swz(r, c);
+      } else {
+        const int j = min(i - A_U4, B_U4 - 1);
+        const int cbl = j / (H * 64), rest = j % (H * 64);
+        const int cb = min(cbt0 + cbl, ncb - 1);
+        src[k] = Bop + ((int64_t)l * nks * ncb + cb) * H * 64 + rest;
+        sstep[k] = (int64_t)ncb * H * 64;
+      }
+    }
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint4 stage[PER_T];
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+      if (valid[k]) stage[k] = ntload(src[k]);
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+      if (valid[k]) lds[0][dst[k]] = stage[k];
+    __syncthreads();
+    for (int ks = 0; ks < nks; ++ks) {
+      const int cur = ks & 1;
+      const bool more = ks + 1 < nks;
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+          if (valid[k]) stage[k] = ntload(src[k] + (int64_t)(ks + 1) * sstep[k]);
+      }
+      const uint4* la = &lds[cur][0];
+      const uint4* lb = &lds[cur][A_U4];
+      uint4 av[MF];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) av[a] = la[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < NF; ++b)
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+          const uint4 bv = lb[((wc * NF + b) * H + h) * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bv, acc[a][b]);
+        }
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+          if (valid[k]) lds[cur ^ 1][dst[k]] = stage[k];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + wr * MW + 16 * a + 4 * (lane >> 4) + r;
+        if (g >= ngrid) continue;
+        const float sg = sG[(int64_t)g * M + l];
+#pragma unroll
+        for (int b = 0; b < NF; ++b) {
+          const int cb = cbt0 + wc * NF + b;
+          const int n = 16 * cb + (lane & 15);
+          const int rup = n >> 1;
+          if (cb < ncb && rup < B)
+            U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
                 acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
         }
       }
@@ -319,6 +443,20 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
     case 1: S2W_GG(64, 64, 2, 2); break;   // 128 x 128
     case 2: S2W_GG(32, 128, 1, 4); break;  // 32 x 512
     case 3: S2W_GG(64, 128, 1, 4); break;  // 64 x 512
+    case 5:
+    case 6: {
+      // LDS-staged eight-wave tiles: 5 = 256 rows x 256 columns, 6 = 128 rows x 512 columns
+      const int MW = cfg == 5 ? 128 : 64, NW = cfg == 5 ? 64 : 128;
+      const int nrb = (ngrid + 2 * MW - 1) / (2 * MW);
+      const int nct = (ncb + 4 * (NW / 16) - 1) / (4 * (NW / 16));
+      if (cfg == 5)
+        hipLaunchKernelGGL((k_gemm_g2<HT, H, 128, 64>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
+                           nks, ncb, B, bp, nrb, nct);
+      else
+        hipLaunchKernelGGL((k_gemm_g2<HT, H, 64, 128>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
+                           nks, ncb, B, bp, nrb, nct);
+      break;
+    }
     default: return hipErrorInvalidValue;
   }
 #undef S2W_GG
@@ -337,11 +475,13 @@ hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const flo
 
 // ---------------------------------------------------------------------------------------------
 // Acoustic GEMM per bin (eq. 2, Alg. 2 step 3, batched), split over grid rows:
-//   part[split][l][o][n] = sum_{g in split} Fq[l][o][g] (x) V[l][g][b]   (n = 2b + re/im)
-// V (float32, [l][g][bp] complex, already multiplied by sF[g][l] and by tau_up[l][b]) is
-// converted to half precision (H terms) in registers.  Workgroup (l, split, column tile):
-// rows = all observers (nof fragments of 16), NW output columns per wave.
-template <int HT, int H, int NF, int MF>
+//   part[split][l][o][n] = sum_{g in split} Fq[l][o][g] (x) V[g][l][b]   (n = 2b + re/im)
+// V holds the mid-chain output (already multiplied by sF[g][l]), either as complex64, which is
+// scaled by tau_up[l][b] and split into H half-precision terms in registers, or (PACKED) as
+// bfloat16 high/low terms of the real and imaginary parts, from which the fragment entries
+// follow by sign flips and half swaps.  Workgroup (l, split, column tile): rows = all
+// observers (MF fragments of 16), NF column blocks per wave, four waves side by side.
+template <int HT, int H, int NF, int MF, bool PACKED>
 __global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, const float2* __restrict__ V,
                                                 const float* __restrict__ tau_up, float* __restrict__ part, int ngrid,
                                                 int ngq, int M, int noq, int B, int bp, int ncb) {
@@ -356,7 +496,6 @@ __global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, co
   for (int a = 0; a < MF; ++a)
 #pragma unroll
     for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // B fragment column of this lane, per column block
   int rup[NF], cim[NF];
   float tu[NF];
 #pragma unroll
@@ -368,7 +507,8 @@ __global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, co
   }
   const int64_t frow = (int64_t)ngq / 4;  // uint4 per (l, o) row of Fq
   const uint4* fa = Fq + (int64_t)l * noq * frow + (lane >> 4);
-  const float2* vb = V + (int64_t)l * ngrid * bp;
+  const int64_t vrow = (int64_t)M * bp;   // complex values per grid row of V
+  const float2* vb = V + (int64_t)l * bp;
   for (int ks = kst0; ks < kst1; ++ks) {
     uint4 av[MF];
 #pragma unroll
@@ -379,22 +519,43 @@ __global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, co
       uint32_t hi[4], lo[4];
 #pragma unroll
       for (int e2 = 0; e2 < 4; ++e2) {
-        const int g = gb + e2;
-        float2 v = g < ngrid ? vb[(int64_t)g * bp + rup[b]] : make_float2(0.f, 0.f);
-        v.x *= tu[b];
-        v.y *= tu[b];
-        float v0, v1;
-        if (dc) {
-          v0 = cim[b] == 0 ? v.x : 0.f;
-          v1 = cim[b] == 0 ? 0.f : v.y;
+        const int g = min(gb + e2, ngrid - 1);
+        const bool gok = gb + e2 < ngrid;
+        if (PACKED) {
+          // words: (re_hi | im_hi << 16), (re_lo | im_lo << 16); column re: (re, -im), column im: (im, re)
+          uint2 w = reinterpret_cast<const uint2*>(vb)[(int64_t)g * vrow + rup[b]];
+          if (!gok) w = make_uint2(0u, 0u);
+          uint32_t wh = w.x, wl = w.y;
+          if (dc) {
+            wh = cim[b] == 0 ? (wh & 0xffffu) : (wh & 0xffff0000u);
+            wl = cim[b] == 0 ? (wl & 0xffffu) : (wl & 0xffff0000u);
+          } else if (cim[b] == 0) {
+            wh ^= 0x80000000u;
+            wl ^= 0x80000000u;
+          } else {
+            wh = (wh >> 16) | (wh << 16);
+            wl = (wl >> 16) | (wl << 16);
+          }
+          hi[e2] = wh;
+          lo[e2] = wl;
         } else {
-          v0 = cim[b] == 0 ? v.x : v.y;
-          v1 = cim[b] == 0 ? -v.y : v.x;
+          float2 v = gok ? vb[(int64_t)g * vrow + rup[b]] : make_float2(0.f, 0.f);
+          v.x *= tu[b];
+          v.y *= tu[b];
+          float v0, v1;
+          if (dc) {
+            v0 = cim[b] == 0 ? v.x : 0.f;
+            v1 = cim[b] == 0 ? 0.f : v.y;
+          } else {
+            v0 = cim[b] == 0 ? v.x : v.y;
+            v1 = cim[b] == 0 ? -v.y : v.x;
+          }
+          const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
+          hi[e2] = h0 | (h1 << 16);
+          if (H == 2)
+            lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) |
+                     (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
         }
-        const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
-        hi[e2] = h0 | (h1 << 16);
-        if (H == 2)
-          lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) | (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
       }
       const uint4 bh = make_uint4(hi[0], hi[1], hi[2], hi[3]);
 #pragma unroll
@@ -421,35 +582,48 @@ __global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, co
     }
 }
 
-hipError_t launch_gemm_f(int ht, int hterms, const uint4* Fq, const float2* V, const float* tau_up, float* part,
-                         int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st) {
-  constexpr int NF = 2;  // column blocks per wave
+template <int HT, int H, int NF, bool PK>
+static hipError_t gemm_f_nf(const uint4* Fq, const float2* V, const float* tau_up, float* part, int ngrid, int ngq,
+                            int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st) {
   dim3 grid(M, splits, (ncb + 4 * NF - 1) / (4 * NF));
   const int mf = noq / 16;
-#define S2W_GF(HT_, H_, MF_)                                                                                     \
-  hipLaunchKernelGGL((k_gemm_f<HT_, H_, NF, MF_>), grid, dim3(256), 0, st, Fq, V, tau_up, part, ngrid, ngq, M, noq, \
+#define S2W_GF(MF_)                                                                                               \
+  hipLaunchKernelGGL((k_gemm_f<HT, H, NF, MF_, PK>), grid, dim3(256), 0, st, Fq, V, tau_up, part, ngrid, ngq, M, noq, \
                      B, bp, ncb)
-#define S2W_GF_M(HT_, H_)                   \
-  do {                                      \
-    if (mf == 1) S2W_GF(HT_, H_, 1);        \
-    else if (mf == 2) S2W_GF(HT_, H_, 2);   \
-    else if (mf == 4) S2W_GF(HT_, H_, 4);   \
-    else if (mf == 8) S2W_GF(HT_, H_, 8);   \
-    else if (mf == 16) S2W_GF(HT_, H_, 16); \
-    else return hipErrorInvalidValue;       \
-  } while (0)
-  if (ht == 1) {
-    if (hterms == 2) S2W_GF_M(1, 2); else S2W_GF_M(1, 1);
-  } else {
-    if (hterms == 2) S2W_GF_M(2, 2); else S2W_GF_M(2, 1);
-  }
-#undef S2W_GF_M
+  if (mf == 1) S2W_GF(1);
+  else if (mf == 2) S2W_GF(2);
+  else if (mf == 4) S2W_GF(4);
+  else if (mf == 8 && NF <= 2) S2W_GF(8);
+  else if (mf == 16 && NF <= 2) S2W_GF(16);
+  else return hipErrorInvalidValue;
 #undef S2W_GF
   return hipGetLastError();
 }
 
+template <int HT, int H, bool PK>
+static hipError_t gemm_f_h(const uint4* Fq, const float2* V, const float* tau_up, float* part, int ngrid, int ngq,
+                           int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st) {
+  // wide batches: each wave covers eight column blocks so one workgroup spans 512 columns
+  if (ncb > 8 && noq <= 64) return gemm_f_nf<HT, H, 8, PK>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
+  return gemm_f_nf<HT, H, 2, PK>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
+}
+
+hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,
+                         float* part, int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits,
+                         hipStream_t st) {
+  if (packed) {
+    if (ht != 1 || hterms != 2) return hipErrorInvalidValue;
+    return gemm_f_h<1, 2, true>(Fq, V, nullptr, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
+  }
+  if (ht == 1)
+    return hterms == 2 ? gemm_f_h<1, 2, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st)
+                       : gemm_f_h<1, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
+  return hterms == 2 ? gemm_f_h<2, 2, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st)
+                     : gemm_f_h<2, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
+}
+
 // Column scales of the acoustic GEMM's activation (float16 operands only): for each (l, b),
-// a power of two mapping max_g |V[l][g][b]| into [2^14, 2^15).
+// a power of two mapping max_g |V[g][l][b]| into [2^14, 2^15).
 __global__ __launch_bounds__(256) void k_col_scale(const float2* __restrict__ V, int ngrid, int M, int B, int bp,
                                                    float* __restrict__ tau_up, float* __restrict__ tau_down) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -457,9 +631,9 @@ __global__ __launch_bounds__(256) void k_col_scale(const float2* __restrict__ V,
   const int l = (int)(i / bp), b = (int)(i - (int64_t)l * bp);
   float mx = 0.f;
   if (b < B) {
-    const float2* v = V + (int64_t)l * ngrid * bp + b;
+    const float2* v = V + (int64_t)l * bp + b;
     for (int g = 0; g < ngrid; ++g) {
-      const float2 x = v[(int64_t)g * bp];
+      const float2 x = v[(int64_t)g * M * bp];
       mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)));
     }
   }
