@@ -34,7 +34,7 @@ class Desc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_cols", ctypes.c_int32),
                 ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32), ("gemm_cfg", ctypes.c_int32),
-                ("fgemm_splits", ctypes.c_int32)]
+                ("fgemm_splits", ctypes.c_int32), ("fgemm_lds", ctypes.c_int32)]
 
 
 EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_create", "s2w_plan_destroy",

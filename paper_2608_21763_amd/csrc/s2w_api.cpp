@@ -268,6 +268,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.batch_path_min_b = 1 << 30;
   p->tune.gemm_cfg = -1;
   p->tune.fgemm_splits = 0;
+  p->tune.fgemm_lds = 1;
   p->row_set.assign((size_t)d.ngrid, 0);
   p->rows_missing = d.ngrid;
   {
@@ -355,9 +356,10 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
   }
   if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
   if (t->gemm_cfg) {
-    if (t->gemm_cfg < -1 || t->gemm_cfg > 6) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    if (t->gemm_cfg < -1 || t->gemm_cfg > 9) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
+  if (t->fgemm_lds) n.fgemm_lds = t->fgemm_lds > 0 ? 1 : 0;
   if (t->fgemm_splits) {
     if (t->fgemm_splits < 0 || t->fgemm_splits > 16) return fail(p, S2W_EINVAL, "tuning: fgemm_splits");
     n.fgemm_splits = t->fgemm_splits;
@@ -484,30 +486,47 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
   if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 5);
-  const int zt = (ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8;
+  // acoustic GEMM: the LDS-staged kernel serves the packed bfloat16 activation when its tile fits
+  const bool packed = h.ht_f == 1 && h.hterms_f == 2;
+  const bool fstaged = packed && p->tune.fgemm_lds != 0 && gemm_f2_supported(h.noq, B);
+  const int zt = fstaged ? gemm_f2_col_tiles(B)
+                         : ((ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8);  // column tiles
   int splits = p->tune.fgemm_splits;
   if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
   splits = std::min(splits, h.splits_max);
   hipError_t e = launch_rfft_rows(s, B, g.nsub, h.nsq, S, 1, bp, (int64_t)h.nsq * bp, g, 1.0f, st);
-  if (e == hipSuccess)
-    e = launch_prep_act(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, ncb, Bop, st);
+  const bool compact = cfg >= 7;
+  if (e == hipSuccess) {
+    if (compact)
+      e = launch_prep_act_compact(h.ht_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (uint2*)Bop, st);
+    else
+      e = launch_prep_act(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, ncb, Bop, st);
+  }
   if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
   e = mark(p->ev_begin, st);
-  if (e == hipSuccess)
-    e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, p->ncu * p->tune.fused_wg_per_cu,
-                      g.ngrid, g.M, h.nks, ncb, B, bp, st);
+  if (e == hipSuccess) {
+    const int nwg = p->ncu * p->tune.fused_wg_per_cu;
+    if (compact)
+      e = launch_gemm_g3(h.ht_g, cfg, Gq, sG, (const uint2*)Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, B, bp,
+                         st);
+    else
+      e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, ncb, B,
+                        bp, st);
+  }
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
   const bool fscale = h.ht_f == 2;
-  const bool packed = h.ht_f == 1 && h.hterms_f == 2;
   e = launch_mid_batch(U, sF, B, bp, false, packed, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
     e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
   }
-  e = launch_gemm_f(h.ht_f, h.hterms_f, packed, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq, B,
-                    bp, ncb, splits, st);
+  if (fstaged)
+    e = launch_gemm_f2(Fq, (const uint2*)U, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, splits, st);
+  else
+    e = launch_gemm_f(h.ht_f, h.hterms_f, packed, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq,
+                      B, bp, ncb, splits, st);
   if (e == hipSuccess)
     e = launch_sum_f(part, splits, g.M, h.noq, g.nobs, B, bp, fscale ? tau_down : nullptr, yh, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");

@@ -68,6 +68,22 @@ hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, f
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
                          hipStream_t st);
+hipError_t launch_prep_act_compact(int ht, const float2* S, float* sig_up, float* sig_down, int M, int nsub, int nsq,
+                                   int B, int bp, int nks, uint2* Sc, hipStream_t st);
+hipError_t launch_gemm_g3(int ht, int cfg, const uint4* Gq, const float* sG, const uint2* Sc, const float* sig_down,
+                          float* U, int nwg, int ngrid, int M, int nks, int B, int bp, hipStream_t st);
+// LDS-staged acoustic GEMM (packed bfloat16 activation): supported observer paddings and the
+// number of rupture tiles it launches for a batch of B.
+inline bool gemm_f2_supported(int noq, int B) {
+  const int mf = noq / 16;
+  return mf == 1 || mf == 2 || mf == 4 || (B <= 64 && mf == 8);
+}
+inline int gemm_f2_col_tiles(int B) {
+  const int nr = B > 64 ? 256 : 64;
+  return (B + nr - 1) / nr;
+}
+hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngrid, int ngq, int M, int noq, int B,
+                          int bp, int splits, hipStream_t st);
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
                             const Geometry& g, hipStream_t st);
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,

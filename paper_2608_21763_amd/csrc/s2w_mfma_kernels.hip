@@ -304,17 +304,199 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
   }
 }
 
+// LDS slot of 16-byte chunk c (0..3) of operator-tile row r: the chunk index is XORed with
+// bits 1-2 of the row so that the eight rows read together by a quarter wave fall into
+// eight distinct 16-byte bank groups.
+__device__ __forceinline__ int swz(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
+
+// Compact activation of the elastic GEMM: Sc[l][ks][jl][b] (b < bp), one uint2 per complex
+// activation value s (scaled by sig_up[l][b]): word x = bf16/f16 bits of (Re s_hi, Im s_hi) in
+// (low, high) halves, word y = the same for the low term s - s_hi.  The 2x2 real embedding is
+// formed in registers from these words (sign flip of the high half for the real output
+// column, half swap for the imaginary column, masks for the packed real slot).
+template <int HT>
+__global__ __launch_bounds__(256) void k_prep_act_compact(const float2* __restrict__ S, const float* __restrict__ sig_up,
+                                                          int M, int nsub, int nsq, int B, int bp, int nks,
+                                                          uint2* __restrict__ Sc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)M * nks * 16 * bp;
+  if (i >= total) return;
+  const int b = (int)(i % bp);
+  int64_t q = i / bp;
+  const int jl = (int)(q % 16);
+  q /= 16;
+  const int ks = (int)(q % nks);
+  const int l = (int)(q / nks);
+  const int j = 16 * ks + jl;
+  float2 s = make_float2(0.f, 0.f);
+  if (b < B && j < nsub) {
+    s = S[((int64_t)l * nsq + j) * bp + b];
+    const float u = sig_up[(int64_t)l * bp + b];
+    s.x *= u;
+    s.y *= u;
+  }
+  const uint32_t hr = to_half_bits<HT>(s.x), hi = to_half_bits<HT>(s.y);
+  const uint32_t lr = to_half_bits<HT>(s.x - from_half_bits<HT>(hr));
+  const uint32_t li = to_half_bits<HT>(s.y - from_half_bits<HT>(hi));
+  Sc[i] = make_uint2(hr | (hi << 16), lr | (li << 16));
+}
+
+hipError_t launch_prep_act_compact(int ht, const float2* S, float* sig_up, float* sig_down, int M, int nsub, int nsq,
+                                   int B, int bp, int nks, uint2* Sc, hipStream_t st) {
+  const int64_t ns = (int64_t)M * bp;
+  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp, sig_up,
+                     sig_down);
+  const int64_t total = (int64_t)M * nks * 16 * bp;
+  dim3 grid((unsigned)((total + 255) / 256));
+  if (ht == 1)
+    hipLaunchKernelGGL(k_prep_act_compact<1>, grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, Sc);
+  else
+    hipLaunchKernelGGL(k_prep_act_compact<2>, grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, Sc);
+  return hipGetLastError();
+}
+
+// Fragment word of the 2x2 embedding for output column parity c (0 real, 1 imaginary) from a
+// packed (re | im << 16) word; dc selects the packed real slot.
+__device__ __forceinline__ uint32_t embed_word(uint32_t w, int c, bool dc) {
+  if (dc) return c == 0 ? (w & 0xffffu) : (w & 0xffff0000u);
+  return c == 0 ? (w ^ 0x80000000u) : ((w >> 16) | (w << 16));
+}
+
+// Elastic GEMM with compact activations, LDS-staged: eight waves (2 row groups x 4 column
+// groups), tile 2*MW grid rows x 4*NW output columns (2*NW ruptures).  Per K step the operator
+// tile (2*MW rows x 64 bytes, chunk-swizzled) and the compact activation tile (16 subfaults x
+// 2*NW ruptures x 8 bytes, rows padded by 64 bytes) are double-buffered in LDS.
+template <int HT, int MW, int NW, int WR>
+__global__ __launch_bounds__(256 * WR, WR == 1 ? 2 : 1) void k_gemm_g3(const uint4* __restrict__ Gq, const float* __restrict__ sG,
+                                                    const uint2* __restrict__ Sc, const float* __restrict__ sig_down,
+                                                    float* __restrict__ U, int ngrid, int M, int nks, int B, int bp,
+                                                    int nrb, int nct) {
+  constexpr int MF = MW / 16, NF = NW / 16;
+  constexpr int NTH = 256 * WR;              // threads
+  constexpr int RT = WR * MW;                // rows per tile
+  constexpr int NR = 2 * NW;                 // ruptures per tile (4 waves x NW columns / 2)
+  constexpr int LDB = NR + 8;                // padded LDS row of the activation tile (uint2)
+  constexpr int A_U4 = RT * 4;               // uint4 of the operator tile
+  constexpr int B_U4 = 16 * NR / 2;          // uint4 of the activation tile (two uint2 each)
+  constexpr int T_U4 = A_U4 + B_U4;
+  constexpr int PER_T = (T_U4 + NTH - 1) / NTH;
+  constexpr int LDS_A = A_U4;                // uint4
+  constexpr int LDS_B = 16 * LDB / 2;        // uint4
+  __shared__ uint4 lds[2][LDS_A + LDS_B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 2, wc = wave & 3;
+  const int c = lane & 1;
+  const int nwg = gridDim.x, w = blockIdx.x;
+  const int nx = 8 < M ? 8 : M;
+  const int x = w % nx, wi = w / nx, nwx = (nwg - x + nx - 1) / nx;
+  const int slots_x = (M - x + nx - 1) / nx;
+  const int64_t per_slot = (int64_t)nrb * nct;
+  const int64_t items = (int64_t)slots_x * per_slot;
+  const int64_t row_u4 = (int64_t)nks * 4;
+  for (int64_t it = wi; it < items; it += nwx) {
+    const int l = x + nx * (int)(it / per_slot);
+    const bool dc = (l == 0);
+    const int64_t rem = it % per_slot;
+    const int rb = (int)(rem / nct), ct = (int)(rem % nct);
+    const int g0 = rb * RT;
+    const int b0 = ct * NR;
+    const uint4* src[PER_T];
+    int64_t sstep[PER_T];
+    bool valid[PER_T];
+    int dst[PER_T];
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k) {
+      const int i = tid + NTH * k;
+      valid[k] = i < T_U4;
+      if (i < A_U4) {
+        const int r = i >> 2, cc = i & 3;
+        const int g = min(g0 + r, ngrid - 1);
+        src[k] = Gq + ((int64_t)g * M + l) * row_u4 + cc;
+        sstep[k] = 4;
+        dst[k] = swz(r, cc);
+      } else {
+        const int j = min(i - A_U4, B_U4 - 1);
+        const int jl = j / (NR / 2), q = j % (NR / 2);  // row jl, uint4 q (ruptures 2q, 2q+1)
+        const int bb = min(b0 + 2 * q, bp - 2);
+        src[k] = reinterpret_cast<const uint4*>(Sc + (((int64_t)l * nks) * 16 + jl) * bp + bb);
+        sstep[k] = (int64_t)16 * bp / 2;
+        dst[k] = LDS_A + (jl * LDB) / 2 + q;
+      }
+    }
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    uint4 stage[PER_T];
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+      if (valid[k]) stage[k] = ntload(src[k]);
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+      if (valid[k]) lds[0][dst[k]] = stage[k];
+    __syncthreads();
+    for (int ks = 0; ks < nks; ++ks) {
+      const int cur = ks & 1;
+      const bool more = ks + 1 < nks;
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+          if (valid[k]) stage[k] = ntload(src[k] + (int64_t)(ks + 1) * sstep[k]);
+      }
+      const uint4* la = &lds[cur][0];
+      const uint2* lb = reinterpret_cast<const uint2*>(&lds[cur][LDS_A]);
+      uint4 av[MF];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) av[a] = la[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        const int rl = wc * (NW / 2) + b * 8 + ((lane & 15) >> 1);  // rupture within the tile
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const uint2 wv = lb[(4 * (lane >> 4) + e2) * LDB + rl];
+          hw[e2] = embed_word(wv.x, c, dc);
+          lw[e2] = embed_word(wv.y, c, dc);
+        }
+        const uint4 bh = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        const uint4 bl = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+#pragma unroll
+        for (int a = 0; a < MF; ++a) {
+          acc[a][b] = mfma16<HT>(av[a], bh, acc[a][b]);
+          acc[a][b] = mfma16<HT>(av[a], bl, acc[a][b]);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+          if (valid[k]) lds[cur ^ 1][dst[k]] = stage[k];
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + wr * MW + 16 * a + 4 * (lane >> 4) + r;
+        if (g >= ngrid) continue;
+        const float sg = sG[(int64_t)g * M + l];
+#pragma unroll
+        for (int b = 0; b < NF; ++b) {
+          const int rup = b0 + wc * (NW / 2) + b * 8 + ((lane & 15) >> 1);
+          if (rup < B)
+            U[(((int64_t)g * M + l) * bp + rup) * 2 + c] = acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+        }
+      }
+  }
+}
+
 // Elastic GEMM, LDS-staged variant for wide batches.  Eight waves (2 row groups x 4 column
 // groups); workgroup tile 2*MW grid rows x 4*NW output columns.  Per K step (16 subfaults)
 // the workgroup copies the operator tile (2*MW rows x 64 bytes) and the activation tile
 // (4*NW/16 column blocks x H fragments) from global memory into one of two LDS buffers
 // while the matrix cores consume the other; each operator and activation fragment is read
 // from HBM/L2 once per workgroup and shared by four (resp. two) waves through LDS.
-// LDS slot of 16-byte chunk c (0..3) of operator-tile row r: the chunk index is XORed with
-// bits 1-2 of the row so that the eight rows read together by a quarter wave fall into
-// eight distinct 16-byte bank groups.
-__device__ __forceinline__ int swz(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
-
 template <int HT, int H, int MW, int NW>
 __global__ __launch_bounds__(512, 1) void k_gemm_g2(const uint4* __restrict__ Gq, const float* __restrict__ sG,
                                                     const uint4* __restrict__ Bop, const float* __restrict__ sig_down,
@@ -463,6 +645,27 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
   return hipGetLastError();
 }
 
+hipError_t launch_gemm_g3(int ht, int cfg, const uint4* Gq, const float* sG, const uint2* Sc, const float* sig_down,
+                          float* U, int nwg, int ngrid, int M, int nks, int B, int bp, hipStream_t st) {
+  // 7: 256 rows x 128 ruptures (eight waves); 8: 128 rows x 256 ruptures (eight waves);
+  // 9: 128 rows x 128 ruptures (four waves, two workgroups per compute unit)
+  const int WR = cfg == 9 ? 1 : 2;
+  const int MW = cfg == 8 ? 64 : 128, NW = cfg == 8 ? 128 : 64;
+  const int nrb = (ngrid + WR * MW - 1) / (WR * MW);
+  const int nct = (B + 2 * NW - 1) / (2 * NW);
+  const int grid = cfg == 9 ? 2 * nwg : nwg;
+#define S2W_G3(HT_, MW_, NW_, WR_)                                                                                 \
+  hipLaunchKernelGGL((k_gemm_g3<HT_, MW_, NW_, WR_>), dim3(grid), dim3(256 * WR_), 0, st, Gq, sG, Sc, sig_down, U, \
+                     ngrid, M, nks, B, bp, nrb, nct)
+  if (ht == 1) {
+    if (cfg == 8) S2W_G3(1, 64, 128, 2); else if (cfg == 9) S2W_G3(1, 128, 64, 1); else S2W_G3(1, 128, 64, 2);
+  } else {
+    if (cfg == 8) S2W_G3(2, 64, 128, 2); else if (cfg == 9) S2W_G3(2, 128, 64, 1); else S2W_G3(2, 128, 64, 2);
+  }
+#undef S2W_G3
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
                          hipStream_t st) {
@@ -580,6 +783,159 @@ __global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, co
         if (cb0 + b < ncb && n < 2 * bp) pw[(int64_t)o * (2 * bp) + n] = acc[a][b][r];
       }
     }
+}
+
+// Acoustic GEMM, LDS-staged, for the packed bfloat16 activation: workgroup (l, split, column
+// tile) of four waves; per K step (16 grid rows) the operator tile (noq observers x 64 bytes,
+// chunk-swizzled) and the activation tile (16 rows x NR ruptures x 8 bytes, rows padded by 64
+// bytes) are double-buffered in LDS, the next step's tiles loaded while the matrix cores
+// consume the current ones.
+template <int MF, int NF>
+__global__ __launch_bounds__(256, 2) void k_gemm_f2(const uint4* __restrict__ Fq, const uint2* __restrict__ V,
+                                                    float* __restrict__ part, int ngrid, int ngq, int M, int noq,
+                                                    int B, int bp) {
+  constexpr int NR = 4 * NF * 8;            // ruptures per tile
+  constexpr int LDB = NR + 8;               // padded LDS row (uint2)
+  constexpr int A_U4 = MF * 16 * 4;         // operator tile uint4
+  constexpr int B_U4 = 16 * NR / 2;         // activation tile uint4
+  constexpr int T_U4 = A_U4 + B_U4;
+  constexpr int PER_T = (T_U4 + 255) / 256;
+  constexpr int LDS_A = A_U4, LDS_B = 16 * LDB / 2;
+  __shared__ uint4 lds[2][LDS_A + LDS_B];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int c = lane & 1;
+  const int l = blockIdx.x;
+  const bool dc = (l == 0);
+  const int split = blockIdx.y, splits = gridDim.y;
+  const int b0 = blockIdx.z * NR;
+  const int nks = ngq / 16;
+  const int kst0 = (int)((int64_t)nks * split / splits), kst1 = (int)((int64_t)nks * (split + 1) / splits);
+  const int64_t frow = (int64_t)ngq / 4;  // uint4 per (l, o) row of Fq
+  const uint4* src[PER_T];
+  int64_t sstep[PER_T];
+  bool valid[PER_T];
+  int dst[PER_T];
+#pragma unroll
+  for (int k = 0; k < PER_T; ++k) {
+    const int i = tid + 256 * k;
+    valid[k] = i < T_U4;
+    if (i < A_U4) {
+      const int r = i >> 2, cc = i & 3;
+      src[k] = Fq + ((int64_t)l * noq + r) * frow + 4 * kst0 + cc;
+      sstep[k] = 4;
+      dst[k] = swz(r, cc);
+    } else {
+      const int j = min(i - A_U4, B_U4 - 1);
+      const int gl = j / (NR / 2), q = j % (NR / 2);
+      const int bb = min(b0 + 2 * q, bp - 2);
+      // rows past the grid read the last row; their operator entries are zero padding
+      const int g = min(16 * kst0 + gl, ngrid - 1);
+      src[k] = reinterpret_cast<const uint4*>(V + ((int64_t)g * M + l) * bp + bb);
+      sstep[k] = 16 * (int64_t)M * bp / 2;
+      dst[k] = LDS_A + (gl * LDB) / 2 + q;
+      if (16 * kst0 + gl >= ngrid) sstep[k] = 0;
+    }
+  }
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (kst0 < kst1) {
+    uint4 stage[PER_T];
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+      if (valid[k]) stage[k] = ntload(src[k]);
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k)
+      if (valid[k]) lds[0][dst[k]] = stage[k];
+    __syncthreads();
+    for (int ks = kst0; ks < kst1; ++ks) {
+      const int cur = (ks - kst0) & 1;
+      const bool more = ks + 1 < kst1;
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k) {
+          if (!valid[k]) continue;
+          // activation rows stop advancing past the last grid row (sstep is then zero, or the
+          // row is clamped below)
+          const uint4* pk = src[k] + (int64_t)(ks + 1 - kst0) * sstep[k];
+          if (k * 256 + tid >= A_U4) {
+            const int j = min(k * 256 + tid - A_U4, B_U4 - 1);
+            const int gl = j / (NR / 2);
+            if (16 * (ks + 1) + gl >= ngrid) {
+              const int q = j % (NR / 2);
+              const int bb = min(b0 + 2 * q, bp - 2);
+              pk = reinterpret_cast<const uint4*>(V + ((int64_t)(ngrid - 1) * M + l) * bp + bb);
+            }
+          }
+          stage[k] = ntload(pk);
+        }
+      }
+      const uint4* la = &lds[cur][0];
+      const uint2* lb = reinterpret_cast<const uint2*>(&lds[cur][LDS_A]);
+      uint4 av[MF];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) av[a] = la[swz(16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        const int rl = wave * (NF * 8) + b * 8 + ((lane & 15) >> 1);
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const uint2 wv = lb[(4 * (lane >> 4) + e2) * LDB + rl];
+          hw[e2] = embed_word(wv.x, c, dc);
+          lw[e2] = embed_word(wv.y, c, dc);
+        }
+        const uint4 bh = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+        const uint4 bl = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+#pragma unroll
+        for (int a = 0; a < MF; ++a) {
+          acc[a][b] = mfma16<1>(av[a], bh, acc[a][b]);
+          acc[a][b] = mfma16<1>(av[a], bl, acc[a][b]);
+        }
+      }
+      if (more) {
+#pragma unroll
+        for (int k = 0; k < PER_T; ++k)
+          if (valid[k]) lds[cur ^ 1][dst[k]] = stage[k];
+      }
+      __syncthreads();
+    }
+  }
+  // part[split][l][o][n], n = 2*rupture + re/im
+  float* pw = part + ((int64_t)split * M + l) * noq * (2 * bp);
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 16 * a + 4 * (lane >> 4) + r;
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        const int rup = b0 + wave * (NF * 8) + b * 8 + ((lane & 15) >> 1);
+        if (rup < bp) pw[(int64_t)o * (2 * bp) + 2 * rup + c] = acc[a][b][r];
+      }
+    }
+}
+
+hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngrid, int ngq, int M, int noq, int B,
+                          int bp, int splits, hipStream_t st) {
+  const int mf = noq / 16;
+  const int nf = B > 64 ? 8 : 2;
+  const int nr = 4 * nf * 8;
+  dim3 grid(M, splits, (B + nr - 1) / nr);
+#define S2W_F2(MF_, NF_) \
+  hipLaunchKernelGGL((k_gemm_f2<MF_, NF_>), grid, dim3(256), 0, st, Fq, V, part, ngrid, ngq, M, noq, B, bp)
+  if (nf == 8) {
+    if (mf == 1) S2W_F2(1, 8); else if (mf == 2) S2W_F2(2, 8); else if (mf == 4) S2W_F2(4, 8);
+    else return hipErrorInvalidValue;
+  } else {
+    if (mf == 1) S2W_F2(1, 2); else if (mf == 2) S2W_F2(2, 2); else if (mf == 4) S2W_F2(4, 2);
+    else if (mf == 8) S2W_F2(8, 2);
+    else return hipErrorInvalidValue;
+  }
+#undef S2W_F2
+  return hipGetLastError();
 }
 
 template <int HT, int H, int NF, bool PK>

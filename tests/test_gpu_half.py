@@ -85,7 +85,7 @@ def test_elastic_gemm_tile_shapes_agree(B):
     op = make_operator(cfg, max_batch=B, g_dtype="f16", f_dtype="f16")
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
     outs = {}
-    for c in (4, 1, 2, 3, 5, 6):
+    for c in (4, 1, 2, 3, 5, 6, 7, 8, 9):
         op.set_tuning(gemm_cfg=c)
         outs[c] = op.forward(s).clone()
     for c in outs:
@@ -95,3 +95,24 @@ def test_elastic_gemm_tile_shapes_agree(B):
     errs = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s.cpu().numpy().astype(np.float64)))
     print("rel-L2 max", errs.max())
     assert errs.max() <= BOUND[("f16", "f16")]
+
+
+@pytest.mark.parametrize("B,nobs", [(40, 20), (130, 20), (40, 120), (130, 120), (257, 50)])
+def test_acoustic_gemm_kernels_agree(B, nobs):
+    # the LDS-staged and the register acoustic kernels take the same K steps in the same order;
+    # with 120 observers and B > 64 the staged tile does not fit and both settings take the
+    # register kernel
+    cfg = synth.SynthConfig(nsub=40, ngrid=333, nobs=nobs, nt=48, seed=95, slip_seed=96, op_kind="dense",
+                            slip_mode="dense")
+    log_case("half_acoustic", B=B, nobs=nobs)
+    op = make_operator(cfg, max_batch=B, g_dtype="bf16", f_dtype="bf16")
+    s = to_dev(synth.gen_slip_batch(cfg, 0, B))
+    op.set_tuning(fgemm_lds=1)
+    y1 = op.forward(s).clone()
+    op.set_tuning(fgemm_lds=-1)
+    y2 = op.forward(s).clone()
+    assert torch.equal(y1, y2)
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    errs = oracle.rel_l2_per_rupture(y1.cpu().numpy(), oracle.forward(G, F, s.cpu().numpy().astype(np.float64)))
+    print("rel-L2 max", errs.max())
+    assert errs.max() <= BOUND[("bf16", "bf16")]
