@@ -36,24 +36,45 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+# device sources each measured kernel is compiled from
+KERNEL_SOURCES = {
+    "k_fused_forward": ["s2w_fft_kernels.hip", "s2w_device.h"],
+    "k_mid_batch256": ["s2w_fft_kernels.hip", "s2w_device.h"],
+    "k_gemm_g": ["s2w_mfma_kernels.hip"],
+    "k_gemm_g2": ["s2w_mfma_kernels.hip"],
+    "k_gemm_f2": ["s2w_mfma_kernels.hip"],
+    "k_cgemm32": ["s2w_mfma32_kernels.hip"],
+}
+
+
+def kernel_source_hash(kernel: str | None = None) -> str:
+    """Hash of the device sources of `kernel` (all kernel sources when None)."""
+    csrc = os.path.join(ROOT, "paper_2608_21763_amd", "csrc")
+    files = KERNEL_SOURCES.get(kernel) if kernel else None
+    paths = [os.path.join(csrc, f) for f in files] if files else sorted(glob.glob(os.path.join(csrc, "*")))
     h = hashlib.sha1()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2608_21763_amd", "csrc", "*"))):
+    for f in paths:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:12]
 
 
-def traffic_for(kernel: str, src_hash: str, per_launch_units: float):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they match the current sources."""
+def traffic_for(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter figures
+    (profiles/traffic_<kernel>.json), or None when its sources changed since they were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
-    if d.get("source_hash") != src_hash:
+    if d.get("source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
+
+
+def elastic_kernel(B: int) -> str:
+    """Kernel of the batched elastic GEMM the library picks by default for a batch of B."""
+    return "k_gemm_g" if B <= 64 else "k_gemm_g2"
 
 
 def time_path(op, s_dev, steps: int, warmup: int, B: int):
@@ -94,6 +115,9 @@ def main():
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngrid", type=int, default=None, help="override the share size (testing only)")
+    ap.add_argument("--cpu-ruptures", type=int, default=3, help="ruptures the oracle baseline runs")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; the cross-GPU sum of partial waveforms "
@@ -116,6 +140,16 @@ def main():
     src_hash = kernel_source_hash()
     cores = len(os.sched_getaffinity(0))
     omp = int(os.environ.get("OMP_NUM_THREADS", cores))
+    if args.copy_probe_mib > 0:
+        # reads and writes exactly n bytes each: the reference for scaling FETCH_SIZE / WRITE_SIZE
+        n = args.copy_probe_mib << 20
+        xa = torch.ones(n // 4, dtype=torch.float32, device=dev)
+        xb = torch.empty_like(xa)
+        torch.cuda.synchronize()
+        torch.neg(xa, out=xb)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n} bytes read, {n} bytes written")
+        del xa, xb
 
     # ---------------- fp32 single-rupture path ----------------
     if "fp32" in paths:
@@ -136,19 +170,22 @@ def main():
                 "achieved_GBs": abytes / (kmean * 1e6), "hbm_frac": abytes / (kmean * 1e6) / HBM_PEAK_GBS,
                 "setup_s": setup_s}
         log(f"fp32: {ms_step:.3f} ms/rupture, kernel {kmean:.3f} ms, {fp32['achieved_GBs']:.0f} GB/s")
-        y0 = op.forward(s_dev[0, 0]).cpu().numpy().astype(np.float64)
         result["fp32"] = fp32
         if not args.no_cpu_baseline:
             import oracle
+            nc = max(1, min(args.cpu_ruptures, nrup))
+            y_gpu = [op.forward(s_dev[b, 0]).cpu().numpy().astype(np.float64) for b in range(nc)]
             t = time.perf_counter()
-            y_ref = oracle.forward_synth(cfg, s_host[0])
+            y_ref = oracle.forward_synth(cfg, s_host[:nc])
             cpu_s = time.perf_counter() - t
-            fp32["rel_l2"] = oracle.rel_l2(y0, y_ref)
+            errs = [oracle.rel_l2(y_gpu[b], y_ref[b]) for b in range(nc)]
+            fp32["rel_l2"] = max(errs)
+            fp32["rel_l2_sampled"] = {str(b): e for b, e in enumerate(errs)}
             result["cpu_baseline"] = {
-                "value": 1.0 / cpu_s, "unit": "ruptures/s", "cores": min(cores, omp), "kind": "oracle",
-                "sample": f"1 rupture (index 0) over the whole {cfg.ngrid}-row share, FP64 direct time-domain "
-                          f"convolution, operators regenerated in chunks, {cpu_s:.1f} s"}
-            log(f"oracle: {cpu_s:.1f} s/rupture, fp32 rel-L2 {fp32['rel_l2']:.2e}")
+                "value": nc / cpu_s, "unit": "ruptures/s", "cores": min(cores, omp), "kind": "oracle",
+                "sample": f"{nc} ruptures (indices 0..{nc - 1}) over the whole {cfg.ngrid}-row share, FP64 direct "
+                          f"time-domain convolution, operators regenerated in chunks, {cpu_s:.1f} s in total"}
+            log(f"oracle: {cpu_s / nc:.1f} s/rupture, fp32 rel-L2 " + " ".join(f"{e:.2e}" for e in errs))
         del op
         torch.cuda.empty_cache()
 
@@ -174,7 +211,7 @@ def main():
         flops_g = 8.0 * bcfg.ngrid * bcfg.nsub * (bcfg.nt) * B      # complex MACs of the elastic stage per call
         hbytes = algorithmic_bytes(bcfg.nsub, bcfg.nobs, bcfg.ngrid, bcfg.nt, 2)
         half = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{fdt}",
-                "kernel": "k_gemm_g", "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)),
+                "kernel": elastic_kernel(B), "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)),
                 "algorithmic_flops": flops_g, "achieved_TFLOPs": flops_g / (kmean * 1e9),
                 "issued_TFLOPs": 2.0 * flops_g / (kmean * 1e9), "algorithmic_bytes": hbytes, "setup_s": setup_s}
         log(f"half {gdt}/{fdt} B={B}: {ms_step:.3f} ms/call, {half['ruptures_per_s']:.0f} ruptures/s, "
@@ -200,12 +237,12 @@ def main():
         roof = {"bound": "mfma", "achieved": half["achieved_TFLOPs"], "peak": MFMA_PEAK[half["dtypes"].split("/")[0]],
                 "unit": "TFLOP/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = traffic_for("k_gemm_g", src_hash, 1)
+        roof["traffic"] = traffic_for(half["kernel"])
         workload = (f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, batched {half['dtypes']} "
                     f"B={half['B']} (vs fp32 single rupture)")
     else:
         roof = {"bound": "hbm", "achieved": fp32["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": fp32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic_for("k_fused_forward", src_hash, 1)}
+                "frac": fp32["achieved_GBs"] / HBM_PEAK_GBS, "traffic": traffic_for("k_fused_forward")}
         workload = f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, fp32 single rupture"
     out = {
         "metric": METRIC,

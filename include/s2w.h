@@ -97,7 +97,7 @@ s2w_status s2w_query_sizes(const s2w_plan* plan, uint64_t* operator_bytes, uint6
 s2w_status s2w_bind_memory(s2w_plan* plan, void* operator_store, uint64_t operator_bytes, void* workspace,
                            uint64_t workspace_bytes);
 
-/* One-time setup (excluded from the paper's timings, Sec. III-D): transform
+/* One-time setup (excluded from the paper's timings, Sec. III-C): transform
  * the time-domain blocks of grid rows [row0, row0+nrows) and keep their
  * spectra in the operator store.  Device inputs, row-major float32:
  *   G_chunk[r][j][k] = [F_{G,k}]_{row0+r, j}   shape [nrows][nsub][nt]   (eq. 1)
@@ -128,7 +128,7 @@ typedef struct s2w_tuning {
   int32_t adj_cols;          /* grid-row contractions (adjoint elastic stage): columns per thread (8 or 16) */
   int32_t adj_splits;        /* single-rupture adjoint: grid splits of the transposed elastic stage */
   int32_t batch_path_min_b;  /* smallest B that takes the batched matrix-core path */
-  int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..8 fixed shapes, 4 = narrow */
+  int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..9 fixed shapes, 4 = narrow */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
   int32_t fgemm_lds;         /* batched acoustic GEMM (bf16): 1 LDS-staged kernel, -1 register kernel */
 } s2w_tuning;

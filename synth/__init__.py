@@ -9,7 +9,7 @@ is a pure function of a seed and its indices (a counter-based generator in
 bit-identically.  This module holds none of the method's arithmetic; the FP64
 oracle and the GPU library's callers both draw their inputs from it.
 
-Workload presets follow the paper's Cascadia shapes (Sec. III-D, Table II):
+Workload presets follow the paper's Cascadia shapes (Sec. III-C, Table II):
 963 subfaults, a 1/64 share (37,760 rows) of the 2,416,530-point seafloor
 grid, 64 observers, 256 one-second steps.
 """

@@ -21,7 +21,7 @@
  *
  * The paper's inputs (FakeQuakes ruptures, FK Green's functions, adjoint
  * acoustic-gravity responses) are not available; these stand in for them
- * with the paper's shapes (Sec. III-D, Table II): a damped sinusoid per
+ * with the paper's shapes (Sec. III-C, Table II): a damped sinusoid per
  * source/receiver pair with spatial decay and a travel-time onset, and
  * triangle slip-rate pulses that start at a rupture-front arrival time.
  */

@@ -4,7 +4,7 @@ Each check is independent of the oracle's loop code: explicit block matrices
 built from the BLTT definition (Sec. II-B3), closed forms of geometric
 kernels, the Nt = 1 case that reduces to a plain matrix product, numpy's
 convolution for the composed kernel, and the defining invariants of a causal
-LTI map (Sec. II-A: linearity, causality, shift invariance, impulse response).
+LTI map (Sec. II-B: linearity, causality, shift invariance, impulse response).
 """
 import numpy as np
 import pytest
