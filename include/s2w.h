@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define S2W_ABI_VERSION 1
+#define S2W_ABI_VERSION 2
 
 typedef struct s2w_plan s2w_plan;
 
@@ -64,6 +64,16 @@ typedef enum s2w_dtype {
 
 typedef enum s2w_diff { S2W_DIFF_NONE = 0, S2W_DIFF_BACKWARD = 1 } s2w_diff;
 
+/* Storage of the spectra and the kernels that go with it.
+ *  SINGLE   float32 only: each (grid row, column) spectrum contiguous over the bins; forward
+ *           runs one fused streaming kernel per rupture (the seafloor field stays on chip),
+ *           B ruptures as B such passes.  Best for B = 1.
+ *  BATCHED  per-bin operator matrices (grid row, bin, column) for matrix-core GEMMs over all
+ *           B ruptures of a call; the seafloor field of the batch goes through the workspace.
+ *           The only layout of the half-precision stores.
+ *  AUTO     BATCHED for half-precision stores or max_batch >= 8, else SINGLE. */
+typedef enum s2w_layout { S2W_LAYOUT_AUTO = 0, S2W_LAYOUT_SINGLE = 1, S2W_LAYOUT_BATCHED = 2 } s2w_layout;
+
 /* Problem description.  Limits of this build: 1 <= nt <= 512, 1 <= nsub <= 1024,
  * 1 <= nobs <= 256, 1 <= ngrid, 0 <= max_batch <= 1024. */
 typedef struct s2w_desc {
@@ -76,6 +86,8 @@ typedef struct s2w_desc {
   int32_t g_dtype;    /* s2w_dtype of the stored elastic spectra */
   int32_t f_dtype;    /* s2w_dtype of the stored acoustic-gravity spectra */
   double dt;          /* time step in seconds (> 0); enters only through D_t */
+  int32_t layout;     /* s2w_layout */
+  int32_t reserved;   /* must be 0 */
 } s2w_desc;
 
 /* Create a plan for `desc` on HIP device `device`.  Host-side only: no device
@@ -131,6 +143,10 @@ typedef struct s2w_tuning {
   int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..9 fixed shapes, 4 = narrow */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
   int32_t fgemm_lds;         /* batched acoustic GEMM (bf16): 1 LDS-staged kernel, -1 register kernel */
+  int32_t gemm32_cfg;        /* batched float32 GEMM tile: -1 automatic, 1..4 = tile shapes 0..3 (rows x ruptures:
+                                64 x 128, 128 x 32, 256 x 8, 64 x 64) */
+  int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
+  int32_t adj32_splits;      /* batched float32 adjoint, transposed elastic GEMM: grid-row splits (1..8) */
 } s2w_tuning;
 
 s2w_status s2w_set_tuning(s2w_plan* plan, const s2w_tuning* t);

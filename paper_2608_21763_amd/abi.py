@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libs2w.so")
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 DIFF_NONE = 0
 DIFF_BACKWARD = 1
+LAYOUTS = {"auto": 0, "single": 1, "batched": 2}
 
 STATUS = {0: "S2W_OK", 1: "S2W_EINVAL", 2: "S2W_ENOMEM", 3: "S2W_ESTATE", 4: "S2W_EUNSUPPORTED", 5: "S2W_EHIP"}
 
@@ -28,13 +29,15 @@ class S2WError(RuntimeError):
 class Desc(ctypes.Structure):
     _fields_ = [("nsub", ctypes.c_int32), ("ngrid", ctypes.c_int32), ("nobs", ctypes.c_int32),
                 ("nt", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("diff", ctypes.c_int32),
-                ("g_dtype", ctypes.c_int32), ("f_dtype", ctypes.c_int32), ("dt", ctypes.c_double)]
+                ("g_dtype", ctypes.c_int32), ("f_dtype", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
     _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_cols", ctypes.c_int32),
                 ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32), ("gemm_cfg", ctypes.c_int32),
-                ("fgemm_splits", ctypes.c_int32), ("fgemm_lds", ctypes.c_int32)]
+                ("fgemm_splits", ctypes.c_int32), ("fgemm_lds", ctypes.c_int32), ("gemm32_cfg", ctypes.c_int32),
+                ("gemm32_splits", ctypes.c_int32), ("adj32_splits", ctypes.c_int32)]
 
 
 EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_create", "s2w_plan_destroy",
@@ -83,9 +86,11 @@ class Plan:
     """Thin owner of an ``s2w_plan*``; methods mirror the C entry points."""
 
     def __init__(self, nsub: int, ngrid: int, nobs: int, nt: int, max_batch: int = 1, dt: float = 1.0,
-                 diff: int = DIFF_BACKWARD, g_dtype: str = "f32", f_dtype: str = "f32", device: int = 0):
+                 diff: int = DIFF_BACKWARD, g_dtype: str = "f32", f_dtype: str = "f32", device: int = 0,
+                 layout: str = "auto"):
         self.lib = load_library()
-        self.desc = Desc(nsub, ngrid, nobs, nt, max_batch, diff, DTYPES[g_dtype], DTYPES[f_dtype], dt)
+        self.desc = Desc(nsub, ngrid, nobs, nt, max_batch, diff, DTYPES[g_dtype], DTYPES[f_dtype], dt,
+                         LAYOUTS[layout], 0)
         self.handle = ctypes.c_void_p()
         st = self.lib.s2w_plan_create(ctypes.byref(self.desc), device, ctypes.byref(self.handle))
         if st != 0:

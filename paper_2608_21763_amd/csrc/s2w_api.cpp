@@ -44,7 +44,19 @@ struct Layout {
   uint64_t sh, part, yh, rh, wp, part2, gsh;
   // workspace (batched half-precision path)
   uint64_t staging, S, sig_up, sig_down, bop, U, tau_up, tau_down, part_f, yhb;
+  // operator store and workspace (batched float32 path)
+  uint64_t gs, fs;
+  uint64_t s32, u32, part32, yh32;
   uint64_t ws_total;
+};
+
+// Extra geometry of the batched float32 path.
+struct BatchGeo32 {
+  bool on = false;
+  int nsk, nok, ngk;          // subfaults padded to 8, observers to 16, grid rows to 8 (zeros)
+  int bp;                     // max_batch padded to a multiple of 8
+  int splits_f_max = 16;      // acoustic GEMM grid-row splits
+  int splits_a_max = 8;       // transposed elastic GEMM grid-row splits
 };
 
 // Extra geometry of the batched half-precision path.
@@ -66,6 +78,7 @@ struct s2w_plan {
   int ncu;
   Geometry geo;
   HalfGeo hg;
+  BatchGeo32 fb;
   Layout lay;
   s2w_tuning tune;
   char* op = nullptr;
@@ -123,10 +136,30 @@ struct DeviceGuard {
   }
 };
 
-Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, int ncu) {
+Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, const BatchGeo32& f, int ncu) {
   Layout L{};
   const uint64_t c8 = sizeof(float2);
   uint64_t off = 0;
+  if (f.on) {
+    const uint64_t bp = (uint64_t)f.bp;
+    L.gs = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * f.nsk * c8, kAlign);
+    L.fs = off;
+    off = round_up(off + (uint64_t)g.M * f.nok * f.ngk * c8, kAlign);
+    L.op_total = off;
+    off = 0;
+    L.s32 = off;
+    off = round_up(off + (uint64_t)g.M * std::max(f.nsk, f.nok) * bp * c8, kAlign);
+    L.u32 = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.M * bp * c8, kAlign);
+    L.part32 = off;
+    const uint64_t prow = std::max((uint64_t)f.splits_f_max * f.nok, (uint64_t)f.splits_a_max * f.nsk);
+    off = round_up(off + prow * g.M * 2 * bp * 4, kAlign);
+    L.yh32 = off;
+    off = round_up(off + bp * std::max(g.nobs, g.nsub) * g.M * c8, kAlign);
+    L.ws_total = off;
+    return L;
+  }
   if (!h.on) {
     L.gh = off;
     off = round_up(off + (uint64_t)g.ngrid * g.M * g.nsp * c8, kAlign);
@@ -221,6 +254,10 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   if (d.g_dtype < S2W_F32 || d.g_dtype > S2W_F16 || d.f_dtype < S2W_F32 || d.f_dtype > S2W_F16) return S2W_EINVAL;
   const bool half = d.g_dtype != S2W_F32 || d.f_dtype != S2W_F32;
   if (half && (d.g_dtype == S2W_F32 || d.f_dtype == S2W_F32)) return S2W_EUNSUPPORTED;
+  if (d.layout < S2W_LAYOUT_AUTO || d.layout > S2W_LAYOUT_BATCHED || d.reserved != 0) return S2W_EINVAL;
+  if (half && d.layout == S2W_LAYOUT_SINGLE) return S2W_EUNSUPPORTED;
+  const bool batched32 =
+      !half && (d.layout == S2W_LAYOUT_BATCHED || (d.layout == S2W_LAYOUT_AUTO && d.max_batch >= 8));
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return S2W_EINVAL;
 
@@ -260,7 +297,15 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
     h.splits_max = 16;
     h.rs = 16;
   }
-  p->lay = make_layout(d, g, h, ncu);
+  if (batched32) {
+    BatchGeo32& f = p->fb;
+    f.on = true;
+    f.nsk = (d.nsub + 7) / 8 * 8;
+    f.nok = (d.nobs + 15) / 16 * 16;
+    f.ngk = (d.ngrid + 7) / 8 * 8;
+    f.bp = (std::max(d.max_batch, 1) + 7) / 8 * 8;
+  }
+  p->lay = make_layout(d, g, h, p->fb, ncu);
   p->tune.fused_wg_per_cu = 1;
   p->tune.fused_rows = 8;
   p->tune.adj_cols = 16;
@@ -269,6 +314,9 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.gemm_cfg = -1;
   p->tune.fgemm_splits = 0;
   p->tune.fgemm_lds = 1;
+  p->tune.gemm32_cfg = -1;
+  p->tune.gemm32_splits = 0;
+  p->tune.adj32_splits = 0;
   p->row_set.assign((size_t)d.ngrid, 0);
   p->rows_missing = d.ngrid;
   {
@@ -360,6 +408,18 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) n.fgemm_lds = t->fgemm_lds > 0 ? 1 : 0;
+  if (t->gemm32_cfg) {
+    if (t->gemm32_cfg < -1 || t->gemm32_cfg > 4) return fail(p, S2W_EINVAL, "tuning: gemm32_cfg");
+    n.gemm32_cfg = t->gemm32_cfg < 0 ? -1 : t->gemm32_cfg - 1;
+  }
+  if (t->gemm32_splits) {
+    if (t->gemm32_splits < 0 || t->gemm32_splits > 16) return fail(p, S2W_EINVAL, "tuning: gemm32_splits");
+    n.gemm32_splits = t->gemm32_splits;
+  }
+  if (t->adj32_splits) {
+    if (t->adj32_splits < 0 || t->adj32_splits > 8) return fail(p, S2W_EINVAL, "tuning: adj32_splits");
+    n.adj32_splits = t->adj32_splits;
+  }
   if (t->fgemm_splits) {
     if (t->fgemm_splits < 0 || t->fgemm_splits > 16) return fail(p, S2W_EINVAL, "tuning: fgemm_splits");
     n.fgemm_splits = t->fgemm_splits;
@@ -371,6 +431,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
 s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   if (!p || !t) return S2W_EINVAL;
   *t = p->tune;
+  t->gemm32_cfg = p->tune.gemm32_cfg < 0 ? -1 : p->tune.gemm32_cfg + 1;
   return S2W_OK;
 }
 
@@ -408,6 +469,30 @@ static s2w_status set_operators_half(s2w_plan* p, const float* G_chunk, const fl
   return S2W_OK;
 }
 
+// Batched float32 setup: the row transforms write the GEMM layouts directly,
+// Gs[g][l][j] (padded subfaults zero) and Fs[l][o][g] (padded observers zero).
+static s2w_status set_operators_b32(s2w_plan* p, const float* G_chunk, const float* F_chunk, int64_t row0,
+                                    int64_t nrows, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const BatchGeo32& f = p->fb;
+  float2* Gs = (float2*)(p->op + p->lay.gs);
+  float2* Fs = (float2*)(p->op + p->lay.fs);
+  hipError_t e = hipSuccess;
+  if (!p->pad_zeroed) {
+    // grid-row padding columns of the acoustic store, as 32-bit words
+    e = launch_zero_strided((uint32_t*)(Fs + g.ngrid), (int64_t)g.M * f.nok, 2 * (int64_t)f.ngk,
+                            2 * (f.ngk - g.ngrid), st);
+    if (e != hipSuccess) return hip_fail(p, e, "set_operators: clear padding");
+    p->pad_zeroed = true;
+  }
+  e = launch_rfft_rows(G_chunk, nrows, g.nsub, f.nsk, Gs + row0 * g.M * f.nsk, (int64_t)g.M * f.nsk, 1, f.nsk, g,
+                       1.0f, st);
+  if (e != hipSuccess) return hip_fail(p, e, "set_operators: elastic transform");
+  e = launch_rfft_rows(F_chunk, nrows, g.nobs, f.nok, Fs + row0, 1, f.ngk, (int64_t)f.nok * f.ngk, g, 1.0f, st);
+  if (e != hipSuccess) return hip_fail(p, e, "set_operators: acoustic transform");
+  return S2W_OK;
+}
+
 s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_chunk, int64_t row0, int64_t nrows,
                              void* stream) {
   if (!p) return S2W_EINVAL;
@@ -422,8 +507,9 @@ s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_c
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "set_operators: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
-  if (p->hg.on) {
-    s2w_status hs = set_operators_half(p, G_chunk, F_chunk, row0, nrows, st);
+  if (p->fb.on || p->hg.on) {
+    s2w_status hs = p->fb.on ? set_operators_b32(p, G_chunk, F_chunk, row0, nrows, st)
+                             : set_operators_half(p, G_chunk, F_chunk, row0, nrows, st);
     if (hs != S2W_OK) return hs;
     for (int64_t r = row0; r < row0 + nrows; ++r) {
       if (!p->row_set[(size_t)r]) {
@@ -535,6 +621,102 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   return S2W_OK;
 }
 
+// Default tile of the batched float32 GEMMs for a batch of B (rows x ruptures: 0 = 64 x 128,
+// 1 = 128 x 32, 2 = 256 x 8, 3 = 64 x 64).
+static int b32_cfg(const s2w_plan* p, int B, bool few_rows) {
+  if (p->tune.gemm32_cfg >= 0) return p->tune.gemm32_cfg;
+  if (few_rows) return B > 64 ? 0 : 3;
+  return B <= 8 ? 2 : (B <= 32 ? 1 : (B <= 64 ? 3 : 0));
+}
+
+static int b32_splits(int tuned, int maxs, int M, int nrows, int B, int cfg) {
+  if (tuned > 0) return std::min(tuned, maxs);
+  const int64_t tiles = (int64_t)M * ((nrows + cgemm32_rows(cfg) - 1) / cgemm32_rows(cfg)) *
+                        ((B + cgemm32_ruptures(cfg) - 1) / cgemm32_ruptures(cfg));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(maxs, 2048 / std::max<int64_t>(1, tiles)));
+}
+
+// Batched forward on the matrix cores (float32 stores).
+static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const BatchGeo32& f = p->fb;
+  const Layout& L = p->lay;
+  const float2* Gs = (const float2*)(p->op + L.gs);
+  const float2* Fs = (const float2*)(p->op + L.fs);
+  float2* S = (float2*)(p->ws + L.s32);
+  float2* U = (float2*)(p->ws + L.u32);
+  float* part = (float*)(p->ws + L.part32);
+  float2* yh = (float2*)(p->ws + L.yh32);
+  const int bp = f.bp;
+  // S[l][j][b]
+  hipError_t e = launch_rfft_rows(s, B, g.nsub, f.nsk, S, 1, bp, (int64_t)f.nsk * bp, g, 1.0f, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
+  // U[g][l][b] = sum_j Gs[g][l][j] S[l][j][b]
+  const int cg = b32_cfg(p, B, false);
+  e = mark(p->ev_begin, st);
+  if (e == hipSuccess)
+    e = launch_cgemm32(cg, false, false, Gs, (int64_t)g.M * f.nsk, 1, f.nsk, g.ngrid, g.ngrid, f.nsk, f.nsk, S, bp,
+                       (int64_t)f.nsk * bp, f.nsk, B, bp, (float*)U, 2 * (int64_t)g.M * bp, 2 * (int64_t)bp, 0, g.M, 1,
+                       st);
+  if (e == hipSuccess) e = mark(p->ev_end, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
+  e = launch_mid_batch(U, nullptr, B, bp, false, false, g, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
+  // part[split][l][o][n] = sum_{g in split} Fs[l][o][g] V[g][l][b]
+  const int cf = b32_cfg(p, B, true);
+  const int sf = b32_splits(p->tune.gemm32_splits, f.splits_f_max, g.M, g.nobs, B, cf);
+  const int64_t prow = 2 * (int64_t)bp;
+  e = launch_cgemm32(cf, false, false, Fs, f.ngk, 1, (int64_t)f.nok * f.ngk, g.nobs, f.nok, f.ngk, f.ngk, U,
+                     (int64_t)g.M * bp, bp, g.ngrid, B, bp, part, prow, (int64_t)f.nok * prow,
+                     (int64_t)g.M * f.nok * prow, g.M, sf, st);
+  if (e == hipSuccess) e = launch_sum_f(part, sf, g.M, f.nok, g.nobs, B, bp, nullptr, yh, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");
+  e = launch_irfft_rows(yh, (int64_t)B * g.nobs, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+  if (e != hipSuccess) return hip_fail(p, e, "forward: output transform");
+  return S2W_OK;
+}
+
+// Batched adjoint on the matrix cores (float32 stores): the conjugate transposes of the two
+// per-bin products around the transposed mid-chain.
+static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const BatchGeo32& f = p->fb;
+  const Layout& L = p->lay;
+  const float2* Gs = (const float2*)(p->op + L.gs);
+  const float2* Fs = (const float2*)(p->op + L.fs);
+  float2* R = (float2*)(p->ws + L.s32);
+  float2* W = (float2*)(p->ws + L.u32);
+  float* part = (float*)(p->ws + L.part32);
+  float2* gh = (float2*)(p->ws + L.yh32);
+  const int bp = f.bp;
+  // R[l][o][b]
+  hipError_t e = launch_rfft_rows(r, B, g.nobs, f.nok, R, 1, bp, (int64_t)f.nok * bp, g, 1.0f, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
+  // W[g][l][b] = sum_o conj(Fs[l][o][g]) R[l][o][b]
+  const int c1 = b32_cfg(p, B, false);
+  e = launch_cgemm32(c1, true, true, Fs, 1, f.ngk, (int64_t)f.nok * f.ngk, g.ngrid, f.ngk, f.nok, f.nok, R, bp,
+                     (int64_t)f.nok * bp, f.nok, B, bp, (float*)W, 2 * (int64_t)g.M * bp, 2 * (int64_t)bp, 0, g.M, 1,
+                     st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
+  e = launch_mid_batch(W, nullptr, B, bp, true, false, g, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
+  // part[split][l][j][n] = sum_{g in split} conj(Gs[g][l][j]) W'[g][l][b]
+  const int c3 = b32_cfg(p, B, true);
+  const int sa = b32_splits(p->tune.adj32_splits, f.splits_a_max, g.M, g.nsub, B, c3);
+  const int64_t prow = 2 * (int64_t)bp;
+  e = mark(p->ev_begin, st);
+  if (e == hipSuccess)
+    e = launch_cgemm32(c3, true, true, Gs, 1, (int64_t)g.M * f.nsk, f.nsk, g.nsub, f.nsk, g.ngrid,
+                       (g.ngrid + 7) / 8 * 8, W, (int64_t)g.M * bp, bp, g.ngrid, B, bp, part, prow,
+                       (int64_t)f.nsk * prow, (int64_t)g.M * f.nsk * prow, g.M, sa, st);
+  if (e == hipSuccess) e = mark(p->ev_end, st);
+  if (e == hipSuccess) e = launch_sum_f(part, sa, g.M, f.nsk, g.nsub, B, bp, nullptr, gh, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: elastic matrix-core stage");
+  e = launch_irfft_rows(gh, (int64_t)B * g.nsub, g.M, 1, gs, g.nt, g, 1.0f / (float)g.L, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: output transform");
+  return S2W_OK;
+}
+
 s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
   s2w_status cs = check_call(p, s, B, y, "forward");
   if (cs != S2W_OK || B == 0) return cs;
@@ -543,6 +725,7 @@ s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* s
   if (!dg.ok) return fail(p, S2W_EHIP, "forward: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
   if (p->hg.on) return forward_half(p, s, B, y, st);
+  if (p->fb.on) return forward_b32(p, s, B, y, st);
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
   float2* Sh = (float2*)(p->ws + p->lay.sh);
@@ -586,6 +769,7 @@ s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* 
   if (!dg.ok) return fail(p, S2W_EHIP, "adjoint: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
   if (p->hg.on) return fail(p, S2W_EUNSUPPORTED, "adjoint: not available for half-precision stores in this build");
+  if (p->fb.on) return adjoint_b32(p, r, B, gs, st);
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
   float2* Rh = (float2*)(p->ws + p->lay.rh);

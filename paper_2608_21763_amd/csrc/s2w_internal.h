@@ -95,4 +95,18 @@ hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs,
                         float2* yh, hipStream_t st);
 hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st);
 
+// ---- batched path (matrix cores, float32 stores) ----
+// Per-slot complex GEMM out(row, b) = sum_k op(A(row, k)) X(k, b) for every slot l < M:
+//   A(row, k) at A + l*a_slot + row*a_row + k*a_k (complex; rcont: a_row == 1, else a_k == 1),
+//   rows < rows_alloc readable, k < kvalid nonzero, K padded to kpad (multiple of 8);
+//   X(k, b) at X + l*x_slot + k*x_k + b, rows k < xk_alloc readable;
+//   out float index split*o_split + l*o_slot + row*o_row + (2*b + re/im), rows < nrows, b < B;
+//   K split over `splits` ranges (one partial per split).
+int cgemm32_rows(int cfg);
+int cgemm32_ruptures(int cfg);
+hipError_t launch_cgemm32(int cfg, bool rcont, bool conj, const float2* A, int64_t a_row, int64_t a_k,
+                          int64_t a_slot, int nrows, int rows_alloc, int kvalid, int kpad, const float2* X,
+                          int64_t x_k, int64_t x_slot, int xk_alloc, int B, int bp, float* out, int64_t o_row,
+                          int64_t o_slot, int64_t o_split, int M, int splits, hipStream_t st);
+
 }  // namespace s2w

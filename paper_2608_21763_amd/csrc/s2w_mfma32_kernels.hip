@@ -1,0 +1,265 @@
+// Batched float32 path on the matrix cores: per-slot complex GEMMs on v_mfma_f32_16x16x4_f32.
+//
+// Float32 stores of the batched layout (complex64):
+//   Gs[g][l][j]  elastic spectra, j padded to nsk (a multiple of 8, zeros)
+//   Fs[l][o][g]  acoustic spectra, o padded to nok (a multiple of 16, zeros), g padded to ngk
+//                (a multiple of 8, zeros)
+//
+// One kernel serves the four per-slot products of the forward map and its adjoint
+// (eq. 1 and eq. 2 per bin, Alg. 2 step 3, and their conjugate transposes):
+//   out(row, b) = sum_k op(A(row, k)) X(k, b),    op = identity or complex conjugate,
+// for every packed slot l.  A(row, k) is read either k-contiguous (Gs as [g][j], Fs as [o][g])
+// or row-contiguous (the conjugate transposes: Fs^H as [g][o], Gs^H as [j][g]); X(k, b) is
+// rupture-contiguous.
+//
+// Complex arithmetic on real matrix cores: the operator value a = ar + i ai contributes the two
+// real K entries (ar, ai) of its row; each activation value x gives two output columns,
+//   real column:       (xr, -xi)   [conjugated operator: (xr,  xi)]
+//   imaginary column:  (xi,  xr)   [conjugated operator: (xi, -xr)]
+// and the packed real slot 0 (bins 0 and L/2) uses (xr, 0) and (0, xi).
+//
+// MFMA v_mfma_f32_16x16x4_f32 fragments, lane l of 64:
+//   A (16 x 4): row l%16, K entry l/16;  B (4 x 16): column l%16, K entry l/16;
+//   D (16 x 16): column l%16, rows 4*(l/16) .. +3.
+// K order: a chunk of 8 complex k (16 real entries) is four MFMA steps e = 0..3; in step e the
+// lane group kq = l/16 carries complex k = 2*kq + e/2, real or imaginary part e%2.  A lane thus
+// reads its operator values for a whole chunk as one float4 (complex k = 2kq, 2kq+1).
+#include "s2w_internal.h"
+
+namespace s2w {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// 16-byte unit c (0..3) of tile row r: XOR swizzle so that the 16 rows read together by a
+// quarter wave spread over distinct bank groups.
+__device__ __forceinline__ int swz32(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
+
+template <bool CONJ>
+__device__ __forceinline__ void embed32(float2 x, int ci, bool dc, float& v0, float& v1) {
+  if (dc) {
+    v0 = ci ? 0.f : x.x;
+    v1 = ci ? x.y : 0.f;
+  } else if (!CONJ) {
+    v0 = ci ? x.y : x.x;
+    v1 = ci ? x.x : -x.y;
+  } else {
+    v0 = ci ? x.y : x.x;
+    v1 = ci ? -x.x : x.y;
+  }
+}
+
+struct CGemmArgs {
+  const float2* A;
+  int64_t a_row, a_k, a_slot;  // complex strides of A(row, k) within slot l (one of a_row, a_k is 1)
+  int nrows;                   // rows written
+  int rows_alloc;              // rows readable (row loads clamp below it)
+  int kvalid;                  // k < kvalid are real; later k read as zero
+  int nchunks;                 // chunks of 8 complex k over the whole K range
+  const float2* X;
+  int64_t x_k, x_slot;         // complex strides of X(k, b); b contiguous
+  int xk_alloc;                // k rows of X that exist (loads clamp below it)
+  int bp;                      // rupture stride padding (even)
+  float* out;
+  int64_t o_row, o_slot, o_split;  // float strides; column n = 2*b + (0 re | 1 im)
+  int ncols;                   // columns written (2*B)
+  int M, nrt, nct, splits;
+};
+
+// Workgroup = 4 waves in a WR x WC grid; wave tile MF x NF fragments of 16 x 16.
+// Tile: RT = WR*MF*16 rows x NRT = WC*NF*8 ruptures; K in chunks of 8 complex values, the
+// operator and activation tiles of the next chunk loaded while the current one is consumed
+// from LDS (double buffer).  Blocks are decoded so that all tiles of slot l run on XCD l mod 8
+// (workgroups are dealt to the eight XCDs round-robin), keeping a slot's activation panel in
+// one L2.
+template <int MF, int NF, int WR, int WC, bool RCONT, bool CONJ>
+__global__ __launch_bounds__(256, 2) void k_cgemm32(const CGemmArgs p) {
+  static_assert(WR * WC == 4, "four waves");
+  constexpr int RT = WR * MF * 16;
+  constexpr int NRT = WC * NF * 8;
+  constexpr int LDX = NRT + 4;             // padded activation row (float2); even
+  constexpr int A_F4 = RT * 4;             // operator tile: RT rows x 8 complex
+  constexpr int X_F4 = 8 * NRT / 2;        // activation tile: 8 k x NRT ruptures
+  constexpr int T_F4 = A_F4 + X_F4;
+  constexpr int PER_T = (T_F4 + 255) / 256;
+  constexpr int LDS_X = 8 * LDX / 2;
+  __shared__ float4 lds[2][A_F4 + LDS_X];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int ci = lane & 1, kq = lane >> 4;
+  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per_slot = p.nrt * p.nct * p.splits;
+  const int l = x + 8 * (q / per_slot);
+  int rem = q % per_slot;
+  const int split = rem % p.splits;
+  rem /= p.splits;
+  const int ct = rem % p.nct, rt = rem / p.nct;
+  const bool dc = (l == 0);
+  const int c0 = (int)((int64_t)p.nchunks * split / p.splits);
+  const int c1 = (int)((int64_t)p.nchunks * (split + 1) / p.splits);
+  const int row0 = rt * RT, b0 = ct * NRT;
+
+  const float2* Al = p.A + (int64_t)l * p.a_slot;
+  const float2* Xl = p.X + (int64_t)l * p.x_slot;
+
+  // loader: item k of this thread (float4 units), for chunk c
+  auto load = [&](int c, float4 (&st)[PER_T]) {
+#pragma unroll
+    for (int it = 0; it < PER_T; ++it) {
+      const int i = tid + 256 * it;
+      if (i >= T_F4) break;
+      if (i < A_F4) {
+        if (!RCONT) {
+          const int r = i >> 2, cc = i & 3;
+          const int row = min(row0 + r, p.rows_alloc - 1);
+          st[it] = *reinterpret_cast<const float4*>(Al + (int64_t)row * p.a_row + 8 * c + 2 * cc);
+        } else {
+          const int kk = i / (RT / 2), rp = i % (RT / 2);
+          const int k = 8 * c + kk;
+          const int row = min(row0 + 2 * rp, p.rows_alloc - 2);
+          float4 v = *reinterpret_cast<const float4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
+          if (k >= p.kvalid) v = make_float4(0.f, 0.f, 0.f, 0.f);
+          st[it] = v;
+        }
+      } else {
+        const int j = i - A_F4;
+        const int kk = j / (NRT / 2), qq = j % (NRT / 2);
+        const int k = 8 * c + kk;
+        const int b = min(b0 + 2 * qq, p.bp - 2);
+        float4 v = *reinterpret_cast<const float4*>(Xl + (int64_t)min(k, p.xk_alloc - 1) * p.x_k + b);
+        if (k >= p.kvalid) v = make_float4(0.f, 0.f, 0.f, 0.f);
+        st[it] = v;
+      }
+    }
+  };
+  auto put = [&](int buf, const float4 (&st)[PER_T]) {
+#pragma unroll
+    for (int it = 0; it < PER_T; ++it) {
+      const int i = tid + 256 * it;
+      if (i >= T_F4) break;
+      if (i < A_F4) {
+        if (!RCONT) {
+          lds[buf][swz32(i >> 2, i & 3)] = st[it];
+        } else {
+          const int kk = i / (RT / 2), rp = i % (RT / 2);
+          float2* la = reinterpret_cast<float2*>(&lds[buf][0]);
+          la[2 * swz32(2 * rp, kk >> 1) + (kk & 1)] = make_float2(st[it].x, st[it].y);
+          la[2 * swz32(2 * rp + 1, kk >> 1) + (kk & 1)] = make_float2(st[it].z, st[it].w);
+        }
+      } else {
+        const int j = i - A_F4;
+        const int kk = j / (NRT / 2), qq = j % (NRT / 2);
+        lds[buf][A_F4 + (kk * LDX) / 2 + qq] = st[it];
+      }
+    }
+  };
+
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (c0 < c1) {
+    float4 st[PER_T];
+    load(c0, st);
+    put(0, st);
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+      const int cur = (c - c0) & 1;
+      const bool more = c + 1 < c1;
+      if (more) load(c + 1, st);
+      const float4* la = &lds[cur][0];
+      const float2* lx = reinterpret_cast<const float2*>(&lds[cur][A_F4]);
+      float4 av[MF];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) av[a] = la[swz32(wr * MF * 16 + 16 * a + (lane & 15), kq)];
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int rl = wc * NF * 8 + f * 8 + ((lane & 15) >> 1);
+        const float2 x0 = lx[(2 * kq) * LDX + rl];
+        const float2 x1 = lx[(2 * kq + 1) * LDX + rl];
+        float bv[4];
+        embed32<CONJ>(x0, ci, dc, bv[0], bv[1]);
+        embed32<CONJ>(x1, ci, dc, bv[2], bv[3]);
+#pragma unroll
+        for (int a = 0; a < MF; ++a) {
+          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[0], acc[a][f], 0, 0, 0);
+          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[1], acc[a][f], 0, 0, 0);
+          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z, bv[2], acc[a][f], 0, 0, 0);
+          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].w, bv[3], acc[a][f], 0, 0, 0);
+        }
+      }
+      if (more) put(cur ^ 1, st);
+      __syncthreads();
+    }
+  }
+  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + wr * MF * 16 + 16 * a + 4 * kq + r;
+      if (row >= p.nrows) continue;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int n = 2 * b0 + wc * NF * 16 + 16 * f + (lane & 15);
+        if (n < p.ncols) ow[(int64_t)row * p.o_row + n] = acc[a][f][r];
+      }
+    }
+}
+
+// Tile shapes (rows x ruptures): 0: 64 x 128, 1: 128 x 32, 2: 256 x 8, 3: 64 x 64.
+int cgemm32_rows(int cfg) { return cfg == 0 ? 64 : cfg == 1 ? 128 : cfg == 2 ? 256 : 64; }
+int cgemm32_ruptures(int cfg) { return cfg == 0 ? 128 : cfg == 1 ? 32 : cfg == 2 ? 8 : 64; }
+
+template <bool RCONT, bool CONJ>
+static void cgemm32_dispatch(int cfg, dim3 grid, hipStream_t st, const CGemmArgs& a) {
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_cgemm32<2, 8, 2, 2, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_cgemm32<4, 2, 2, 2, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_cgemm32<4, 1, 4, 1, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_cgemm32<2, 4, 2, 2, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+  }
+}
+
+hipError_t launch_cgemm32(int cfg, bool rcont, bool conj, const float2* A, int64_t a_row, int64_t a_k,
+                          int64_t a_slot, int nrows, int rows_alloc, int kvalid, int kpad, const float2* X,
+                          int64_t x_k, int64_t x_slot, int xk_alloc, int B, int bp, float* out, int64_t o_row,
+                          int64_t o_slot, int64_t o_split, int M, int splits, hipStream_t st) {
+  if (cfg < 0 || cfg > 3 || (M & 7) || (bp & 1) || bp < 2 || kpad % 8 || splits < 1) return hipErrorInvalidValue;
+  if (rcont && (rows_alloc < 2 || (rows_alloc & 1))) return hipErrorInvalidValue;
+  CGemmArgs a;
+  a.A = A;
+  a.a_row = a_row;
+  a.a_k = a_k;
+  a.a_slot = a_slot;
+  a.nrows = nrows;
+  a.rows_alloc = rows_alloc;
+  a.kvalid = kvalid;
+  a.nchunks = kpad / 8;
+  a.X = X;
+  a.x_k = x_k;
+  a.x_slot = x_slot;
+  a.xk_alloc = xk_alloc;
+  a.bp = bp;
+  a.out = out;
+  a.o_row = o_row;
+  a.o_slot = o_slot;
+  a.o_split = o_split;
+  a.ncols = 2 * B;
+  a.M = M;
+  a.nrt = (nrows + cgemm32_rows(cfg) - 1) / cgemm32_rows(cfg);
+  a.nct = (B + cgemm32_ruptures(cfg) - 1) / cgemm32_ruptures(cfg);
+  a.splits = splits;
+  const int64_t blocks = (int64_t)M * a.nrt * a.nct * splits;
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+  if (!rcont && !conj) cgemm32_dispatch<false, false>(cfg, grid, st, a);
+  else if (!rcont && conj) cgemm32_dispatch<false, true>(cfg, grid, st, a);
+  else if (rcont && !conj) cgemm32_dispatch<true, false>(cfg, grid, st, a);
+  else cgemm32_dispatch<true, true>(cfg, grid, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace s2w
