@@ -6,8 +6,9 @@ Workload: one GPU's share of the Cascadia-sized problem -- 963 subfaults x
 256 packed bins) -- on seeded synthetic operators and ruptures.
 
 A step is one forward call of the whole map over one batch of ruptures whose
-slip histories are already resident in HBM.  Two paths are timed:
+slip histories are already resident in HBM.  Three paths are timed:
   fp32   single rupture per call, complex64 spectra (the plain path)
+  fp32b  B ruptures per call, complex64 spectra, float32 matrix-core GEMMs
   half   B ruptures per call on the batched matrix-core path with bf16 spectra
 The headline value is the half path's ruptures/s when it is available.
 Operator setup (generation, upload, transforms) is excluded, as in the paper.
@@ -29,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ruptures/s on 963×37,760×64×256 share, batched bf16 vs plain fp32, stated rel-L2"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK = {"bf16": 2500.0, "f16": 2500.0}  # dense matrix-core TFLOP/s
+MFMA_PEAK = {"bf16": 2500.0, "f16": 2500.0, "f32": 157.3}  # dense matrix-core TFLOP/s
 
 
 def log(*a):
@@ -111,7 +112,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,half")
+    ap.add_argument("--paths", default="fp32,fp32b,half",
+                    help="fp32 (single rupture), fp32b (batched float32), half (batched half precision)")
+    ap.add_argument("--batch32", type=int, default=256, help="ruptures per call on the batched float32 path")
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngrid", type=int, default=None, help="override the share size (testing only)")
@@ -189,13 +192,57 @@ def main():
         del op
         torch.cuda.empty_cache()
 
+    bcfg = synth.workload("cascadia_batch")
+    if args.ngrid:
+        bcfg = bcfg.replace(ngrid=args.ngrid)
+    bref = {}
+
+    def batch_oracle(s_host, picks):
+        """FP64 oracle waveforms of ruptures `picks` of the ensemble (each with its own active columns)."""
+        import oracle
+        for b in picks:
+            if b not in bref:
+                bref[b] = oracle.forward_synth(bcfg, s_host[b])
+        return [bref[b] for b in picks]
+
+    # ---------------- batched float32 path ----------------
+    if "fp32b" in paths:
+        import oracle
+        B = args.batch32
+        op = S2WOperator(bcfg.nsub, bcfg.ngrid, bcfg.nobs, bcfg.nt, max_batch=B, dt=bcfg.dt, device=0,
+                         layout="batched")
+        t = time.perf_counter()
+        op.load_operators(*host_generators(bcfg), chunk_rows=1024)
+        setup_s = time.perf_counter() - t
+        nb = 2
+        s_host = synth.gen_slip_batch(bcfg, 0, nb * B)
+        s_dev = torch.tensor(s_host, device=dev).reshape(nb, B, bcfg.nsub, bcfg.nt)
+        total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, B)
+        ms_step = total_ms / args.steps
+        kmean = float(np.mean(kern_ms))
+        flops_g = 8.0 * bcfg.ngrid * bcfg.nsub * bcfg.nt * B
+        fp32b = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "kernel": "k_cgemm32",
+                 "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)), "algorithmic_flops": flops_g,
+                 "achieved_TFLOPs": flops_g / (kmean * 1e9),
+                 "mfma_frac": flops_g / (kmean * 1e9) / MFMA_PEAK["f32"], "setup_s": setup_s}
+        log(f"fp32 batched B={B}: {ms_step:.3f} ms/call, {fp32b['ruptures_per_s']:.0f} ruptures/s, "
+            f"elastic GEMM {kmean:.3f} ms = {fp32b['achieved_TFLOPs']:.1f} TFLOP/s")
+        if not args.no_cpu_baseline:
+            y = op.forward(s_dev[0]).cpu().numpy().astype(np.float64)
+            act = [int(np.count_nonzero(np.any(s_host[b] != 0, axis=1))) for b in range(B)]
+            pick = sorted({int(np.argmin(act)), 0})
+            errs = [oracle.rel_l2(y[b], r) for b, r in zip(pick, batch_oracle(s_host, pick))]
+            fp32b["rel_l2_sampled"] = {str(b): e for b, e in zip(pick, errs)}
+            fp32b["rel_l2"] = max(errs)
+            log(f"fp32 batched rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
+        result["fp32b"] = fp32b
+        del op
+        torch.cuda.empty_cache()
+
     # ---------------- batched half-precision path ----------------
     if "half" in paths:
         B = args.batch
         gdt, fdt = args.half_dtype.split("/") if "/" in args.half_dtype else (args.half_dtype, args.half_dtype)
-        bcfg = synth.workload("cascadia_batch")
-        if args.ngrid:
-            bcfg = bcfg.replace(ngrid=args.ngrid)
         op = S2WOperator(bcfg.nsub, bcfg.ngrid, bcfg.nobs, bcfg.nt, max_batch=B, dt=bcfg.dt, device=0,
                          g_dtype=gdt, f_dtype=fdt)
         t = time.perf_counter()
@@ -221,8 +268,7 @@ def main():
             y = op.forward(s_dev[0]).cpu().numpy().astype(np.float64)
             act = [int(np.count_nonzero(np.any(s_host[b] != 0, axis=1))) for b in range(B)]
             pick = sorted({int(np.argmin(act)), int(np.argmax(act)), 0, 1})
-            y_ref = oracle.forward_synth(bcfg, s_host[pick])
-            errs = [oracle.rel_l2(y[b], y_ref[i]) for i, b in enumerate(pick)]
+            errs = [oracle.rel_l2(y[b], r) for b, r in zip(pick, batch_oracle(s_host, pick))]
             half["rel_l2_sampled"] = {str(b): e for b, e in zip(pick, errs)}
             half["rel_l2"] = max(errs)
             log(f"half rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
@@ -263,6 +309,8 @@ def main():
         "cpu_baseline": result.get("cpu_baseline"),
         "rel_l2": head.get("rel_l2"),
         "speedup_vs_fp32": (half["ruptures_per_s"] / fp32["ruptures_per_s"]) if (half and fp32) else None,
+        "speedup_fp32_batched_vs_fp32": (result["fp32b"]["ruptures_per_s"] / fp32["ruptures_per_s"])
+        if ("fp32b" in result and fp32) else None,
         "paths": {k: v for k, v in result.items() if k != "cpu_baseline"},
         "source_hash": src_hash,
     }

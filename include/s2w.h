@@ -143,8 +143,10 @@ typedef struct s2w_tuning {
   int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..9 fixed shapes, 4 = narrow */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
   int32_t fgemm_lds;         /* batched acoustic GEMM (bf16): 1 LDS-staged kernel, -1 register kernel */
-  int32_t gemm32_cfg;        /* batched float32 GEMM tile: -1 automatic, 1..4 = tile shapes 0..3 (rows x ruptures:
-                                64 x 128, 128 x 32, 256 x 8, 64 x 64) */
+  int32_t gemm32_cfg;        /* batched float32 GEMMs over grid rows (forward elastic, adjoint acoustic): tile,
+                                -1 automatic, 1..4 = rows x ruptures 64 x 128, 128 x 32, 256 x 8, 64 x 64 */
+  int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint
+                                elastic): tile, same values */
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
   int32_t adj32_splits;      /* batched float32 adjoint, transposed elastic GEMM: grid-row splits (1..8) */
 } s2w_tuning;
@@ -162,6 +164,9 @@ s2w_status s2w_set_profile_events(s2w_plan* plan, void* begin, void* end);
  * number of stored complex values per spectrum, L/2 (bins 0 and L/2 are real
  * and share one slot). */
 s2w_status s2w_transform_length(const s2w_plan* plan, int32_t* L);
+
+/* The layout the plan resolved S2W_LAYOUT_AUTO to: S2W_LAYOUT_SINGLE or S2W_LAYOUT_BATCHED. */
+s2w_status s2w_plan_layout(const s2w_plan* plan, int32_t* layout);
 
 const char* s2w_status_string(s2w_status st);
 const char* s2w_last_error(const s2w_plan* plan);

@@ -37,12 +37,12 @@ class Tuning(ctypes.Structure):
     _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_cols", ctypes.c_int32),
                 ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32), ("gemm_cfg", ctypes.c_int32),
                 ("fgemm_splits", ctypes.c_int32), ("fgemm_lds", ctypes.c_int32), ("gemm32_cfg", ctypes.c_int32),
-                ("gemm32_splits", ctypes.c_int32), ("adj32_splits", ctypes.c_int32)]
+                ("gemm32_cfg_k", ctypes.c_int32), ("gemm32_splits", ctypes.c_int32), ("adj32_splits", ctypes.c_int32)]
 
 
 EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_create", "s2w_plan_destroy",
            "s2w_query_sizes", "s2w_bind_memory", "s2w_set_operators", "s2w_forward", "s2w_adjoint",
-           "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events"]
+           "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events", "s2w_plan_layout"]
 
 _lib = None
 
@@ -74,6 +74,7 @@ def load_library(path: str | None = None):
     lib.s2w_get_tuning.argtypes = [plan_p, P(Tuning)]
     lib.s2w_transform_length.argtypes = [plan_p, P(i32)]
     lib.s2w_set_profile_events.argtypes = [plan_p, vp, vp]
+    lib.s2w_plan_layout.argtypes = [plan_p, P(i32)]
     for name in EXPORTS:
         if name not in ("s2w_abi_version", "s2w_status_string", "s2w_last_error"):
             getattr(lib, name).restype = i32
@@ -121,6 +122,11 @@ class Plan:
         L = ctypes.c_int32()
         self._check(self.lib.s2w_transform_length(self.handle, ctypes.byref(L)), "s2w_transform_length")
         return L.value
+
+    def layout(self) -> str:
+        v = ctypes.c_int32()
+        self._check(self.lib.s2w_plan_layout(self.handle, ctypes.byref(v)), "s2w_plan_layout")
+        return {1: "single", 2: "batched"}[v.value]
 
     def bind(self, op_ptr: int, op_bytes: int, ws_ptr: int, ws_bytes: int):
         self._check(self.lib.s2w_bind_memory(self.handle, op_ptr, op_bytes, ws_ptr, ws_bytes), "s2w_bind_memory")

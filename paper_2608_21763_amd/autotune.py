@@ -1,0 +1,100 @@
+"""Tile-shape autotuner for an ``S2WOperator``.
+
+Times every candidate kernel shape of the operator's path for a batch of B ruptures with
+HIP events on the current stream and keeps the fastest through ``s2w_set_tuning``.  The
+candidates differ only in how work is tiled: every shape accumulates each output over the
+same K steps in the same order, so the choice never changes the numbers for a fixed
+split count, and the split counts stay on their defaults.
+
+Results can be cached in a JSON file keyed by the problem shape, the dtypes, the layout,
+B and the device name, so that a later process applies the stored choice without timing.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import torch
+
+from .hiprt import HipEvent
+
+
+def candidates(op) -> list[dict]:
+    """Tuning dictionaries worth timing for this operator's path."""
+    if op.g_dtype != "f32":
+        return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 1, 2, 3, 5, 6, 7, 8, 9) for f in (1, -1)]
+    if op.plan_layout() == "batched":
+        return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
+    return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]
+
+
+def _key(op, B: int) -> str:
+    name = torch.cuda.get_device_name(op.device)
+    return (f"{name}|{op.nsub}x{op.ngrid}x{op.nobs}x{op.nt}|{op.g_dtype}/{op.f_dtype}|{op.plan_layout()}|B={B}"
+            f"|diff={op.diff}")
+
+
+def _time(op, fn, reps: int) -> float:
+    stream = torch.cuda.current_stream(op.device).cuda_stream
+    fn()  # warm-up (first launch of each kernel shape)
+    best = float("inf")
+    for _ in range(reps):
+        t0, t1 = HipEvent(), HipEvent()
+        t0.record(stream)
+        fn()
+        t1.record(stream)
+        t1.synchronize()
+        best = min(best, t0.elapsed_ms(t1))
+    return best
+
+
+def autotune(op, B: int, reps: int = 3, adjoint: bool | None = None, cache_path: str | None = None,
+             s: torch.Tensor | None = None) -> dict:
+    """Pick the fastest tile shapes of ``op`` for batches of B and apply them.
+
+    The objective is the time of one forward call, plus one adjoint call when ``adjoint``
+    is true (default: whenever the path has an adjoint).  Returns
+    ``{"best": tuning, "ms": time, "results": [(tuning, ms), ...], "cached": bool}``.
+    """
+    if not 1 <= B <= op.max_batch:
+        raise ValueError(f"B={B} outside [1, {op.max_batch}]")
+    key = _key(op, B)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            op.set_tuning(**cache[key]["best"])
+            return dict(cache[key], cached=True)
+    if adjoint is None:
+        adjoint = op.g_dtype == "f32"
+    dev = op.device
+    if s is None:
+        s = torch.randn((B, op.nsub, op.nt), device=dev, dtype=torch.float32)
+    y = torch.empty((B, op.nobs, op.nt), device=dev, dtype=torch.float32)
+    r = torch.randn((B, op.nobs, op.nt), device=dev, dtype=torch.float32) if adjoint else None
+    gs = torch.empty((B, op.nsub, op.nt), device=dev, dtype=torch.float32) if adjoint else None
+    base = op.get_tuning()
+    results = []
+    for cand in candidates(op):
+        op.set_tuning(**cand)
+
+        def call():
+            op.forward(s, out=y)
+            if adjoint:
+                op.adjoint(r, out=gs)
+
+        results.append((cand, _time(op, call, reps)))
+    best, ms = min(results, key=lambda t: t[1])
+    restore = {k: base[k] for k in best}
+    op.set_tuning(**restore)
+    op.set_tuning(**best)
+    out = {"best": best, "ms": ms, "results": results, "cached": False}
+    if cache_path:
+        cache[key] = {"best": best, "ms": ms, "results": results}
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(cache, fh, indent=1)
+        os.replace(tmp, cache_path)
+    return out

@@ -315,6 +315,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.fgemm_splits = 0;
   p->tune.fgemm_lds = 1;
   p->tune.gemm32_cfg = -1;
+  p->tune.gemm32_cfg_k = -1;
   p->tune.gemm32_splits = 0;
   p->tune.adj32_splits = 0;
   p->row_set.assign((size_t)d.ngrid, 0);
@@ -343,6 +344,12 @@ s2w_status s2w_query_sizes(const s2w_plan* p, uint64_t* operator_bytes, uint64_t
   if (!p) return S2W_EINVAL;
   if (operator_bytes) *operator_bytes = p->lay.op_total;
   if (workspace_bytes) *workspace_bytes = p->lay.ws_total;
+  return S2W_OK;
+}
+
+s2w_status s2w_plan_layout(const s2w_plan* p, int32_t* layout) {
+  if (!p || !layout) return S2W_EINVAL;
+  *layout = (p->hg.on || p->fb.on) ? S2W_LAYOUT_BATCHED : S2W_LAYOUT_SINGLE;
   return S2W_OK;
 }
 
@@ -412,6 +419,10 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     if (t->gemm32_cfg < -1 || t->gemm32_cfg > 4) return fail(p, S2W_EINVAL, "tuning: gemm32_cfg");
     n.gemm32_cfg = t->gemm32_cfg < 0 ? -1 : t->gemm32_cfg - 1;
   }
+  if (t->gemm32_cfg_k) {
+    if (t->gemm32_cfg_k < -1 || t->gemm32_cfg_k > 4) return fail(p, S2W_EINVAL, "tuning: gemm32_cfg_k");
+    n.gemm32_cfg_k = t->gemm32_cfg_k < 0 ? -1 : t->gemm32_cfg_k - 1;
+  }
   if (t->gemm32_splits) {
     if (t->gemm32_splits < 0 || t->gemm32_splits > 16) return fail(p, S2W_EINVAL, "tuning: gemm32_splits");
     n.gemm32_splits = t->gemm32_splits;
@@ -432,6 +443,7 @@ s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   if (!p || !t) return S2W_EINVAL;
   *t = p->tune;
   t->gemm32_cfg = p->tune.gemm32_cfg < 0 ? -1 : p->tune.gemm32_cfg + 1;
+  t->gemm32_cfg_k = p->tune.gemm32_cfg_k < 0 ? -1 : p->tune.gemm32_cfg_k + 1;
   return S2W_OK;
 }
 
@@ -622,11 +634,16 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
 }
 
 // Default tile of the batched float32 GEMMs for a batch of B (rows x ruptures: 0 = 64 x 128,
-// 1 = 128 x 32, 2 = 256 x 8, 3 = 64 x 64).
+// 1 = 128 x 32, 2 = 256 x 8, 3 = 64 x 64), from a sweep on the Cascadia-sized share: the
+// products over all grid rows favour tall tiles, the grid-row reductions (few output rows)
+// wide ones once the batch fills them.
 static int b32_cfg(const s2w_plan* p, int B, bool few_rows) {
+  if (few_rows) {
+    if (p->tune.gemm32_cfg_k >= 0) return p->tune.gemm32_cfg_k;
+    return B <= 8 ? 2 : (B <= 64 ? 3 : 0);
+  }
   if (p->tune.gemm32_cfg >= 0) return p->tune.gemm32_cfg;
-  if (few_rows) return B > 64 ? 0 : 3;
-  return B <= 8 ? 2 : (B <= 32 ? 1 : (B <= 64 ? 3 : 0));
+  return B <= 64 ? 2 : 1;
 }
 
 static int b32_splits(int tuned, int maxs, int M, int nrows, int B, int cfg) {

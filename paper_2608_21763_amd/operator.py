@@ -96,6 +96,10 @@ class S2WOperator:
                 progress(r0 + n, self.ngrid)
         torch.cuda.synchronize(self.device)
 
+    def plan_layout(self) -> str:
+        """"single" or "batched": the storage layout the plan uses."""
+        return self.plan.layout()
+
     def set_tuning(self, **kw):
         self.plan.set_tuning(**kw)
 

@@ -106,13 +106,15 @@ def test_tile_shapes_bit_identical(B):
     r = to_dev(synth.normals(7, "r", 0, (B, cfg.nobs, cfg.nt)))
     ys, gs = {}, {}
     for c in (1, 2, 3, 4):
-        op.set_tuning(gemm32_cfg=c, gemm32_splits=3, adj32_splits=2)
-        ys[c] = op.forward(s).clone()
-        gs[c] = op.adjoint(r).clone()
+        for ck in (1, 2, 3, 4):
+            op.set_tuning(gemm32_cfg=c, gemm32_cfg_k=ck, gemm32_splits=3, adj32_splits=2)
+            ys[c, ck] = op.forward(s).clone()
+            gs[c, ck] = op.adjoint(r).clone()
+    first = (1, 1)
     for c in ys:
-        assert torch.equal(ys[c], ys[1]) and torch.equal(gs[c], gs[1]), f"tile shape {c} differs"
+        assert torch.equal(ys[c], ys[first]) and torch.equal(gs[c], gs[first]), f"tile shapes {c} differ"
     G, F = _oracle_ops(cfg)
-    assert oracle.rel_l2_per_rupture(ys[1].cpu().numpy(), oracle.forward(G, F, s.cpu().numpy())).max() <= TOL
+    assert oracle.rel_l2_per_rupture(ys[first].cpu().numpy(), oracle.forward(G, F, s.cpu().numpy())).max() <= TOL
 
 
 def test_layouts_agree():
