@@ -43,6 +43,7 @@ KERNEL_SOURCES = {
     "k_mid_batch256": ["s2w_fft_kernels.hip", "s2w_device.h"],
     "k_gemm_g": ["s2w_mfma_kernels.hip"],
     "k_gemm_g2": ["s2w_mfma_kernels.hip"],
+    "k_gemm_g4": ["s2w_mfma_kernels.hip"],
     "k_gemm_f2": ["s2w_mfma_kernels.hip"],
     "k_cgemm32": ["s2w_mfma32_kernels.hip"],
 }
@@ -75,7 +76,7 @@ def traffic_for(kernel: str):
 
 def elastic_kernel(B: int) -> str:
     """Kernel of the batched elastic GEMM the library picks by default for a batch of B."""
-    return "k_gemm_g" if B <= 64 else "k_gemm_g2"
+    return "k_gemm_g" if B <= 64 else "k_gemm_g4"
 
 
 def time_path(op, s_dev, steps: int, warmup: int, B: int):

@@ -411,7 +411,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
   }
   if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
   if (t->gemm_cfg) {
-    if (t->gemm_cfg < -1 || t->gemm_cfg > 9) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    if (t->gemm_cfg < -1 || t->gemm_cfg > 14) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) n.fgemm_lds = t->fgemm_lds > 0 ? 1 : 0;
@@ -583,7 +583,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int bp = h.bp;
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
-  if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 5);
+  if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 10);
   // acoustic GEMM: the LDS-staged kernel serves the packed bfloat16 activation when its tile fits
   const bool packed = h.ht_f == 1 && h.hterms_f == 2;
   const bool fstaged = packed && p->tune.fgemm_lds != 0 && gemm_f2_supported(h.noq, B);
@@ -593,7 +593,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
   splits = std::min(splits, h.splits_max);
   hipError_t e = launch_rfft_rows(s, B, g.nsub, h.nsq, S, 1, bp, (int64_t)h.nsq * bp, g, 1.0f, st);
-  const bool compact = cfg >= 7;
+  const bool compact = cfg >= 7 && cfg <= 9;
   if (e == hipSuccess) {
     if (compact)
       e = launch_prep_act_compact(h.ht_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (uint2*)Bop, st);

@@ -610,6 +610,167 @@ __global__ __launch_bounds__(512, 1) void k_gemm_g2(const uint4* __restrict__ Gq
   }
 }
 
+// Elastic GEMM fed by direct global-to-LDS copies (global_load_lds_dwordx4): the same tile
+// and wave arrangement as k_gemm_g2, but the operator and activation tiles of a K step
+// travel from global memory to LDS without passing through registers, so NS stages can be in
+// flight at once (NS - 1 K steps ahead of the matrix cores).  A copy instruction moves 1 KB
+// per wave, lane p landing at byte 16*p of the wave's LDS target; for the operator tile the
+// lanes are assigned so that this linear placement is the chunk-swizzled layout the fragment
+// reads expect, and the activation blocks are already stored in fragment order.
+// Copies of K step ks (clamped to the last step: copies past the end land in a stage that is
+// never read) into `stage`; every wave issues PER_W of them.
+template <int PER_W, int NWAVE>
+__device__ __forceinline__ void g4_issue(const uint4* const* src, const int64_t* sstep, int ks, int nks, uint4* stage,
+                                         int wave) {
+  const int kc = min(ks, nks - 1);
+#pragma unroll
+  for (int q = 0; q < PER_W; ++q)
+    __builtin_amdgcn_global_load_lds(src[q] + (int64_t)kc * sstep[q],
+                                     (__attribute__((address_space(3))) void*)(stage + (wave + NWAVE * q) * 64), 16, 0,
+                                     0);
+}
+
+// Wait for this wave's copies of the current step (at most the NS - 2 later steps' copies stay
+// in flight), then a workgroup barrier without a memory fence; the empty asm statements keep
+// the compiler from moving LDS accesses across it.
+template <int PENDING>
+__device__ __forceinline__ void g4_sync() {
+  __builtin_amdgcn_s_waitcnt(0x0F70 | PENDING);
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+template <int HT, int H, int MF, int NF, int MW, int A_BLK, int WC>
+__device__ __forceinline__ void g4_compute(const uint4* cur, f32x4 (&acc)[MF][NF], int wr, int wc, int lane) {
+  const uint4* lb = cur + A_BLK * 64;
+  uint4 av[MF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a) av[a] = cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+  for (int b = 0; b < NF; ++b)
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint4 bv = lb[((wc * NF + b) * H + h) * 64 + lane];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bv, acc[a][b]);
+    }
+  (void)WC;
+}
+
+template <int HT, int H, int MW, int NW, int NS, int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g4(const uint4* __restrict__ Gq, const float* __restrict__ sG,
+                                                    const uint4* __restrict__ Bop, const float* __restrict__ sig_down,
+                                                    float* __restrict__ U, int ngrid, int M, int nks, int ncb, int B,
+                                                    int bp, int nrb, int nct) {
+  constexpr int MF = MW / 16, NF = NW / 16;
+  constexpr int NWAVE = WR * WC;
+  constexpr int RT = WR * MW;                // rows per tile
+  constexpr int CBT = WC * NF;               // column blocks per tile
+  constexpr int A_BLK = RT / 16;             // 1 KB copy blocks of the operator tile per K step
+  constexpr int B_BLK = CBT * H;             // 1 KB copy blocks of the activation tile per K step
+  constexpr int NBLK = A_BLK + B_BLK;
+  constexpr int PER_W = NBLK / NWAVE;        // copy instructions per wave per K step
+  constexpr int STAGE = NBLK * 64;           // uint4 per stage
+  constexpr int PENDING = (NS - 2) * PER_W;  // copies of later steps allowed in flight
+  static_assert(NBLK % NWAVE == 0, "every wave issues the same number of copies per K step");
+  static_assert(NS >= 2 && NS <= 4 && PENDING < 16, "stages and wait counts");
+  // one LDS object per stage, so that the compiler can tell the stages apart when it orders
+  // the fragment reads after the copies
+  __shared__ uint4 st0[STAGE];
+  __shared__ uint4 st1[STAGE];
+  __shared__ uint4 st2[NS > 2 ? STAGE : 1];
+  __shared__ uint4 st3[NS > 3 ? STAGE : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int nwg = gridDim.x, w = blockIdx.x;
+  const int nx = 8 < M ? 8 : M;
+  const int x = w % nx, wi = w / nx, nwx = (nwg - x + nx - 1) / nx;
+  const int slots_x = (M - x + nx - 1) / nx;
+  const int64_t per_slot = (int64_t)nrb * nct;
+  const int64_t items = (int64_t)slots_x * per_slot;
+  const int64_t row_u4 = (int64_t)nks * 4;
+  // operator lanes: block row rr = lane/4, chunk c such that the linear LDS slot is swz(rr, c)
+  const int a_rr = lane >> 2, a_c = (lane & 3) ^ ((a_rr >> 1) & 3);
+  for (int64_t it = wi; it < items; it += nwx) {
+    const int l = x + nx * (int)(it / per_slot);
+    const int64_t rem = it % per_slot;
+    const int rb = (int)(rem / nct), ct = (int)(rem % nct);
+    const int g0 = rb * RT;
+    const int cbt0 = ct * CBT;
+    // per copy slot of this wave: global source at K step 0 and its stride per K step
+    const uint4* src[PER_W];
+    int64_t sstep[PER_W];
+#pragma unroll
+    for (int q = 0; q < PER_W; ++q) {
+      const int blk = wave + NWAVE * q;
+      if (blk < A_BLK) {
+        const int g = min(g0 + 16 * blk + a_rr, ngrid - 1);
+        src[q] = Gq + ((int64_t)g * M + l) * row_u4 + a_c;
+        sstep[q] = 4;
+      } else {
+        const int j = blk - A_BLK;
+        const int cb = min(cbt0 + j / H, ncb - 1), h = j % H;
+        src[q] = Bop + (((int64_t)l * nks * ncb + cb) * H + h) * 64 + lane;
+        sstep[q] = (int64_t)ncb * H * 64;
+      }
+    }
+    f32x4 acc[MF][NF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // every copy of the previous item has landed and every wave is past its reads
+    g4_sync<0>();
+    g4_issue<PER_W, NWAVE>(src, sstep, 0, nks, st0, wave);
+    if (NS > 2) g4_issue<PER_W, NWAVE>(src, sstep, 1, nks, st1, wave);
+    if (NS > 3) g4_issue<PER_W, NWAVE>(src, sstep, 2, nks, st2, wave);
+    // step ks reads stage ks % NS and refills stage (ks - 1) % NS with step ks + NS - 1; every
+    // step issues its copies so that the count in flight is the same on every path
+#define S2W_G4_STEP(K, CUR, NEXT)                                      \
+  do {                                                                  \
+    g4_sync<PENDING>();                                                 \
+    g4_issue<PER_W, NWAVE>(src, sstep, (K) + NS - 1, nks, NEXT, wave);  \
+    if ((K) < nks) g4_compute<HT, H, MF, NF, MW, A_BLK, WC>(CUR, acc, wr, wc, lane); \
+  } while (0)
+    for (int k0 = 0; k0 < nks; k0 += NS) {
+      if (NS == 2) {
+        S2W_G4_STEP(k0, st0, st1);
+        S2W_G4_STEP(k0 + 1, st1, st0);
+      } else if (NS == 3) {
+        S2W_G4_STEP(k0, st0, st2);
+        S2W_G4_STEP(k0 + 1, st1, st0);
+        S2W_G4_STEP(k0 + 2, st2, st1);
+      } else {
+        S2W_G4_STEP(k0, st0, st3);
+        S2W_G4_STEP(k0 + 1, st1, st0);
+        S2W_G4_STEP(k0 + 2, st2, st1);
+        S2W_G4_STEP(k0 + 3, st3, st2);
+      }
+    }
+#undef S2W_G4_STEP
+#pragma unroll
+    for (int a = 0; a < MF; ++a)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int g = g0 + wr * MW + 16 * a + 4 * (lane >> 4) + r;
+        if (g >= ngrid) continue;
+        const float sg = sG[(int64_t)g * M + l];
+#pragma unroll
+        for (int b = 0; b < NF; ++b) {
+          const int cb = cbt0 + wc * NF + b;
+          const int n = 16 * cb + (lane & 15);
+          const int rup = n >> 1;
+          if (cb < ncb && rup < B)
+            U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
+                acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+        }
+      }
+  }
+  // no copy into LDS may still be in flight when the workgroup ends
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 template <int HT, int H>
 static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint4* Bop, const float* sig_down,
                            float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp, hipStream_t st) {
@@ -637,6 +798,40 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
       else
         hipLaunchKernelGGL((k_gemm_g2<HT, H, 64, 128>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
                            nks, ncb, B, bp, nrb, nct);
+      break;
+    }
+    case 10:
+    case 11:
+    case 12: {
+      // direct-to-LDS copies: 10 = 256 x 256 (three stages), 11 = 128 x 512 (two stages),
+      // 12 = 256 x 128 (four stages)
+      const int MW = cfg == 11 ? 64 : 128, NW = cfg == 11 ? 128 : (cfg == 12 ? 32 : 64);
+      const int nrb = (ngrid + 2 * MW - 1) / (2 * MW);
+      const int nct = (ncb + 4 * (NW / 16) - 1) / (4 * (NW / 16));
+      if (cfg == 10)
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 3, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
+                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      else if (cfg == 11)
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 64, 128, 2, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
+                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      else
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 32, 4, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
+                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      break;
+    }
+    case 13:
+    case 14: {
+      // direct-to-LDS copies, one wave per SIMD with 128 x 128 wave tiles (accumulators in the
+      // extended register file): 13 = 256 x 256 (three stages), 14 = 128 x 512 (two stages)
+      const int WR = cfg == 13 ? 2 : 1, WC = cfg == 13 ? 2 : 4;
+      const int nrb = (ngrid + 128 * WR - 1) / (128 * WR);
+      const int nct = (ncb + 8 * WC - 1) / (8 * WC);
+      if (cfg == 13)
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 3, 2, 2>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop, sig_down,
+                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      else
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 2, 1, 4>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop, sig_down,
+                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
       break;
     }
     default: return hipErrorInvalidValue;
