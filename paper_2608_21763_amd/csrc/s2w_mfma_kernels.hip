@@ -658,8 +658,8 @@ __device__ __forceinline__ void g4_compute(const uint4* cur, f32x4 (&acc)[MF][NF
   (void)WC;
 }
 
-template <int HT, int H, int MW, int NW, int NS, int WR, int WC>
-__global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g4(const uint4* __restrict__ Gq, const float* __restrict__ sG,
+template <int HT, int H, int MW, int NW, int NS, int WR, int WC, int MINB = 1>
+__global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __restrict__ Gq, const float* __restrict__ sG,
                                                     const uint4* __restrict__ Bop, const float* __restrict__ sig_down,
                                                     float* __restrict__ U, int ngrid, int M, int nks, int ncb, int B,
                                                     int bp, int nrb, int nct) {
@@ -817,6 +817,21 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
       else
         hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 32, 4, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
                            U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      break;
+    }
+    case 15:
+    case 16: {
+      // direct-to-LDS copies, four waves, two stages, two workgroups per compute unit:
+      // 15 = 128 x 256, 16 = 256 x 128
+      const int MW = cfg == 15 ? 64 : 128, NW = cfg == 15 ? 128 : 64;
+      const int nrb = (ngrid + 2 * MW - 1) / (2 * MW);
+      const int nct = (ncb + 2 * (NW / 16) - 1) / (2 * (NW / 16));
+      if (cfg == 15)
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 64, 128, 2, 2, 2, 2>), dim3(2 * nwg), dim3(256), 0, st, Gq, sG, Bop,
+                           sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      else
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 2, 2, 2, 2>), dim3(2 * nwg), dim3(256), 0, st, Gq, sG, Bop,
+                           sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);
       break;
     }
     case 13:
