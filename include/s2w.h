@@ -165,6 +165,43 @@ s2w_status s2w_set_profile_events(s2w_plan* plan, void* begin, void* end);
  * and share one slot). */
 s2w_status s2w_transform_length(const s2w_plan* plan, int32_t* L);
 
+/* ---------------------------------------------------------------------------------------
+ * One block lower-triangular Toeplitz operator on its own (Alg. 2, Sec. II-C1):
+ *   y_n = sum_{k=0}^{n} F_k x_{n-k},  F_k in R^{nrow x ncol},  n < nt,
+ * evaluated by zero-padding to L, a real FFT, one complex product per bin and the inverse
+ * FFT truncated to nt.  With F_k = F_{G,k} restricted to a share's rows this gives the
+ * seafloor displacement of eq. (1) (x = slip rate, y = displacement per grid row); with
+ * F_k = F_{q,k} restricted to a share's columns, eq. (2) (x = seafloor motion, y = the
+ * share's partial waveforms).  Float32 spectra in a per-bin GEMM layout; products on the
+ * matrix cores for every batch size.  The conventions of the map's entry points apply
+ * (caller-owned 256-byte aligned device memory, host-side validation before any enqueue,
+ * asynchronous on `stream`, no allocation, deterministic, no exceptions).
+ * Limits: 1 <= nt <= 512, 1 <= nrow, ncol <= 2^24, 0 <= max_batch <= 1024. */
+typedef struct s2w_bltt s2w_bltt;
+
+typedef struct s2w_bltt_desc {
+  int32_t nrow;       /* rows of each block F_k (output channels) */
+  int32_t ncol;       /* columns of each block F_k (input channels) */
+  int32_t nt;         /* time steps */
+  int32_t max_batch;  /* largest number of input histories per call */
+} s2w_bltt_desc;
+
+s2w_status s2w_bltt_create(const s2w_bltt_desc* desc, int32_t device, s2w_bltt** out);
+s2w_status s2w_bltt_destroy(s2w_bltt* op);
+s2w_status s2w_bltt_query_sizes(const s2w_bltt* op, uint64_t* operator_bytes, uint64_t* workspace_bytes);
+/* Same contract as s2w_bind_memory; re-binding discards the blocks set so far. */
+s2w_status s2w_bltt_bind_memory(s2w_bltt* op, void* operator_store, uint64_t operator_bytes, void* workspace,
+                                uint64_t workspace_bytes);
+/* Spectra of rows [row0, row0+nrows): F_chunk[r][c][k] = [F_k]_{row0+r, c}, float32
+ * [nrows][ncol][nt] (device, row-major).  Chunks in any order; apply and adjoint require
+ * every row to have been set since the last bind. */
+s2w_status s2w_bltt_set_blocks(s2w_bltt* op, const float* F_chunk, int64_t row0, int64_t nrows, void* stream);
+/* y[b][r][n] = sum_c sum_{k<=n} [F_k]_{r,c} x[b][c][n-k]: x float32 [B][ncol][nt], y float32 [B][nrow][nt]. */
+s2w_status s2w_bltt_apply(s2w_bltt* op, const float* x, int32_t B, float* y, void* stream);
+/* Transpose: x[b][c][n] = sum_r sum_{k<nt-n} [F_k]_{r,c} y[b][r][n+k]. */
+s2w_status s2w_bltt_adjoint(s2w_bltt* op, const float* y, int32_t B, float* x, void* stream);
+const char* s2w_bltt_last_error(const s2w_bltt* op);
+
 /* The layout the plan resolved S2W_LAYOUT_AUTO to: S2W_LAYOUT_SINGLE or S2W_LAYOUT_BATCHED. */
 s2w_status s2w_plan_layout(const s2w_plan* plan, int32_t* layout);
 

@@ -5,7 +5,7 @@ C-ABI declared in ``include/s2w.h``); this package only marshals arguments.
 ``S2WOperator`` owns the device memory (allocated with PyTorch) and
 ``SourceToWaveform`` exposes the map to ``torch.autograd``.
 """
-from .abi import S2WError, Plan, load_library, DTYPES, DIFF_NONE, DIFF_BACKWARD  # noqa: F401
-from .operator import S2WOperator, SourceToWaveform, source_to_waveform  # noqa: F401
+from .abi import S2WError, Plan, Bltt, load_library, DTYPES, DIFF_NONE, DIFF_BACKWARD  # noqa: F401
+from .operator import S2WOperator, SourceToWaveform, source_to_waveform, BLTTOperator  # noqa: F401
 from .sizes import spectral_store_bytes, algorithmic_bytes  # noqa: F401
 from .autotune import autotune  # noqa: F401

@@ -33,6 +33,11 @@ class Desc(ctypes.Structure):
                 ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class BlttDesc(ctypes.Structure):
+    _fields_ = [("nrow", ctypes.c_int32), ("ncol", ctypes.c_int32), ("nt", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("fused_wg_per_cu", ctypes.c_int32), ("fused_rows", ctypes.c_int32), ("adj_cols", ctypes.c_int32),
                 ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32), ("gemm_cfg", ctypes.c_int32),
@@ -42,7 +47,9 @@ class Tuning(ctypes.Structure):
 
 EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_create", "s2w_plan_destroy",
            "s2w_query_sizes", "s2w_bind_memory", "s2w_set_operators", "s2w_forward", "s2w_adjoint",
-           "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events", "s2w_plan_layout"]
+           "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events", "s2w_plan_layout",
+           "s2w_bltt_create", "s2w_bltt_destroy", "s2w_bltt_query_sizes", "s2w_bltt_bind_memory",
+           "s2w_bltt_set_blocks", "s2w_bltt_apply", "s2w_bltt_adjoint", "s2w_bltt_last_error"]
 
 _lib = None
 
@@ -75,8 +82,17 @@ def load_library(path: str | None = None):
     lib.s2w_transform_length.argtypes = [plan_p, P(i32)]
     lib.s2w_set_profile_events.argtypes = [plan_p, vp, vp]
     lib.s2w_plan_layout.argtypes = [plan_p, P(i32)]
+    lib.s2w_bltt_create.argtypes = [P(BlttDesc), i32, P(vp)]
+    lib.s2w_bltt_destroy.argtypes = [vp]
+    lib.s2w_bltt_query_sizes.argtypes = [vp, P(u64), P(u64)]
+    lib.s2w_bltt_bind_memory.argtypes = [vp, vp, u64, vp, u64]
+    lib.s2w_bltt_set_blocks.argtypes = [vp, vp, i64, i64, vp]
+    lib.s2w_bltt_apply.argtypes = [vp, vp, i32, vp, vp]
+    lib.s2w_bltt_adjoint.argtypes = [vp, vp, i32, vp, vp]
+    lib.s2w_bltt_last_error.restype = ctypes.c_char_p
+    lib.s2w_bltt_last_error.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("s2w_abi_version", "s2w_status_string", "s2w_last_error"):
+        if name not in ("s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_bltt_last_error"):
             getattr(lib, name).restype = i32
     if path is None:
         _lib = lib
@@ -152,3 +168,50 @@ class Plan:
     def set_tuning(self, **kw):
         t = Tuning(**{n: int(kw.get(n, 0)) for n, _ in Tuning._fields_})
         self._check(self.lib.s2w_set_tuning(self.handle, ctypes.byref(t)), "s2w_set_tuning")
+
+
+class Bltt:
+    """Thin owner of an ``s2w_bltt*`` (one block lower-triangular Toeplitz operator)."""
+
+    def __init__(self, nrow: int, ncol: int, nt: int, max_batch: int = 1, device: int = 0):
+        self.lib = load_library()
+        self.desc = BlttDesc(nrow, ncol, nt, max_batch)
+        self.handle = ctypes.c_void_p()
+        st = self.lib.s2w_bltt_create(ctypes.byref(self.desc), device, ctypes.byref(self.handle))
+        if st != 0:
+            raise S2WError(st, "s2w_bltt_create")
+
+    def _check(self, st: int, where: str):
+        if st != 0:
+            msg = self.lib.s2w_bltt_last_error(self.handle)
+            raise S2WError(st, where, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            self.lib.s2w_bltt_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def query_sizes(self):
+        op, ws = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self.lib.s2w_bltt_query_sizes(self.handle, ctypes.byref(op), ctypes.byref(ws)),
+                    "s2w_bltt_query_sizes")
+        return op.value, ws.value
+
+    def bind(self, op_ptr: int, op_bytes: int, ws_ptr: int, ws_bytes: int):
+        self._check(self.lib.s2w_bltt_bind_memory(self.handle, op_ptr, op_bytes, ws_ptr, ws_bytes),
+                    "s2w_bltt_bind_memory")
+
+    def set_blocks(self, f_ptr: int, row0: int, nrows: int, stream: int = 0):
+        self._check(self.lib.s2w_bltt_set_blocks(self.handle, f_ptr, row0, nrows, stream), "s2w_bltt_set_blocks")
+
+    def apply(self, x_ptr: int, B: int, y_ptr: int, stream: int = 0):
+        self._check(self.lib.s2w_bltt_apply(self.handle, x_ptr, B, y_ptr, stream), "s2w_bltt_apply")
+
+    def adjoint(self, y_ptr: int, B: int, x_ptr: int, stream: int = 0):
+        self._check(self.lib.s2w_bltt_adjoint(self.handle, y_ptr, B, x_ptr, stream), "s2w_bltt_adjoint")

@@ -815,3 +815,237 @@ s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// One BLTT operator on its own (Alg. 2): the batched float32 machinery with a single product.
+
+struct s2w_bltt {
+  s2w_bltt_desc desc;
+  int device = 0;
+  Geometry geo;           // nt, L, M (nsub/ngrid/nobs unused)
+  int ncol_k = 0;         // columns padded to 8 (zeros): K of the forward product
+  int nrow_k = 0;         // rows padded to 8 (zeros in the transformed adjoint input)
+  int bp = 8;             // max_batch padded to 8
+  int splits_f = 1, splits_a = 1;
+  uint64_t op_total = 0, ws_total = 0;
+  uint64_t o_fs = 0, o_s = 0, o_part = 0, o_yh = 0;
+  char* op = nullptr;
+  char* ws = nullptr;
+  std::vector<uint8_t> row_set;
+  int64_t rows_missing = 0;
+  std::string err;
+};
+
+namespace {
+
+s2w_status bfail(s2w_bltt* p, s2w_status st, const char* fmt, ...) {
+  if (p) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    p->err = buf;
+  }
+  return st;
+}
+
+s2w_status bhip(s2w_bltt* p, hipError_t e, const char* what) {
+  return bfail(p, S2W_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// grid-row splits of a product with `rows` output rows: enough workgroups to fill the chip
+int bltt_splits(int M, int rows) {
+  const int64_t tiles = (int64_t)M * ((rows + 63) / 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, 2048 / std::max<int64_t>(1, tiles)));
+}
+
+int bltt_cfg(int B, bool few_rows) {
+  if (few_rows) return B <= 8 ? 2 : (B <= 64 ? 3 : 0);
+  return B <= 64 ? 2 : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+s2w_status s2w_bltt_create(const s2w_bltt_desc* desc, int32_t device, s2w_bltt** out) {
+  if (!out) return S2W_EINVAL;
+  *out = nullptr;
+  if (!desc) return S2W_EINVAL;
+  const s2w_bltt_desc& d = *desc;
+  if (d.nrow < 1 || d.ncol < 1 || d.nrow > (1 << 24) || d.ncol > (1 << 24) || d.nt < 1 || d.nt > 512 ||
+      d.max_batch < 0 || d.max_batch > 1024)
+    return S2W_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return S2W_EINVAL;
+  s2w_bltt* p = new (std::nothrow) s2w_bltt();
+  if (!p) return S2W_ENOMEM;
+  p->desc = d;
+  p->device = device;
+  Geometry& g = p->geo;
+  g = Geometry{};
+  g.nsub = d.ncol;
+  g.ngrid = d.nrow;
+  g.nobs = d.nrow;
+  g.nt = d.nt;
+  g.L = std::max(32, next_pow2(2 * d.nt - 1));
+  g.M = g.L / 2;
+  g.logM = ilog2(g.M);
+  g.diff = S2W_DIFF_NONE;
+  g.dt = 1.0f;
+  p->ncol_k = (d.ncol + 7) / 8 * 8;
+  p->nrow_k = (d.nrow + 7) / 8 * 8;
+  p->bp = (std::max(d.max_batch, 1) + 7) / 8 * 8;
+  p->splits_f = bltt_splits(g.M, d.nrow);
+  p->splits_a = bltt_splits(g.M, d.ncol);
+  const uint64_t c8 = sizeof(float2), M = (uint64_t)g.M, bp = (uint64_t)p->bp;
+  p->o_fs = 0;
+  p->op_total = round_up((uint64_t)d.nrow * M * p->ncol_k * c8, kAlign);
+  uint64_t off = 0;
+  p->o_s = off;
+  off = round_up(off + M * std::max(p->ncol_k, p->nrow_k) * bp * c8, kAlign);
+  p->o_part = off;
+  const uint64_t prow = std::max((uint64_t)p->splits_f * p->nrow_k, (uint64_t)p->splits_a * p->ncol_k);
+  off = round_up(off + prow * M * 2 * bp * 4, kAlign);
+  p->o_yh = off;
+  off = round_up(off + bp * std::max(d.nrow, d.ncol) * M * c8, kAlign);
+  p->ws_total = off;
+  p->row_set.assign((size_t)d.nrow, 0);
+  p->rows_missing = d.nrow;
+  {
+    DeviceGuard dg(device);
+    if (!dg.ok || ensure_twiddles(device) != hipSuccess) {
+      delete p;
+      return S2W_EHIP;
+    }
+  }
+  *out = p;
+  return S2W_OK;
+}
+
+s2w_status s2w_bltt_destroy(s2w_bltt* op) {
+  delete op;
+  return S2W_OK;
+}
+
+const char* s2w_bltt_last_error(const s2w_bltt* op) { return op ? op->err.c_str() : ""; }
+
+s2w_status s2w_bltt_query_sizes(const s2w_bltt* p, uint64_t* operator_bytes, uint64_t* workspace_bytes) {
+  if (!p) return S2W_EINVAL;
+  if (operator_bytes) *operator_bytes = p->op_total;
+  if (workspace_bytes) *workspace_bytes = p->ws_total;
+  return S2W_OK;
+}
+
+s2w_status s2w_bltt_bind_memory(s2w_bltt* p, void* operator_store, uint64_t operator_bytes, void* workspace,
+                                uint64_t workspace_bytes) {
+  if (!p) return S2W_EINVAL;
+  if (!operator_store || !workspace) return bfail(p, S2W_EINVAL, "bind: null pointer");
+  if (!aligned(operator_store) || !aligned(workspace)) return bfail(p, S2W_EINVAL, "bind: pointers must be 256-byte aligned");
+  if (operator_bytes < p->op_total || workspace_bytes < p->ws_total)
+    return bfail(p, S2W_ENOMEM, "bind: need %llu + %llu bytes", (unsigned long long)p->op_total,
+                 (unsigned long long)p->ws_total);
+  p->op = (char*)operator_store;
+  p->ws = (char*)workspace;
+  std::fill(p->row_set.begin(), p->row_set.end(), 0);
+  p->rows_missing = p->desc.nrow;
+  return S2W_OK;
+}
+
+s2w_status s2w_bltt_set_blocks(s2w_bltt* p, const float* F_chunk, int64_t row0, int64_t nrows, void* stream) {
+  if (!p) return S2W_EINVAL;
+  if (!p->op) return bfail(p, S2W_ESTATE, "set_blocks: memory not bound");
+  if (!F_chunk) return bfail(p, S2W_EINVAL, "set_blocks: null chunk pointer");
+  if (!aligned(F_chunk)) return bfail(p, S2W_EINVAL, "set_blocks: chunk pointer must be 256-byte aligned");
+  if (row0 < 0 || nrows < 0 || row0 + nrows > p->desc.nrow)
+    return bfail(p, S2W_EINVAL, "set_blocks: rows [%lld, %lld) outside [0, %d)", (long long)row0,
+                 (long long)(row0 + nrows), p->desc.nrow);
+  if (nrows == 0) return S2W_OK;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return bfail(p, S2W_EHIP, "set_blocks: cannot select device %d", p->device);
+  const Geometry& g = p->geo;
+  float2* Fs = (float2*)(p->op + p->o_fs);
+  // Fs[row][l][c]: the GEMM layout of the forward product (c padded with zeros)
+  hipError_t e = launch_rfft_rows(F_chunk, nrows, p->desc.ncol, p->ncol_k, Fs + row0 * g.M * p->ncol_k,
+                                  (int64_t)g.M * p->ncol_k, 1, p->ncol_k, g, 1.0f, (hipStream_t)stream);
+  if (e != hipSuccess) return bhip(p, e, "set_blocks: transform");
+  for (int64_t r = row0; r < row0 + nrows; ++r)
+    if (!p->row_set[(size_t)r]) {
+      p->row_set[(size_t)r] = 1;
+      --p->rows_missing;
+    }
+  return S2W_OK;
+}
+
+static s2w_status bltt_check(s2w_bltt* p, const void* in, int32_t B, const void* out, const char* who) {
+  if (!p) return S2W_EINVAL;
+  if (B < 0 || B > p->desc.max_batch) return bfail(p, S2W_EINVAL, "%s: B=%d outside [0, %d]", who, B, p->desc.max_batch);
+  if (B == 0) return S2W_OK;
+  if (!in || !out) return bfail(p, S2W_EINVAL, "%s: null pointer", who);
+  if (!aligned(in) || !aligned(out)) return bfail(p, S2W_EINVAL, "%s: pointers must be 256-byte aligned", who);
+  if (in == out) return bfail(p, S2W_EINVAL, "%s: input and output must be distinct", who);
+  if (!p->op) return bfail(p, S2W_ESTATE, "%s: memory not bound", who);
+  if (p->rows_missing > 0) return bfail(p, S2W_ESTATE, "%s: %lld rows have no blocks yet", who, (long long)p->rows_missing);
+  return S2W_OK;
+}
+
+s2w_status s2w_bltt_apply(s2w_bltt* p, const float* x, int32_t B, float* y, void* stream) {
+  s2w_status cs = bltt_check(p, x, B, y, "apply");
+  if (cs != S2W_OK || B == 0) return cs;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return bfail(p, S2W_EHIP, "apply: cannot select device %d", p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = p->geo;
+  const int nrow = p->desc.nrow, ncol = p->desc.ncol, bp = p->bp;
+  const float2* Fs = (const float2*)(p->op + p->o_fs);
+  float2* S = (float2*)(p->ws + p->o_s);
+  float* part = (float*)(p->ws + p->o_part);
+  float2* yh = (float2*)(p->ws + p->o_yh);
+  // S[l][c][b]
+  hipError_t e = launch_rfft_rows(x, B, ncol, p->ncol_k, S, 1, bp, (int64_t)p->ncol_k * bp, g, 1.0f, st);
+  if (e != hipSuccess) return bhip(p, e, "apply: input transform");
+  // part[split][l][r][n] = sum_{c in split} Fs[r][l][c] S[l][c][b]
+  const int splits = p->splits_f;
+  const int cfg = bltt_cfg(B, splits > 1);
+  const int64_t prow = 2 * (int64_t)bp;
+  e = launch_cgemm32(cfg, false, false, Fs, (int64_t)g.M * p->ncol_k, 1, p->ncol_k, nrow, nrow, p->ncol_k, p->ncol_k,
+                     S, bp, (int64_t)p->ncol_k * bp, p->ncol_k, B, bp, part, prow, (int64_t)p->nrow_k * prow,
+                     (int64_t)g.M * p->nrow_k * prow, g.M, splits, st);
+  if (e == hipSuccess) e = launch_sum_f(part, splits, g.M, p->nrow_k, nrow, B, bp, nullptr, yh, st);
+  if (e != hipSuccess) return bhip(p, e, "apply: matrix-core product");
+  e = launch_irfft_rows(yh, (int64_t)B * nrow, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+  if (e != hipSuccess) return bhip(p, e, "apply: output transform");
+  return S2W_OK;
+}
+
+s2w_status s2w_bltt_adjoint(s2w_bltt* p, const float* y, int32_t B, float* x, void* stream) {
+  s2w_status cs = bltt_check(p, y, B, x, "adjoint");
+  if (cs != S2W_OK || B == 0) return cs;
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return bfail(p, S2W_EHIP, "adjoint: cannot select device %d", p->device);
+  hipStream_t st = (hipStream_t)stream;
+  const Geometry& g = p->geo;
+  const int nrow = p->desc.nrow, ncol = p->desc.ncol, bp = p->bp;
+  const float2* Fs = (const float2*)(p->op + p->o_fs);
+  float2* R = (float2*)(p->ws + p->o_s);
+  float* part = (float*)(p->ws + p->o_part);
+  float2* xh = (float2*)(p->ws + p->o_yh);
+  // R[l][r][b] (rows padded with zeros)
+  hipError_t e = launch_rfft_rows(y, B, nrow, p->nrow_k, R, 1, bp, (int64_t)p->nrow_k * bp, g, 1.0f, st);
+  if (e != hipSuccess) return bhip(p, e, "adjoint: input transform");
+  // part[split][l][c][n] = sum_{r in split} conj(Fs[r][l][c]) R[l][r][b]
+  const int splits = p->splits_a;
+  const int cfg = bltt_cfg(B, splits > 1);
+  const int64_t prow = 2 * (int64_t)bp;
+  e = launch_cgemm32(cfg, true, true, Fs, 1, (int64_t)g.M * p->ncol_k, p->ncol_k, ncol, p->ncol_k, nrow, p->nrow_k, R,
+                     bp, (int64_t)p->nrow_k * bp, p->nrow_k, B, bp, part, prow, (int64_t)p->ncol_k * prow,
+                     (int64_t)g.M * p->ncol_k * prow, g.M, splits, st);
+  if (e == hipSuccess) e = launch_sum_f(part, splits, g.M, p->ncol_k, ncol, B, bp, nullptr, xh, st);
+  if (e != hipSuccess) return bhip(p, e, "adjoint: matrix-core product");
+  e = launch_irfft_rows(xh, (int64_t)B * ncol, g.M, 1, x, g.nt, g, 1.0f / (float)g.L, st);
+  if (e != hipSuccess) return bhip(p, e, "adjoint: output transform");
+  return S2W_OK;
+}
+
+}  // extern "C"

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from .abi import DIFF_BACKWARD, Plan
+from .abi import DIFF_BACKWARD, Bltt, Plan
 
 _ALIGN = 256
 
@@ -159,3 +159,57 @@ def host_generators(cfg):
         synth.gen_F(cfg, r0, n, out=out)
 
     return gG, gF
+
+
+class BLTTOperator:
+    """One block lower-triangular Toeplitz operator y_n = sum_{k<=n} F_k x_{n-k} (Alg. 2 on its own).
+
+    ``F_k`` is ``nrow x ncol``; blocks are set in row chunks ``F[r][c][k]``.  ``apply(x)``
+    maps x[B][ncol][nt] to y[B][nrow][nt], ``adjoint(y)`` is its transpose.  With the elastic
+    blocks of a share this gives the seafloor displacement (eq. 1); with the acoustic blocks,
+    the partial waveforms of a given seafloor motion (eq. 2).
+    """
+
+    def __init__(self, nrow: int, ncol: int, nt: int, max_batch: int = 1, device: int | str = 0):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        self.nrow, self.ncol, self.nt, self.max_batch = nrow, ncol, nt, max_batch
+        self.plan = Bltt(nrow, ncol, nt, max_batch, idx)
+        op_bytes, ws_bytes = self.plan.query_sizes()
+        self.op_store = torch.empty(max(op_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=self.device)
+        self.plan.bind(self.op_store.data_ptr(), op_bytes, self.workspace.data_ptr(), ws_bytes)
+
+    def set_blocks(self, F_chunk: torch.Tensor, row0: int):
+        n = F_chunk.shape[0]
+        F_chunk = _prep(F_chunk, (n, self.ncol, self.nt), self.device)
+        self.plan.set_blocks(F_chunk.data_ptr(), row0, n, _stream_handle(self.device))
+        return F_chunk
+
+    def load_blocks(self, gen, chunk_rows: int = 256):
+        """Fill every row from a host generator ``gen(row0, n, out)`` writing float32 [n][ncol][nt]."""
+        for r0 in range(0, self.nrow, chunk_rows):
+            n = min(chunk_rows, self.nrow - r0)
+            h = torch.empty((n, self.ncol, self.nt), dtype=torch.float32, pin_memory=True)
+            gen(r0, n, h.numpy())
+            d = h.to(self.device, non_blocking=True)
+            self.plan.set_blocks(d.data_ptr(), r0, n, _stream_handle(self.device))
+            torch.cuda.current_stream(self.device).synchronize()
+
+    def apply(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        squeeze = x.dim() == 2
+        B = 1 if squeeze else x.shape[0]
+        x = _prep(x, (B, self.ncol, self.nt), self.device)
+        y = out if out is not None else torch.empty((B, self.nrow, self.nt), dtype=torch.float32, device=self.device)
+        assert y.is_contiguous() and _aligned(y) and y.shape == (B, self.nrow, self.nt)
+        self.plan.apply(x.data_ptr(), B, y.data_ptr(), _stream_handle(self.device))
+        return y[0] if squeeze else y
+
+    def adjoint(self, y: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        squeeze = y.dim() == 2
+        B = 1 if squeeze else y.shape[0]
+        y = _prep(y, (B, self.nrow, self.nt), self.device)
+        x = out if out is not None else torch.empty((B, self.ncol, self.nt), dtype=torch.float32, device=self.device)
+        assert x.is_contiguous() and _aligned(x) and x.shape == (B, self.ncol, self.nt)
+        self.plan.adjoint(y.data_ptr(), B, x.data_ptr(), _stream_handle(self.device))
+        return x[0] if squeeze else x
