@@ -113,8 +113,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,fp32b,half",
-                    help="fp32 (single rupture), fp32b (batched float32), half (batched half precision)")
+    ap.add_argument("--paths", default="fp32,fp32b,half,bltt,strong,weak",
+                    help="fp32 (single rupture), fp32b (batched float32), half (batched half precision), "
+                         "bltt (elastic operator alone: seafloor displacement), strong / weak (the float32 "
+                         "single-rupture path on the strong- and weak-scaling per-GPU shares)")
     ap.add_argument("--batch32", type=int, default=256, help="ruptures per call on the batched float32 path")
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -274,6 +276,68 @@ def main():
             half["rel_l2"] = max(errs)
             log(f"half rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
         result["half"] = half
+        del op
+        torch.cuda.empty_cache()
+
+    # ---------------- elastic operator alone (seafloor displacement of the share) ----------------
+    if "bltt" in paths:
+        from paper_2608_21763_amd import BLTTOperator
+        from paper_2608_21763_amd.hiprt import HipEvent
+        import oracle
+        op = BLTTOperator(cfg.ngrid, cfg.nsub, cfg.nt, max_batch=1)
+        t = time.perf_counter()
+        op.load_blocks(lambda r0, n, out: synth.gen_G(cfg, r0, n, out=out), chunk_rows=1024)
+        setup_s = time.perf_counter() - t
+        s_host = synth.gen_slip_batch(cfg, 0, 1)
+        x = torch.tensor(s_host, device=dev)
+        m = torch.empty((1, cfg.ngrid, cfg.nt), device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+        for _ in range(args.warmup):
+            op.apply(x, out=m)
+        e0, e1 = HipEvent(), HipEvent()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            op.apply(x, out=m)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_ms(e1) / args.steps
+        pad = (cfg.nsub + 7) // 8 * 8
+        slots = max(32, 1 << (2 * cfg.nt - 2).bit_length()) // 2      # L/2 packed slots
+        store = cfg.ngrid * slots * pad * 8
+        bl = {"ms_per_call": ms, "ruptures_per_s": 1000.0 / ms, "B": 1, "store_bytes": store,
+              "achieved_GBs": store / (ms * 1e6), "hbm_frac": store / (ms * 1e6) / HBM_PEAK_GBS, "setup_s": setup_s}
+        if not args.no_cpu_baseline:
+            rows = np.array([0, cfg.ngrid // 2, cfg.ngrid - 1])
+            ref = oracle.bltt(np.stack([synth.gen_G(cfg, int(g), 1)[0] for g in rows]), s_host[0])
+            bl["rel_l2_sampled_rows"] = oracle.rel_l2(m[0].cpu().numpy()[rows], ref)
+        log(f"elastic operator alone B=1: {ms:.3f} ms, {bl['achieved_GBs']:.0f} GB/s")
+        result["bltt"] = bl
+        del op
+        torch.cuda.empty_cache()
+
+    # ---------------- Table I per-GPU shares, float32 single rupture ----------------
+    for name, key in (("strong_p8", "strong"), ("weak", "weak")):
+        if key not in paths:
+            continue
+        scfg = synth.workload(name)
+        op = S2WOperator(scfg.nsub, scfg.ngrid, scfg.nobs, scfg.nt, max_batch=1, dt=scfg.dt, device=0)
+        t = time.perf_counter()
+        op.load_operators(*host_generators(scfg), chunk_rows=2048)
+        setup_s = time.perf_counter() - t
+        nrup = max(args.steps, args.warmup, 1)
+        s_host = synth.gen_slip_batch(scfg, 0, nrup)
+        s_dev = torch.tensor(s_host, device=dev).reshape(nrup, 1, scfg.nsub, scfg.nt)
+        total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, 1)
+        ms_step = total_ms / args.steps
+        abytes = algorithmic_bytes(scfg.nsub, scfg.nobs, scfg.ngrid, scfg.nt, 4)
+        kmean = float(np.mean(kern_ms))
+        sh = {"workload": f"{scfg.nsub}x{scfg.ngrid}x{scfg.nobs}x{scfg.nt}", "ruptures_per_s": 1000.0 / ms_step,
+              "ms_per_step": ms_step, "kernel_ms": kmean, "algorithmic_bytes": abytes,
+              "achieved_GBs": abytes / (kmean * 1e6), "hbm_frac": abytes / (kmean * 1e6) / HBM_PEAK_GBS,
+              "setup_s": setup_s}
+        log(f"{name}: {ms_step:.3f} ms/rupture, kernel {kmean:.3f} ms, {sh['achieved_GBs']:.0f} GB/s")
+        result[key] = sh
         del op
         torch.cuda.empty_cache()
 

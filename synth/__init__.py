@@ -141,6 +141,9 @@ def workload(name: str) -> SynthConfig:
     cascadia_batch same operators; K ~ U{20..963} active subfaults, W ~ U(2, 10) s
     cascadia_x2    963 x 75,520 x 64 x 256 (a 1/32 share), batch slip as above
     cascadia_adj   cascadia operators; batch slip; used for the misfit gradient
+    strong_p8      60 x 302,067 x 4 x 256: one of eight GPUs' shares of the strong-scaling
+                   problem (60 subfaults, 4 observers, all 2,416,530 grid points), Table I
+    weak           480 x 37,758 x 32 x 256: one GPU's share of the weak-scaling problem, Table I
     """
     small = SynthConfig(nsub=16, ngrid=512, nobs=4, nt=32, seed=MASTER_SEED, slip_seed=MASTER_SEED)
     strip = dict(box_x=1000.0, box_y=150.0, seed=MASTER_SEED + 1)
@@ -160,6 +163,12 @@ def workload(name: str) -> SynthConfig:
     if name == "cascadia_adj":
         return SynthConfig(nsub=963, ngrid=37760, nobs=64, nt=256, slip_mode="knearest", w_lo=2.0, w_hi=10.0,
                            slip_seed=MASTER_SEED + 4, **strip)
+    if name == "strong_p8":
+        return SynthConfig(nsub=60, ngrid=302067, nobs=4, nt=256, slip_mode="length", slip_seed=MASTER_SEED + 5,
+                           **strip)
+    if name == "weak":
+        return SynthConfig(nsub=480, ngrid=37758, nobs=32, nt=256, slip_mode="length", slip_seed=MASTER_SEED + 6,
+                           **strip)
     raise KeyError(name)
 
 
