@@ -60,3 +60,25 @@ def test_bench_refuses_several_gpus():
     import sys
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode == 2 and "one GPU" in r.stdout
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # without the built HIP library the package refuses to work instead of falling back
+    import subprocess
+    import sys
+    import textwrap
+    code = textwrap.dedent(f"""
+        import sys
+        sys.path.insert(0, {repr(str(ROOT))})
+        import paper_2608_21763_amd.abi as abi
+        abi.LIB_PATH = {repr(str(tmp_path / 'missing' / 'libs2w.so'))}
+        try:
+            abi.Plan(4, 8, 2, 16)
+        except ImportError as e:
+            print("refused:", e)
+            sys.exit(0)
+        sys.exit(1)
+    """)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "refused" in r.stdout
