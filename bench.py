@@ -76,7 +76,7 @@ def traffic_for(kernel: str):
 
 def elastic_kernel(B: int) -> str:
     """Kernel of the batched elastic GEMM the library picks by default for a batch of B."""
-    return "k_gemm_g" if B <= 64 else "k_gemm_g4"
+    return "k_gemm_g4"
 
 
 def time_path(op, s_dev, steps: int, warmup: int, B: int):

@@ -583,7 +583,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int bp = h.bp;
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
-  if (cfg < 0) cfg = B <= 8 ? 0 : (B <= 64 ? 1 : 10);
+  if (cfg < 0) cfg = B <= 64 ? 12 : 10;
   // acoustic GEMM: the LDS-staged kernel serves the packed bfloat16 activation when its tile fits
   const bool packed = h.ht_f == 1 && h.hterms_f == 2;
   const bool fstaged = packed && p->tune.fgemm_lds != 0 && gemm_f2_supported(h.noq, B);
