@@ -110,7 +110,7 @@ def time_path(op, s_dev, steps: int, warmup: int, B: int):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
     ap.add_argument("--paths", default="fp32,fp32b,half,bltt,strong,weak",
