@@ -1,0 +1,60 @@
+"""The descriptor's limits on every path: all maxima at once (1024 subfaults, 256 observers,
+512 steps) and the largest batch (1024 ruptures per call), against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import log_case, make_operator, to_dev
+
+pytestmark = pytest.mark.gpu
+
+PATHS = {
+    "single": (dict(layout="single"), 1e-5),
+    "batched32": (dict(layout="batched"), 1e-5),
+    "f16": (dict(g_dtype="f16", f_dtype="f16"), 2e-3),
+    "bf16": (dict(g_dtype="bf16", f_dtype="bf16"), 1e-2),
+}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_all_maxima(path):
+    kw, tol = PATHS[path]
+    cfg = synth.SynthConfig(nsub=1024, ngrid=40, nobs=256, nt=512, seed=91, slip_seed=92, op_kind="dense",
+                            slip_mode="dense")
+    log_case("limits_maxima", path=path)
+    op = make_operator(cfg, max_batch=3, **kw)
+    s = synth.gen_slip_batch(cfg, 0, 3)
+    y = op.forward(to_dev(s)).cpu().numpy()
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    errs = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s))
+    print(path, "rel-L2", errs)
+    assert errs.max() <= tol
+    if path in ("single", "batched32"):
+        r = synth.normals(9, "r", 0, (3, cfg.nobs, cfg.nt))
+        g = op.adjoint(to_dev(r)).cpu().numpy()
+        assert oracle.rel_l2_per_rupture(g, oracle.adjoint(G, F, r)).max() <= tol
+
+
+@pytest.mark.parametrize("path", ["batched32", "f16", "bf16"])
+def test_largest_batch(path):
+    kw, tol = PATHS[path]
+    cfg = synth.SynthConfig(nsub=8, ngrid=64, nobs=4, nt=16, seed=93, slip_seed=94, op_kind="dense",
+                            slip_mode="dense")
+    B = 1024
+    log_case("limits_batch", path=path, B=B)
+    op = make_operator(cfg, max_batch=B, **kw)
+    s = synth.gen_slip_batch(cfg, 0, B)
+    y = op.forward(to_dev(s)).cpu().numpy()
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    errs = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s))
+    print(path, "rel-L2 max", errs.max())
+    assert errs.max() <= tol
