@@ -287,8 +287,10 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
     h.on = true;
     h.ht_g = d.g_dtype == S2W_BF16 ? 1 : 2;
     h.ht_f = d.f_dtype == S2W_BF16 ? 1 : 2;
-    h.hterms_g = 2;
-    h.hterms_f = 2;
+    // activations: a high and a low bf16 term each for bfloat16 operators; one scaled f16
+    // term for float16 operators (its rounding is then of the operator's own order)
+    h.hterms_g = d.g_dtype == S2W_F16 ? 1 : 2;
+    h.hterms_f = d.f_dtype == S2W_F16 ? 1 : 2;
     h.nsq = (d.nsub + 15) / 16 * 16;
     h.noq = 16 * next_pow2((d.nobs + 15) / 16);
     h.ngq = (d.ngrid + 15) / 16 * 16;
@@ -605,8 +607,8 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (e == hipSuccess) {
     const int nwg = p->ncu * p->tune.fused_wg_per_cu;
     if (compact)
-      e = launch_gemm_g3(h.ht_g, cfg, Gq, sG, (const uint2*)Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, B, bp,
-                         st);
+      e = launch_gemm_g3(h.ht_g, h.hterms_g, cfg, Gq, sG, (const uint2*)Bop, sig_down, (float*)U, nwg, g.ngrid, g.M,
+                         h.nks, B, bp, st);
     else
       e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, ncb, B,
                         bp, st);

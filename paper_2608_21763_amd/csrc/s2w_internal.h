@@ -70,8 +70,9 @@ hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const flo
                          hipStream_t st);
 hipError_t launch_prep_act_compact(int ht, const float2* S, float* sig_up, float* sig_down, int M, int nsub, int nsq,
                                    int B, int bp, int nks, uint2* Sc, hipStream_t st);
-hipError_t launch_gemm_g3(int ht, int cfg, const uint4* Gq, const float* sG, const uint2* Sc, const float* sig_down,
-                          float* U, int nwg, int ngrid, int M, int nks, int B, int bp, hipStream_t st);
+hipError_t launch_gemm_g3(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint2* Sc,
+                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int B, int bp,
+                          hipStream_t st);
 // LDS-staged acoustic GEMM (packed bfloat16 activation): supported observer paddings and the
 // number of rupture tiles it launches for a batch of B.
 inline bool gemm_f2_supported(int noq, int B) {

@@ -366,7 +366,7 @@ __device__ __forceinline__ uint32_t embed_word(uint32_t w, int c, bool dc) {
 // groups), tile 2*MW grid rows x 4*NW output columns (2*NW ruptures).  Per K step the operator
 // tile (2*MW rows x 64 bytes, chunk-swizzled) and the compact activation tile (16 subfaults x
 // 2*NW ruptures x 8 bytes, rows padded by 64 bytes) are double-buffered in LDS.
-template <int HT, int MW, int NW, int WR>
+template <int HT, int MW, int NW, int WR, int H = 2>
 __global__ __launch_bounds__(256 * WR, WR == 1 ? 2 : 1) void k_gemm_g3(const uint4* __restrict__ Gq, const float* __restrict__ sG,
                                                     const uint2* __restrict__ Sc, const float* __restrict__ sig_down,
                                                     float* __restrict__ U, int ngrid, int M, int nks, int B, int bp,
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(256 * WR, WR == 1 ? 2 : 1) void k_gemm_g3(const uin
 #pragma unroll
         for (int a = 0; a < MF; ++a) {
           acc[a][b] = mfma16<HT>(av[a], bh, acc[a][b]);
-          acc[a][b] = mfma16<HT>(av[a], bl, acc[a][b]);
+          if (H == 2) acc[a][b] = mfma16<HT>(av[a], bl, acc[a][b]);
         }
       }
       if (more) {
@@ -855,8 +855,9 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_g3(int ht, int cfg, const uint4* Gq, const float* sG, const uint2* Sc, const float* sig_down,
-                          float* U, int nwg, int ngrid, int M, int nks, int B, int bp, hipStream_t st) {
+hipError_t launch_gemm_g3(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint2* Sc,
+                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int B, int bp,
+                          hipStream_t st) {
   // 7: 256 rows x 128 ruptures (eight waves); 8: 128 rows x 256 ruptures (eight waves);
   // 9: 128 rows x 128 ruptures (four waves, two workgroups per compute unit)
   const int WR = cfg == 9 ? 1 : 2;
@@ -864,13 +865,15 @@ hipError_t launch_gemm_g3(int ht, int cfg, const uint4* Gq, const float* sG, con
   const int nrb = (ngrid + WR * MW - 1) / (WR * MW);
   const int nct = (B + 2 * NW - 1) / (2 * NW);
   const int grid = cfg == 9 ? 2 * nwg : nwg;
-#define S2W_G3(HT_, MW_, NW_, WR_)                                                                                 \
-  hipLaunchKernelGGL((k_gemm_g3<HT_, MW_, NW_, WR_>), dim3(grid), dim3(256 * WR_), 0, st, Gq, sG, Sc, sig_down, U, \
-                     ngrid, M, nks, B, bp, nrb, nct)
+#define S2W_G3(HT_, MW_, NW_, WR_, H_)                                                                            \
+  hipLaunchKernelGGL((k_gemm_g3<HT_, MW_, NW_, WR_, H_>), dim3(grid), dim3(256 * WR_), 0, st, Gq, sG, Sc, sig_down, \
+                     U, ngrid, M, nks, B, bp, nrb, nct)
   if (ht == 1) {
-    if (cfg == 8) S2W_G3(1, 64, 128, 2); else if (cfg == 9) S2W_G3(1, 128, 64, 1); else S2W_G3(1, 128, 64, 2);
+    if (cfg == 8) S2W_G3(1, 64, 128, 2, 2); else if (cfg == 9) S2W_G3(1, 128, 64, 1, 2); else S2W_G3(1, 128, 64, 2, 2);
+  } else if (hterms == 2) {
+    if (cfg == 8) S2W_G3(2, 64, 128, 2, 2); else if (cfg == 9) S2W_G3(2, 128, 64, 1, 2); else S2W_G3(2, 128, 64, 2, 2);
   } else {
-    if (cfg == 8) S2W_G3(2, 64, 128, 2); else if (cfg == 9) S2W_G3(2, 128, 64, 1); else S2W_G3(2, 128, 64, 2);
+    if (cfg == 8) S2W_G3(2, 64, 128, 2, 1); else if (cfg == 9) S2W_G3(2, 128, 64, 1, 1); else S2W_G3(2, 128, 64, 2, 1);
   }
 #undef S2W_G3
   return hipGetLastError();
