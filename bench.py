@@ -11,6 +11,7 @@ slip histories are already resident in HBM.  Paths timed:
   fp32b   B ruptures per call, complex64 spectra, float32 matrix-core GEMMs
   half    B ruptures per call on the batched matrix-core path with bf16 spectra (headline)
   half16  the same with f16 spectra (single-term activations)
+  adj     the batched float32 adjoint (gradient of a waveform misfit), B = 64
   bltt    the elastic operator alone (seafloor displacement), one rupture
   strong / weak  the single-rupture path on the paper's strong- and weak-scaling shares
 The headline value is the half path's ruptures/s when it is available.
@@ -116,12 +117,13 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,fp32b,half,half16,bltt,strong,weak",
+    ap.add_argument("--paths", default="fp32,fp32b,half,half16,adj,bltt,strong,weak",
                     help="fp32 (single rupture), fp32b (batched float32), half (batched half precision, --half-dtype), "
-                         "half16 (batched float16 stores), "
+                         "half16 (batched float16 stores), adj (batched float32 adjoint), "
                          "bltt (elastic operator alone: seafloor displacement), strong / weak (the float32 "
                          "single-rupture path on the strong- and weak-scaling per-GPU shares)")
     ap.add_argument("--batch32", type=int, default=256, help="ruptures per call on the batched float32 path")
+    ap.add_argument("--batch-adj", type=int, default=64, help="residuals per call on the batched float32 adjoint")
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ngrid", type=int, default=None, help="override the share size (testing only)")
@@ -288,6 +290,45 @@ def main():
         result["half"] = half_path(gdt, fdt, args.batch)
     if "half16" in paths:
         result["half16"] = half_path("f16", "f16", args.batch)
+
+    # ---------------- misfit gradient: batched float32 adjoint ----------------
+    if "adj" in paths:
+        from paper_2608_21763_amd.hiprt import HipEvent
+        B = args.batch_adj
+        acfg = synth.workload("cascadia_adj")
+        if args.ngrid:
+            acfg = acfg.replace(ngrid=args.ngrid)
+        op = S2WOperator(acfg.nsub, acfg.ngrid, acfg.nobs, acfg.nt, max_batch=B, dt=acfg.dt, device=0,
+                         layout="batched")
+        t = time.perf_counter()
+        op.load_operators(*host_generators(acfg), chunk_rows=1024)
+        setup_s = time.perf_counter() - t
+        r = torch.randn((B, acfg.nobs, acfg.nt), device=dev)
+        gs = torch.empty((B, acfg.nsub, acfg.nt), device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+        for _ in range(args.warmup):
+            op.adjoint(r, out=gs)
+        torch.cuda.synchronize()
+        evs = [(HipEvent(), HipEvent()) for _ in range(args.steps)]
+        t0, t1 = HipEvent(), HipEvent()
+        t0.record(stream)
+        for k in range(args.steps):
+            op.plan.set_profile_events(evs[k][0].handle, evs[k][1].handle)
+            op.adjoint(r, out=gs)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        op.plan.set_profile_events(0, 0)
+        ms_step = t0.elapsed_ms(t1) / args.steps
+        kmean = float(np.mean([a.elapsed_ms(e) for a, e in evs]))
+        flops = 8.0 * acfg.ngrid * acfg.nsub * acfg.nt * B
+        result["adj"] = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B,
+                         "kernel": "k_cgemm32 (transposed elastic)", "kernel_ms": kmean,
+                         "achieved_TFLOPs": flops / (kmean * 1e9), "mfma_frac": flops / (kmean * 1e9) / MFMA_PEAK["f32"],
+                         "setup_s": setup_s}
+        log(f"fp32 batched adjoint B={B}: {ms_step:.3f} ms/call, {result['adj']['ruptures_per_s']:.0f} gradients/s, "
+            f"transposed elastic GEMM {kmean:.3f} ms = {result['adj']['achieved_TFLOPs']:.1f} TFLOP/s")
+        del op
+        torch.cuda.empty_cache()
 
     # ---------------- elastic operator alone (seafloor displacement of the share) ----------------
     if "bltt" in paths:
