@@ -117,9 +117,10 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,fp32b,half,half16,adj,bltt,strong,weak",
+    ap.add_argument("--paths", default="fp32,fp32b,half,half16,adj,hadj,bltt,strong,weak",
                     help="fp32 (single rupture), fp32b (batched float32), half (batched half precision, --half-dtype), "
-                         "half16 (batched float16 stores), adj (batched float32 adjoint), "
+                         "half16 (batched float16 stores), adj (batched float32 adjoint), hadj (batched bfloat16 adjoint, "
+                         "--batch residuals), "
                          "bltt (elastic operator alone: seafloor displacement), strong / weak (the float32 "
                          "single-rupture path on the strong- and weak-scaling per-GPU shares)")
     ap.add_argument("--batch32", type=int, default=256, help="ruptures per call on the batched float32 path")
@@ -291,15 +292,14 @@ def main():
     if "half16" in paths:
         result["half16"] = half_path("f16", "f16", args.batch)
 
-    # ---------------- misfit gradient: batched float32 adjoint ----------------
-    if "adj" in paths:
+    # ---------------- misfit gradients: batched adjoints ----------------
+    def adj_path(B, gdt, label, kernel, peak, **kw):
         from paper_2608_21763_amd.hiprt import HipEvent
-        B = args.batch_adj
         acfg = synth.workload("cascadia_adj")
         if args.ngrid:
             acfg = acfg.replace(ngrid=args.ngrid)
         op = S2WOperator(acfg.nsub, acfg.ngrid, acfg.nobs, acfg.nt, max_batch=B, dt=acfg.dt, device=0,
-                         layout="batched")
+                         g_dtype=gdt, f_dtype=gdt, **kw)
         t = time.perf_counter()
         op.load_operators(*host_generators(acfg), chunk_rows=1024)
         setup_s = time.perf_counter() - t
@@ -321,14 +321,21 @@ def main():
         ms_step = t0.elapsed_ms(t1) / args.steps
         kmean = float(np.mean([a.elapsed_ms(e) for a, e in evs]))
         flops = 8.0 * acfg.ngrid * acfg.nsub * acfg.nt * B
-        result["adj"] = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B,
-                         "kernel": "k_cgemm32 (transposed elastic)", "kernel_ms": kmean,
-                         "achieved_TFLOPs": flops / (kmean * 1e9), "mfma_frac": flops / (kmean * 1e9) / MFMA_PEAK["f32"],
-                         "setup_s": setup_s}
-        log(f"fp32 batched adjoint B={B}: {ms_step:.3f} ms/call, {result['adj']['ruptures_per_s']:.0f} gradients/s, "
-            f"transposed elastic GEMM {kmean:.3f} ms = {result['adj']['achieved_TFLOPs']:.1f} TFLOP/s")
+        res = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{gdt}",
+               "kernel": kernel, "kernel_ms": kmean, "achieved_TFLOPs": flops / (kmean * 1e9),
+               "mfma_frac": flops / (kmean * 1e9) / peak, "setup_s": setup_s}
+        log(f"{label} adjoint B={B}: {ms_step:.3f} ms/call, {res['ruptures_per_s']:.0f} gradients/s, "
+            f"transposed elastic GEMM {kmean:.3f} ms = {res['achieved_TFLOPs']:.1f} TFLOP/s")
         del op
         torch.cuda.empty_cache()
+        return res
+
+    if "adj" in paths:
+        result["adj"] = adj_path(args.batch_adj, "f32", "fp32 batched", "k_cgemm32 (transposed elastic)",
+                                 MFMA_PEAK["f32"], layout="batched")
+    if "hadj" in paths:
+        result["hadj"] = adj_path(args.batch, "bf16", "bf16 batched", "k_gemm_t (transposed elastic)",
+                                  MFMA_PEAK["bf16"])
 
     # ---------------- elastic operator alone (seafloor displacement of the share) ----------------
     if "bltt" in paths:

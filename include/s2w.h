@@ -130,7 +130,11 @@ s2w_status s2w_forward(s2w_plan* plan, const float* s, int32_t B, float* y, void
  * the transpose of D_t: gs = A^T r, so that for L = 0.5 ||A s - y_obs||^2 the
  * gradient is dL/ds = adjoint(A s - y_obs).
  *   r[b][o][n]   float32 [B][nobs][nt] (device)
- *   gs[b][j][n]  float32 [B][nsub][nt] (device, overwritten) */
+ *   gs[b][j][n]  float32 [B][nsub][nt] (device, overwritten)
+ * Every layout and store precision has it.  With half-precision stores the residual and the
+ * mid-chain output enter the matrix cores as half terms the same way the slip spectra do in
+ * the forward map (a high and a low bfloat16 term, or one scaled float16 term), so the
+ * adjoint's error is of the forward map's order. */
 s2w_status s2w_adjoint(s2w_plan* plan, const float* r, int32_t B, float* gs, void* stream);
 
 /* Kernel-shape controls for the tuner.  Zero fields keep the library default. */
@@ -148,7 +152,8 @@ typedef struct s2w_tuning {
   int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint
                                 elastic): tile, same values */
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
-  int32_t adj32_splits;      /* batched float32 adjoint, transposed elastic GEMM: grid-row splits (1..8) */
+  int32_t adj32_splits;      /* batched adjoint (float32 and half stores), transposed elastic GEMM: grid-row
+                                splits (1..8; half stores may clamp to what the partial region holds) */
 } s2w_tuning;
 
 s2w_status s2w_set_tuning(s2w_plan* plan, const s2w_tuning* t);

@@ -213,8 +213,8 @@ Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, const
     off = round_up(off + (uint64_t)g.M * bp * 4, kAlign);
     L.tau_down = off;
     off = round_up(off + (uint64_t)g.M * bp * 4, kAlign);
-    L.part_f = off;
-    off = round_up(off + (uint64_t)h.splits_max * g.M * h.noq * 2 * bp * 4, kAlign);
+    L.part_f = off;  // acoustic partials; the adjoint's residual spectra and elastic partials
+    off = round_up(off + (uint64_t)std::max(h.splits_max * h.noq, h.nsq) * g.M * 2 * bp * 4, kAlign);
     L.yhb = off;
     off = round_up(off + bp * g.nobs * g.M * c8, kAlign);
   }
@@ -736,6 +736,59 @@ static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs,
   return S2W_OK;
 }
 
+// Batched adjoint on the matrix cores (half-precision stores): the conjugate transposes of the
+// two per-bin products around the transposed mid-chain.  The acoustic scale sF multiplies the
+// first product's rows; the elastic scale sG rides on the mid-chain's output, ahead of the
+// grid-row reduction.
+static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const HalfGeo& h = p->hg;
+  const Layout& L = p->lay;
+  float* part = (float*)(p->ws + L.part_f);
+  float2* R = (float2*)part;                     // residual spectra R[l][o][b]
+  float2* W = (float2*)(p->ws + L.U);            // W[g][l][b]
+  float2* gh = (float2*)(p->ws + L.S);           // rows gh[b][j][l]
+  float* sig_up = (float*)(p->ws + L.sig_up);
+  float* sig_down = (float*)(p->ws + L.sig_down);
+  float* tau_up = (float*)(p->ws + L.tau_up);
+  float* tau_down = (float*)(p->ws + L.tau_down);
+  const uint32_t* Gq = (const uint32_t*)(p->op + L.gq);
+  const float* sG = (const float*)(p->op + L.sg);
+  const uint32_t* Fq = (const uint32_t*)(p->op + L.fq);
+  const float* sF = (const float*)(p->op + L.sf);
+  const int bp = h.bp;
+  const bool sf16 = h.ht_f == 2, sg16 = h.ht_g == 2;
+  hipError_t e = launch_rfft_rows(r, B, g.nobs, g.nobs, R, 1, bp, (int64_t)g.nobs * bp, g, 1.0f, st);
+  if (e == hipSuccess && sf16) e = launch_act_scale(R, g.M, g.nobs, g.nobs, B, bp, sig_up, sig_down, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
+  // W[g][l][b] = sF[g][l] * sum_o conj(Fq[l][o][g]) R[l][o][b]
+  e = launch_gemm_t(h.ht_f, h.hterms_f, 0, Fq, (int64_t)h.noq * h.ngq, h.ngq, g.ngrid, h.ngq, g.nobs, h.noq, R,
+                    (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
+                    (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
+  e = launch_mid_batch(W, sG, B, bp, true, false, g, st);
+  if (e == hipSuccess && sg16) e = launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
+  // part[split][l][j][n] = sum_{g in split} conj(Gq[g][l][j]) W'[g][l][b]
+  const int64_t prow = 2 * (int64_t)bp;
+  const int tiles = g.M * ((g.nsub + 255) / 256) * ((2 * B + 63) / 64);
+  const int fit = std::max(1, std::max(h.splits_max * h.noq, h.nsq) / h.nsq);
+  int sa = p->tune.adj32_splits > 0 ? p->tune.adj32_splits : std::max(1, 2048 / std::max(1, tiles));
+  sa = std::min(std::min(std::min(sa, fit), 8), (g.ngrid + 15) / 16);
+  e = mark(p->ev_begin, st);
+  if (e == hipSuccess)
+    e = launch_gemm_t(h.ht_g, h.hterms_g, 1, Gq, h.nsq, (int64_t)g.M * h.nsq, g.nsub, h.nsq, g.ngrid,
+                      (g.ngrid + 15) / 16 * 16, W, bp, (int64_t)g.M * bp, g.ngrid, sg16 ? tau_up : nullptr,
+                      sg16 ? tau_down : nullptr, nullptr, 0, 0, part, (int64_t)g.M * h.nsq * prow,
+                      (int64_t)h.nsq * prow, prow, B, bp, g.M, sa, st);
+  if (e == hipSuccess) e = mark(p->ev_end, st);
+  if (e == hipSuccess) e = launch_sum_f(part, sa, g.M, h.nsq, g.nsub, B, bp, nullptr, gh, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: elastic matrix-core stage");
+  e = launch_irfft_rows(gh, (int64_t)B * g.nsub, g.M, 1, gs, g.nt, g, 1.0f / (float)g.L, st);
+  if (e != hipSuccess) return hip_fail(p, e, "adjoint: output transform");
+  return S2W_OK;
+}
+
 s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
   s2w_status cs = check_call(p, s, B, y, "forward");
   if (cs != S2W_OK || B == 0) return cs;
@@ -787,7 +840,7 @@ s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* 
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "adjoint: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
-  if (p->hg.on) return fail(p, S2W_EUNSUPPORTED, "adjoint: not available for half-precision stores in this build");
+  if (p->hg.on) return adjoint_half(p, r, B, gs, st);
   if (p->fb.on) return adjoint_b32(p, r, B, gs, st);
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);

@@ -95,6 +95,15 @@ hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const
 hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs, int B, int bp, const float* tau_down,
                         float2* yh, hipStream_t st);
 hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st);
+hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int bp, float* sig_up, float* sig_down,
+                            hipStream_t st);
+// Conjugate-transposed half-precision GEMM per slot (adjoint products); see the kernel.
+// shape 0: tall operator (many rows, short K); shape 1: few rows, long K.
+hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k, int nrows,
+                         int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
+                         int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
+                         int64_t rs_l, float* out, int64_t o_split, int64_t o_slot, int64_t o_row, int B, int bp,
+                         int M, int splits, hipStream_t st);
 
 // ---- batched path (matrix cores, float32 stores) ----
 // Per-slot complex GEMM out(row, b) = sum_k op(A(row, k)) X(k, b) for every slot l < M:

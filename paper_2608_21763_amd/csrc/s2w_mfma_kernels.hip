@@ -20,6 +20,8 @@
 //   D (16 x 16): column l%16, rows 4*(l/16) .. +3        (4 floats)
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "s2w_internal.h"
 
 namespace s2w {
@@ -1189,6 +1191,242 @@ hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const
                        : gemm_f_h<1, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
   return hterms == 2 ? gemm_f_h<2, 2, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st)
                      : gemm_f_h<2, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Conjugate-transposed half-precision GEMM per slot (the adjoint's per-bin products):
+//   out(row, b) = rowscale(row, l) * down(l, b) * sum_k conj(A(k, row)) * up(l, b) * X(k, b)
+// A is a half-precision store read transposed: A(k, row) at Aq + l*a_slot + k*a_k + row (32-bit
+// words re | im << 16, rows contiguous); rows < rows_alloc are readable, k < kvalid are real.
+// X is a complex64 activation X(k, b) at X + l*x_slot + k*x_k + b, split into H half terms in
+// registers after the optional power-of-two scale up(l, b).  The operator tile of a K step (16
+// k x RT rows) is staged through LDS (double-buffered) and read back as fragments of four
+// consecutive k; conjugation flips the sign of the imaginary halves, except in the packed real
+// slot 0 where the products are componentwise.  K may be split over workgroups (one partial
+// per split, out + split*o_split).
+struct TArgs {
+  const uint32_t* Aq;
+  int64_t a_slot, a_k;
+  int nrows, rows_alloc, kvalid, nks;  // nks: K steps of 16 over the padded K range
+  const float2* X;
+  int64_t x_slot, x_k;
+  int xk_alloc;
+  const float* up;                     // [l][bp] or null
+  const float* down;                   // [l][bp] or null
+  const float* rowscale;               // rowscale[row * rs_row + l * rs_l] or null
+  int64_t rs_row, rs_l;
+  float* out;
+  int64_t o_split, o_slot, o_row;      // float strides; column n = 2*b + (0 re, 1 im)
+  int B, bp, nrt, nct, splits;
+};
+
+template <int RT, int PER_T>
+__device__ __forceinline__ void gt_load(const TArgs& p, const uint32_t* Al, int ks, int row0, int tid, uint4* st) {
+  constexpr int A_U4 = 16 * RT / 4;
+#pragma unroll
+  for (int it = 0; it < PER_T; ++it) {
+    const int i = tid + 256 * it;
+    if (i < A_U4) {
+      const int kk = i / (RT / 4), rg = i % (RT / 4);
+      const int k = 16 * ks + kk;
+      const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
+      uint4 v = *reinterpret_cast<const uint4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
+      if (k >= p.kvalid) v = make_uint4(0u, 0u, 0u, 0u);
+      st[it] = v;
+    }
+  }
+}
+
+template <int RT, int LDA, int PER_T>
+__device__ __forceinline__ void gt_put(uint32_t* buf, int tid, const uint4* st) {
+  constexpr int A_U4 = 16 * RT / 4;
+#pragma unroll
+  for (int it = 0; it < PER_T; ++it) {
+    const int i = tid + 256 * it;
+    if (i < A_U4) {
+      const int kk = i / (RT / 4), rg = i % (RT / 4);
+      *reinterpret_cast<uint4*>(buf + kk * LDA + 4 * rg) = st[it];
+    }
+  }
+}
+
+template <int HT, int H, int MF, int NF, int WR, int WC>
+__global__ __launch_bounds__(256) void k_gemm_t(const TArgs p) {
+  static_assert(WR * WC == 4, "four waves");
+  constexpr int RT = 16 * MF * WR;        // rows per tile
+  constexpr int LDA = RT + 4;             // padded LDS row (words)
+  constexpr int PER_T = (16 * RT / 4 + 255) / 256;
+  __shared__ uint32_t lds[2][16 * LDA];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per_slot = p.nrt * p.nct * p.splits;
+  const int l = x + 8 * (q / per_slot);
+  int rem = q % per_slot;
+  const int split = rem % p.splits;
+  rem /= p.splits;
+  const int ct = rem % p.nct, rt = rem / p.nct;
+  const bool dc = (l == 0);
+  const uint32_t cmask = dc ? 0u : 0x80000000u;
+  const int ks0 = (int)((int64_t)p.nks * split / p.splits), ks1 = (int)((int64_t)p.nks * (split + 1) / p.splits);
+  const int row0 = rt * RT;
+  const int cb0 = (ct * WC + wc) * NF;
+  const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
+  const float2* Xl = p.X + (int64_t)l * p.x_slot;
+  int rup[NF], cim[NF];
+  float upv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const int n = 16 * (cb0 + f) + (lane & 15);
+    rup[f] = min(n >> 1, p.bp - 1);
+    cim[f] = n & 1;
+    upv[f] = p.up ? p.up[(int64_t)l * p.bp + rup[f]] : 1.f;
+  }
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (ks0 < ks1) {
+    uint4 st[PER_T];
+    gt_load<RT, PER_T>(p, Al, ks0, row0, tid, st);
+    gt_put<RT, LDA, PER_T>(lds[0], tid, st);
+    __syncthreads();
+    for (int ks = ks0; ks < ks1; ++ks) {
+      const int cur = (ks - ks0) & 1;
+      const bool more = ks + 1 < ks1;
+      if (more) gt_load<RT, PER_T>(p, Al, ks + 1, row0, tid, st);
+      uint4 av[MF];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) {
+        const int r = 16 * (MF * wr + a) + (lane & 15);
+        const uint32_t* la = &lds[cur][(4 * (lane >> 4)) * LDA + r];
+        av[a] = make_uint4(la[0] ^ cmask, la[LDA] ^ cmask, la[2 * LDA] ^ cmask, la[3 * LDA] ^ cmask);
+      }
+      const int kb = 16 * ks + 4 * (lane >> 4);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        uint32_t hi[4], lo[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          const int k = kb + e2;
+          float2 v = Xl[(int64_t)min(k, p.xk_alloc - 1) * p.x_k + rup[f]];
+          if (k >= p.kvalid) v = make_float2(0.f, 0.f);
+          v.x *= upv[f];
+          v.y *= upv[f];
+          float v0, v1;
+          if (dc) {
+            v0 = cim[f] == 0 ? v.x : 0.f;
+            v1 = cim[f] == 0 ? 0.f : v.y;
+          } else {
+            v0 = cim[f] == 0 ? v.x : v.y;
+            v1 = cim[f] == 0 ? -v.y : v.x;
+          }
+          const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
+          hi[e2] = h0 | (h1 << 16);
+          if (H == 2)
+            lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) |
+                     (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
+        }
+        const uint4 bh = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+#pragma unroll
+        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
+        if (H == 2) {
+          const uint4 bl = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+#pragma unroll
+          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bl, acc[a][f]);
+        }
+      }
+      if (more) gt_put<RT, LDA, PER_T>(lds[cur ^ 1], tid, st);
+      __syncthreads();
+    }
+  }
+  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
+      if (row < p.nrows) {
+        const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int n = 16 * (cb0 + f) + (lane & 15);
+          const int b = n >> 1;
+          if (b < p.B) {
+            const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
+            ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
+          }
+        }
+      }
+    }
+}
+
+// shape 0: 64 rows x 256 columns per workgroup (many rows, short K);
+// shape 1: 256 rows x 64 columns (few rows, long K)
+hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k, int nrows,
+                         int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
+                         int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
+                         int64_t rs_l, float* out, int64_t o_split, int64_t o_slot, int64_t o_row, int B, int bp,
+                         int M, int splits, hipStream_t st) {
+  constexpr int MF = 4, NF = 4;
+  if ((M & 7) || kpad % 16 || kpad < kvalid || kvalid < 1 || rows_alloc % 4 || rows_alloc < nrows || nrows < 1 ||
+      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || (shape != 0 && shape != 1))
+    return hipErrorInvalidValue;
+  const int rt = shape == 0 ? 64 : 256, ctc = shape == 0 ? 256 : 64;
+  TArgs a;
+  a.Aq = Aq;
+  a.a_slot = a_slot;
+  a.a_k = a_k;
+  a.nrows = nrows;
+  a.rows_alloc = rows_alloc;
+  a.kvalid = kvalid;
+  a.nks = kpad / 16;
+  a.X = X;
+  a.x_slot = x_slot;
+  a.x_k = x_k;
+  a.xk_alloc = xk_alloc;
+  a.up = up;
+  a.down = down;
+  a.rowscale = rowscale;
+  a.rs_row = rs_row;
+  a.rs_l = rs_l;
+  a.out = out;
+  a.o_split = o_split;
+  a.o_slot = o_slot;
+  a.o_row = o_row;
+  a.B = B;
+  a.bp = bp;
+  a.nrt = (nrows + rt - 1) / rt;
+  a.nct = (2 * B + ctc - 1) / ctc;
+  a.splits = std::min(splits, a.nks);
+  const int64_t blocks = (int64_t)M * a.nrt * a.nct * a.splits;
+  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)blocks);
+#define S2W_GT(HT_, H_, WR_, WC_) hipLaunchKernelGGL((k_gemm_t<HT_, H_, MF, NF, WR_, WC_>), grid, dim3(256), 0, st, a)
+  if (shape == 0) {
+    if (ht == 1) {
+      if (hterms == 2) S2W_GT(1, 2, 1, 4); else S2W_GT(1, 1, 1, 4);
+    } else {
+      if (hterms == 2) S2W_GT(2, 2, 1, 4); else S2W_GT(2, 1, 1, 4);
+    }
+  } else {
+    if (ht == 1) {
+      if (hterms == 2) S2W_GT(1, 2, 4, 1); else S2W_GT(1, 1, 4, 1);
+    } else {
+      if (hterms == 2) S2W_GT(2, 2, 4, 1); else S2W_GT(2, 1, 4, 1);
+    }
+  }
+#undef S2W_GT
+  return hipGetLastError();
+}
+
+hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int bp, float* sig_up, float* sig_down,
+                            hipStream_t st) {
+  const int64_t ns = (int64_t)M * bp;
+  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nk, nkp, B, bp, sig_up,
+                     sig_down);
+  return hipGetLastError();
 }
 
 // Column scales of the acoustic GEMM's activation (float16 operands only): for each (l, b),

@@ -66,13 +66,61 @@ def test_ragged_shapes_half(shape):
     _check(cfg, op, 5, 0.75, 1, dtypes=("f16", "f16"))
 
 
-def test_half_adjoint_is_reported_unsupported():
-    from paper_2608_21763_amd import S2WError
+def _check_adjoint(cfg, op, B, dt, dtypes, first=0):
+    # the half-precision adjoint against the FP64 oracle's exact transpose, and the dot-product
+    # identity <A s, r> = <s, A^T r> against the same plan's forward (both sides quantized the same)
+    r = synth.normals(cfg.seed, "r", first, (B, cfg.nobs, cfg.nt))
+    s = synth.gen_slip_batch(cfg, first, B)
+    g = op.adjoint(to_dev(r)).cpu().numpy()
+    y = op.forward(to_dev(s)).cpu().numpy()
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    errs = oracle.rel_l2_per_rupture(g, oracle.adjoint(G, F, r, dt=dt))
+    print(dtypes, "adjoint B", B, "rel-L2 per rupture", " ".join(f"{e:.2e}" for e in errs))
+    assert np.all(np.isfinite(g))
+    assert errs.max() <= BOUND[tuple(dtypes)]
+    for b in range(min(B, 4)):
+        lhs = np.sum(y[b].astype(np.float64) * r[b])
+        rhs = np.sum(s[b].astype(np.float64) * g[b])
+        assert abs(lhs - rhs) <= BOUND[tuple(dtypes)] * np.linalg.norm(y[b]) * np.linalg.norm(r[b])
+
+
+@pytest.mark.parametrize("dtypes", [("bf16", "bf16"), ("f16", "f16"), ("bf16", "f16"), ("f16", "bf16")])
+def test_half_adjoint_dense_small(dtypes):
     cfg = synth.workload("small_dense")
-    op = make_operator(cfg, max_batch=1, g_dtype="bf16", f_dtype="bf16")
-    with pytest.raises(S2WError) as e:
-        op.adjoint(to_dev(np.zeros((1, cfg.nobs, cfg.nt))))
-    assert e.value.code == "S2W_EUNSUPPORTED"
+    log_case("half_adjoint_dense", dtypes=dtypes)
+    op = make_operator(cfg, max_batch=12, dt=0.5, g_dtype=dtypes[0], f_dtype=dtypes[1])
+    _check_adjoint(cfg, op, 12, 0.5, dtypes)
+
+
+@pytest.mark.parametrize("shape", HALF_SHAPES, ids=[f"{a}x{b}x{c}x{d}" for a, b, c, d in HALF_SHAPES])
+def test_half_adjoint_ragged_shapes(shape):
+    nsub, ngrid, nobs, nt = shape
+    cfg = synth.SynthConfig(nsub=nsub, ngrid=ngrid, nobs=nobs, nt=nt, seed=97, slip_seed=98, op_kind="dense",
+                            slip_mode="dense")
+    log_case("half_adjoint_ragged", shape=shape)
+    op = make_operator(cfg, max_batch=5, dt=0.75, g_dtype="f16", f_dtype="f16", chunk_rows=13)
+    _check_adjoint(cfg, op, 5, 0.75, ("f16", "f16"))
+
+
+@pytest.mark.parametrize("B", [1, 9, 70, 300])
+def test_half_adjoint_batch_sizes(B):
+    # spans one and several column tiles of both transposed products, with a ragged last tile
+    cfg = synth.SynthConfig(nsub=300, ngrid=200, nobs=20, nt=40, seed=99, slip_seed=100, op_kind="dense",
+                            slip_mode="dense")
+    log_case("half_adjoint_batches", B=B)
+    op = make_operator(cfg, max_batch=B, g_dtype="bf16", f_dtype="bf16")
+    _check_adjoint(cfg, op, B, cfg.dt, ("bf16", "bf16"))
+
+
+def test_half_adjoint_split_counts_agree():
+    # the grid-row reduction split over 1, 2, 5 and 8 workgroups agrees with the oracle each time
+    cfg = synth.SynthConfig(nsub=40, ngrid=700, nobs=6, nt=32, seed=101, slip_seed=102, op_kind="dense",
+                            slip_mode="dense")
+    log_case("half_adjoint_splits")
+    op = make_operator(cfg, max_batch=3, g_dtype="f16", f_dtype="f16")
+    for sa in (1, 2, 5, 8):
+        op.set_tuning(adj32_splits=sa)
+        _check_adjoint(cfg, op, 3, cfg.dt, ("f16", "f16"))
 
 
 @pytest.mark.parametrize("B", [40, 130])
