@@ -771,13 +771,16 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(Gq[g][l][j]) W'[g][l][b]
   const int64_t prow = 2 * (int64_t)bp;
-  const int tiles = g.M * ((g.nsub + 255) / 256) * ((2 * B + 63) / 64);
+  // eight-wave tile of 256 subfault rows x 64, 128 or 256 columns (32, 64 or 128 residuals)
+  const int shape3 = B <= 32 ? 2 : (B <= 64 ? 3 : 4);
+  const int cols3 = shape3 == 2 ? 64 : (shape3 == 3 ? 128 : 256);
+  const int tiles = g.M * ((g.nsub + 255) / 256) * ((2 * B + cols3 - 1) / cols3);
   const int fit = std::max(1, std::max(h.splits_max * h.noq, h.nsq) / h.nsq);
   int sa = p->tune.adj32_splits > 0 ? p->tune.adj32_splits : std::max(1, 2048 / std::max(1, tiles));
   sa = std::min(std::min(std::min(sa, fit), 8), (g.ngrid + 15) / 16);
   e = mark(p->ev_begin, st);
   if (e == hipSuccess)
-    e = launch_gemm_t(h.ht_g, h.hterms_g, 1, Gq, h.nsq, (int64_t)g.M * h.nsq, g.nsub, h.nsq, g.ngrid,
+    e = launch_gemm_t(h.ht_g, h.hterms_g, shape3, Gq, h.nsq, (int64_t)g.M * h.nsq, g.nsub, h.nsq, g.ngrid,
                       (g.ngrid + 15) / 16 * 16, W, bp, (int64_t)g.M * bp, g.ngrid, sg16 ? tau_up : nullptr,
                       sg16 ? tau_down : nullptr, nullptr, 0, 0, part, (int64_t)g.M * h.nsq * prow,
                       (int64_t)h.nsq * prow, prow, B, bp, g.M, sa, st);

@@ -42,16 +42,29 @@ template <int HT>
 __device__ __forceinline__ uint32_t to_half_bits(float v);
 template <>
 __device__ __forceinline__ uint32_t to_half_bits<1>(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+  // round to nearest even (the hardware conversion)
+  const __bf16 h = (__bf16)v;
+  return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 template <>
 __device__ __forceinline__ uint32_t to_half_bits<2>(float v) {
   _Float16 h = (_Float16)v;
   return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
+typedef float s2w_f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 s2w_b2v __attribute__((ext_vector_type(2)));
+typedef _Float16 s2w_h2v __attribute__((ext_vector_type(2)));
+
+// Two values rounded to nearest even into one word: a in the low half, b in the high half.
+template <int HT>
+__device__ __forceinline__ uint32_t pack_half2(float a, float b) {
+  const s2w_f2v v = {a, b};
+  if constexpr (HT == 1)
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, s2w_b2v));
+  else
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, s2w_h2v));
+}
+
 template <int HT>
 __device__ __forceinline__ float from_half_bits(uint32_t b);
 template <>
@@ -1362,8 +1375,165 @@ __global__ __launch_bounds__(256) void k_gemm_t(const TArgs p) {
     }
 }
 
+// Eight-wave variant for the long-K product: a 256-row x 32*NF-column tile per workgroup (waves
+// 4 x 2, each 64 rows x 16*NF columns).  Per K step of 16 both operands pass through LDS, double
+// buffered with one barrier per step: the operator tile as [k][row] words, the activation
+// converted once per workgroup into MFMA B fragments (H terms) by threads that each own four
+// consecutive k of one rupture.  The next step's global loads are issued before the current
+// step's matrix products.
+template <int NF>
+struct T2Geo {
+  static constexpr int RT = 256, LDA = RT + 4, RB = 16 * NF;  // rows, LDS row words, ruptures per tile
+  static constexpr int NCB = 2 * NF;                           // 16-column blocks per tile
+};
+
+// One B-fragment granule per thread and term: lane L = 16*kg + c16 of column block cb holds the
+// four k = 4*kg + e of column n = 16*cb + c16 (rupture n/2; real part if n even, else imaginary).
+template <int HT, int H>
+__device__ __forceinline__ void t2_convert(const float2* v, float up, bool dc, int cim, uint4* dst) {
+  uint32_t hi[4], lo[4];
+#pragma unroll
+  for (int e2 = 0; e2 < 4; ++e2) {
+    const float x = v[e2].x * up, y = v[e2].y * up;
+    // column re: (x, -y) (DC: (x, 0)); column im: (y, x) (DC: (0, y))
+    const float c0 = cim ? (dc ? 0.f : y) : x;
+    const float c1 = cim ? (dc ? y : x) : (dc ? 0.f : -y);
+    hi[e2] = pack_half2<HT>(c0, c1);
+    if (H == 2)
+      lo[e2] = pack_half2<HT>(c0 - from_half_bits<HT>(hi[e2] & 0xffffu), c1 - from_half_bits<HT>(hi[e2] >> 16));
+  }
+  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+}
+
+template <int HT, int H, int NF>
+__global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
+  using Gm = T2Geo<NF>;
+  constexpr int RT = Gm::RT, LDA = Gm::LDA, RB = Gm::RB, NCB = Gm::NCB;
+  constexpr int MF = 4;
+  __shared__ uint32_t la_s[2][16 * LDA];
+  __shared__ uint4 lb_s[2][NCB * H * 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per_slot = p.nrt * p.nct * p.splits;
+  const int l = x + 8 * (q / per_slot);
+  int rem = q % per_slot;
+  const int split = rem % p.splits;
+  rem /= p.splits;
+  const int ct = rem % p.nct, rt = rem / p.nct;
+  const bool dc = (l == 0);
+  const uint32_t cmask = dc ? 0u : 0x80000000u;
+  const int ks0 = (int)((int64_t)p.nks * split / p.splits), ks1 = (int)((int64_t)p.nks * (split + 1) / p.splits);
+  const int row0 = rt * RT;
+  const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
+  const float2* Xl = p.X + (int64_t)l * p.x_slot;
+  // activation ownership: granule slot s = tid + 512 * rep -> column block s / 64, lane s % 64
+  constexpr int XSLOTS = NCB * 64, XREP = (XSLOTS + 511) / 512;
+  int bx[XREP], xkg[XREP];
+  float upx[XREP];
+#pragma unroll
+  for (int rp = 0; rp < XREP; ++rp) {
+    const int s = min(tid + 512 * rp, XSLOTS - 1);
+    const int L = s & 63;
+    xkg[rp] = L >> 4;
+    bx[rp] = min(ct * RB + 8 * (s >> 6) + ((L & 15) >> 1), p.bp - 1);
+    upx[rp] = p.up ? p.up[(int64_t)l * p.bp + bx[rp]] : 1.f;
+  }
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+  uint4 ast[2];
+  float2 xv[XREP][4];
+  auto fetch = [&](int ks) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int i = tid + 512 * it;  // 16 k x 64 row groups
+      const int kk = i >> 6, rg = i & 63;
+      const int k = 16 * ks + kk;
+      const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
+      uint4 v = *reinterpret_cast<const uint4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
+      ast[it] = k < p.kvalid ? v : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int rp = 0; rp < XREP; ++rp)
+#pragma unroll
+      for (int e2 = 0; e2 < 4; ++e2) {
+        const int k = 16 * ks + 4 * xkg[rp] + e2;
+        const float2 v = Xl[(int64_t)min(k, p.xk_alloc - 1) * p.x_k + bx[rp]];
+        xv[rp][e2] = k < p.kvalid ? v : make_float2(0.f, 0.f);
+      }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int i = tid + 512 * it;
+      const int kk = i >> 6, rg = i & 63;
+      *reinterpret_cast<uint4*>(&la_s[buf][kk * LDA + 4 * rg]) = ast[it];
+    }
+#pragma unroll
+    for (int rp = 0; rp < XREP; ++rp) {
+      const int s = tid + 512 * rp;
+      if (s < XSLOTS) t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, &lb_s[buf][(s >> 6) * H * 64 + (s & 63)]);
+    }
+  };
+  if (ks0 < ks1) {
+    fetch(ks0);
+    stage(0);
+    __syncthreads();
+    for (int ks = ks0; ks < ks1; ++ks) {
+      const int cur = (ks - ks0) & 1;
+      const bool more = ks + 1 < ks1;
+      if (more) fetch(ks + 1);
+      uint4 av[MF];
+#pragma unroll
+      for (int a = 0; a < MF; ++a) {
+        const int r = 16 * (MF * wr + a) + (lane & 15);
+        const uint32_t* la = &la_s[cur][(4 * (lane >> 4)) * LDA + r];
+        av[a] = make_uint4(la[0] ^ cmask, la[LDA] ^ cmask, la[2 * LDA] ^ cmask, la[3 * LDA] ^ cmask);
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int cb = NF * wc + f;
+        const uint4 bh = lb_s[cur][cb * H * 64 + lane];
+#pragma unroll
+        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
+        if (H == 2) {
+          const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
+#pragma unroll
+          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+        }
+      }
+      if (more) stage(cur ^ 1);
+      __syncthreads();
+    }
+  }
+  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
+      if (row < p.nrows) {
+        const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int n = 2 * ct * RB + 16 * (NF * wc + f) + (lane & 15);
+          const int b = n >> 1;
+          if (b < p.B) {
+            const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
+            ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
+          }
+        }
+      }
+    }
+}
+
 // shape 0: 64 rows x 256 columns per workgroup (many rows, short K);
-// shape 1: 256 rows x 64 columns (few rows, long K)
+// shape 1: 256 rows x 64 columns (few rows, long K);
+// shapes 2, 3, 4: eight waves, 256 rows x 64, 128 or 256 columns, both operands staged in LDS
 hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k, int nrows,
                          int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
                          int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
@@ -1371,9 +1541,10 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
                          int M, int splits, hipStream_t st) {
   constexpr int MF = 4, NF = 4;
   if ((M & 7) || kpad % 16 || kpad < kvalid || kvalid < 1 || rows_alloc % 4 || rows_alloc < nrows || nrows < 1 ||
-      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || (shape != 0 && shape != 1))
+      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || shape < 0 || shape > 4)
     return hipErrorInvalidValue;
-  const int rt = shape == 0 ? 64 : 256, ctc = shape == 0 ? 256 : 64;
+  const int rt = shape == 0 ? 64 : 256;
+  const int ctc = shape == 0 ? 256 : shape == 1 ? 64 : shape == 2 ? 64 : shape == 3 ? 128 : 256;
   TArgs a;
   a.Aq = Aq;
   a.a_slot = a_slot;
@@ -1404,7 +1575,20 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
 #define S2W_GT(HT_, H_, WR_, WC_) hipLaunchKernelGGL((k_gemm_t<HT_, H_, MF, NF, WR_, WC_>), grid, dim3(256), 0, st, a)
-  if (shape == 0) {
+#define S2W_GT2(HT_, H_, NF_) hipLaunchKernelGGL((k_gemm_t2<HT_, H_, NF_>), grid, dim3(512), 0, st, a)
+#define S2W_GT2_NF(HT_, H_) \
+  do {                                                                        \
+    if (shape == 2) S2W_GT2(HT_, H_, 2);                                      \
+    else if (shape == 3) S2W_GT2(HT_, H_, 4);                                 \
+    else S2W_GT2(HT_, H_, 8);                                                 \
+  } while (0)
+  if (shape >= 2) {
+    if (ht == 1) {
+      if (hterms == 2) S2W_GT2_NF(1, 2); else S2W_GT2_NF(1, 1);
+    } else {
+      if (hterms == 2) S2W_GT2_NF(2, 2); else S2W_GT2_NF(2, 1);
+    }
+  } else if (shape == 0) {
     if (ht == 1) {
       if (hterms == 2) S2W_GT(1, 2, 1, 4); else S2W_GT(1, 1, 1, 4);
     } else {
@@ -1418,6 +1602,8 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
     }
   }
 #undef S2W_GT
+#undef S2W_GT2
+#undef S2W_GT2_NF
   return hipGetLastError();
 }
 

@@ -102,9 +102,10 @@ def test_half_adjoint_ragged_shapes(shape):
     _check_adjoint(cfg, op, 5, 0.75, ("f16", "f16"))
 
 
-@pytest.mark.parametrize("B", [1, 9, 70, 300])
+@pytest.mark.parametrize("B", [1, 9, 40, 70, 300])
 def test_half_adjoint_batch_sizes(B):
-    # spans one and several column tiles of both transposed products, with a ragged last tile
+    # spans one and several column tiles of both transposed products, with a ragged last tile,
+    # and the three column widths of the grid-row reduction (B <= 32, <= 64, > 64)
     cfg = synth.SynthConfig(nsub=300, ngrid=200, nobs=20, nt=40, seed=99, slip_seed=100, op_kind="dense",
                             slip_mode="dense")
     log_case("half_adjoint_batches", B=B)
