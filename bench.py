@@ -45,10 +45,11 @@ def log(*a):
 KERNEL_SOURCES = {
     "k_fused_forward": ["s2w_fft_kernels.hip", "s2w_device.h"],
     "k_mid_batch256": ["s2w_fft_kernels.hip", "s2w_device.h"],
-    "k_gemm_g": ["s2w_mfma_kernels.hip"],
-    "k_gemm_g2": ["s2w_mfma_kernels.hip"],
-    "k_gemm_g4": ["s2w_mfma_kernels.hip"],
-    "k_gemm_f2": ["s2w_mfma_kernels.hip"],
+    "k_gemm_g": ["s2w_mfma_kernels.hip", "s2w_half.h"],
+    "k_gemm_g2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
+    "k_gemm_g4": ["s2w_mfma_kernels.hip", "s2w_half.h"],
+    "k_gemm_f2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
+    "k_gemm_t2": ["s2w_mfma_adj_kernels.hip", "s2w_half.h"],
     "k_cgemm32": ["s2w_mfma32_kernels.hip"],
 }
 

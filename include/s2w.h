@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define S2W_ABI_VERSION 2
+#define S2W_ABI_VERSION 3
 
 typedef struct s2w_plan s2w_plan;
 
@@ -154,6 +154,10 @@ typedef struct s2w_tuning {
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
   int32_t adj32_splits;      /* batched adjoint (float32 and half stores), transposed elastic GEMM: grid-row
                                 splits (1..8; half stores may clamp to what the partial region holds) */
+  int32_t hadj_tile_f;       /* half-precision adjoint, transposed acoustic GEMM tile: -1 automatic, 1..5 =
+                                rows x columns 64 x 256, 256 x 64 (four waves), 256 x 64, 256 x 128,
+                                256 x 256 (eight waves, both operands through LDS) */
+  int32_t hadj_tile_g;       /* half-precision adjoint, transposed elastic GEMM tile: same values */
 } s2w_tuning;
 
 s2w_status s2w_set_tuning(s2w_plan* plan, const s2w_tuning* t);

@@ -20,8 +20,14 @@ import torch
 from .hiprt import HipEvent
 
 
-def candidates(op) -> list[dict]:
-    """Tuning dictionaries worth timing for this operator's path."""
+def candidates(op, adjoint: bool = False) -> list[dict]:
+    """Tuning dictionaries worth timing for this operator's path (forward, or adjoint)."""
+    if adjoint:
+        if op.g_dtype != "f32":
+            return [{"hadj_tile_f": a, "hadj_tile_g": b} for a in (1, 3, 4, 5) for b in (3, 4, 5)]
+        if op.plan_layout() == "batched":
+            return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
+        return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]
     if op.g_dtype != "f32":
         return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16) for f in (1, -1)]
     if op.plan_layout() == "batched":
@@ -54,7 +60,8 @@ def autotune(op, B: int, reps: int = 3, adjoint: bool | None = None, cache_path:
     """Pick the fastest tile shapes of ``op`` for batches of B and apply them.
 
     The objective is the time of one forward call, plus one adjoint call when ``adjoint``
-    is true (default: whenever the path has an adjoint).  Returns
+    is true (the default; half-precision stores tune the adjoint's own tiles on the adjoint's
+    time).  Returns
     ``{"best": tuning, "ms": time, "results": [(tuning, ms), ...], "cached": bool}``.
     """
     if not 1 <= B <= op.max_batch:
@@ -68,7 +75,7 @@ def autotune(op, B: int, reps: int = 3, adjoint: bool | None = None, cache_path:
             op.set_tuning(**cache[key]["best"])
             return dict(cache[key], cached=True)
     if adjoint is None:
-        adjoint = op.g_dtype == "f32"
+        adjoint = True
     dev = op.device
     if s is None:
         s = torch.randn((B, op.nsub, op.nt), device=dev, dtype=torch.float32)
@@ -76,20 +83,35 @@ def autotune(op, B: int, reps: int = 3, adjoint: bool | None = None, cache_path:
     r = torch.randn((B, op.nobs, op.nt), device=dev, dtype=torch.float32) if adjoint else None
     gs = torch.empty((B, op.nsub, op.nt), device=dev, dtype=torch.float32) if adjoint else None
     base = op.get_tuning()
-    results = []
-    for cand in candidates(op):
-        op.set_tuning(**cand)
 
-        def call():
-            op.forward(s, out=y)
-            if adjoint:
-                op.adjoint(r, out=gs)
+    def fwd():
+        op.forward(s, out=y)
 
-        results.append((cand, _time(op, call, reps)))
-    best, ms = min(results, key=lambda t: t[1])
-    restore = {k: base[k] for k in best}
-    op.set_tuning(**restore)
-    op.set_tuning(**best)
+    def adj():
+        op.adjoint(r, out=gs)
+
+    def both():
+        fwd()
+        adj()
+
+    if op.g_dtype != "f32" and adjoint:
+        # the half-precision adjoint has tile controls of its own: tune the two calls apart
+        phases = [(candidates(op), fwd), (candidates(op, adjoint=True), adj)]
+    else:
+        # the float32 tile controls serve the forward and the adjoint products alike
+        phases = [(candidates(op), both if adjoint else fwd)]
+    results, best, ms = [], {}, 0.0
+    for cands, call in phases:
+        timed = []
+        for cand in cands:
+            op.set_tuning(**cand)
+            timed.append((cand, _time(op, call, reps)))
+        pbest, pms = min(timed, key=lambda t: t[1])
+        op.set_tuning(**{k: base[k] for k in pbest})
+        op.set_tuning(**pbest)
+        results += timed
+        best.update(pbest)
+        ms += pms
     out = {"best": best, "ms": ms, "results": results, "cached": False}
     if cache_path:
         cache[key] = {"best": best, "ms": ms, "results": results}

@@ -320,6 +320,8 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.gemm32_cfg_k = -1;
   p->tune.gemm32_splits = 0;
   p->tune.adj32_splits = 0;
+  p->tune.hadj_tile_f = -1;
+  p->tune.hadj_tile_g = -1;
   p->row_set.assign((size_t)d.ngrid, 0);
   p->rows_missing = d.ngrid;
   {
@@ -437,6 +439,14 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     if (t->fgemm_splits < 0 || t->fgemm_splits > 16) return fail(p, S2W_EINVAL, "tuning: fgemm_splits");
     n.fgemm_splits = t->fgemm_splits;
   }
+  if (t->hadj_tile_f) {
+    if (t->hadj_tile_f < -1 || t->hadj_tile_f > 5) return fail(p, S2W_EINVAL, "tuning: hadj_tile_f");
+    n.hadj_tile_f = t->hadj_tile_f < 0 ? -1 : t->hadj_tile_f - 1;
+  }
+  if (t->hadj_tile_g) {
+    if (t->hadj_tile_g < -1 || t->hadj_tile_g > 5) return fail(p, S2W_EINVAL, "tuning: hadj_tile_g");
+    n.hadj_tile_g = t->hadj_tile_g < 0 ? -1 : t->hadj_tile_g - 1;
+  }
   p->tune = n;
   return S2W_OK;
 }
@@ -446,6 +456,8 @@ s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   *t = p->tune;
   t->gemm32_cfg = p->tune.gemm32_cfg < 0 ? -1 : p->tune.gemm32_cfg + 1;
   t->gemm32_cfg_k = p->tune.gemm32_cfg_k < 0 ? -1 : p->tune.gemm32_cfg_k + 1;
+  t->hadj_tile_f = p->tune.hadj_tile_f < 0 ? -1 : p->tune.hadj_tile_f + 1;
+  t->hadj_tile_g = p->tune.hadj_tile_g < 0 ? -1 : p->tune.hadj_tile_g + 1;
   return S2W_OK;
 }
 
@@ -762,7 +774,10 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   if (e == hipSuccess && sf16) e = launch_act_scale(R, g.M, g.nobs, g.nobs, B, bp, sig_up, sig_down, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
   // W[g][l][b] = sF[g][l] * sum_o conj(Fq[l][o][g]) R[l][o][b]
-  e = launch_gemm_t(h.ht_f, h.hterms_f, 0, Fq, (int64_t)h.noq * h.ngq, h.ngq, g.ngrid, h.ngq, g.nobs, h.noq, R,
+  // default tiles (sweep on the Cascadia-sized share): eight waves, 256 rows x 128 columns, and
+  // 256 x 64 for batches of at most 32
+  const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 2 : 3);
+  e = launch_gemm_t(h.ht_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, h.ngq, g.ngrid, h.ngq, g.nobs, h.noq, R,
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
                     (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
@@ -771,10 +786,10 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(Gq[g][l][j]) W'[g][l][b]
   const int64_t prow = 2 * (int64_t)bp;
-  // eight-wave tile of 256 subfault rows x 64, 128 or 256 columns (32, 64 or 128 residuals)
-  const int shape3 = B <= 32 ? 2 : (B <= 64 ? 3 : 4);
-  const int cols3 = shape3 == 2 ? 64 : (shape3 == 3 ? 128 : 256);
-  const int tiles = g.M * ((g.nsub + 255) / 256) * ((2 * B + cols3 - 1) / cols3);
+  const int shape3 = p->tune.hadj_tile_g >= 0 ? p->tune.hadj_tile_g : (B <= 32 ? 2 : 3);
+  const int cols3 = shape3 == 0 ? 256 : shape3 == 1 ? 64 : shape3 == 2 ? 64 : (shape3 == 3 ? 128 : 256);
+  const int rows3 = shape3 == 0 ? 64 : 256;
+  const int tiles = g.M * ((g.nsub + rows3 - 1) / rows3) * ((2 * B + cols3 - 1) / cols3);
   const int fit = std::max(1, std::max(h.splits_max * h.noq, h.nsq) / h.nsq);
   int sa = p->tune.adj32_splits > 0 ? p->tune.adj32_splits : std::max(1, 2048 / std::max(1, tiles));
   sa = std::min(std::min(std::min(sa, fit), 8), (g.ngrid + 15) / 16);

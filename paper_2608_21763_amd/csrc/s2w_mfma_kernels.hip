@@ -18,90 +18,12 @@
 //   A (16 x 32): row l%16, K entries 8*(l/16) .. +7      (16 bytes, 4 complex operand values)
 //   B (32 x 16): column l%16, K entries 8*(l/16) .. +7
 //   D (16 x 16): column l%16, rows 4*(l/16) .. +3        (4 floats)
-#include <hip/hip_bf16.h>
-
 #include <algorithm>
 
+#include "s2w_half.h"
 #include "s2w_internal.h"
 
 namespace s2w {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// streaming 16-byte load that bypasses cache retention
-__device__ __forceinline__ uint4 ntload(const uint4* p) {
-  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
-
-// float -> half bits, round to nearest even
-template <int HT>
-__device__ __forceinline__ uint32_t to_half_bits(float v);
-template <>
-__device__ __forceinline__ uint32_t to_half_bits<1>(float v) {
-  // round to nearest even (the hardware conversion)
-  const __bf16 h = (__bf16)v;
-  return (uint32_t)__builtin_bit_cast(uint16_t, h);
-}
-template <>
-__device__ __forceinline__ uint32_t to_half_bits<2>(float v) {
-  _Float16 h = (_Float16)v;
-  return (uint32_t)__builtin_bit_cast(uint16_t, h);
-}
-typedef float s2w_f2v __attribute__((ext_vector_type(2)));
-typedef __bf16 s2w_b2v __attribute__((ext_vector_type(2)));
-typedef _Float16 s2w_h2v __attribute__((ext_vector_type(2)));
-
-// Two values rounded to nearest even into one word: a in the low half, b in the high half.
-template <int HT>
-__device__ __forceinline__ uint32_t pack_half2(float a, float b) {
-  const s2w_f2v v = {a, b};
-  if constexpr (HT == 1)
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, s2w_b2v));
-  else
-    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, s2w_h2v));
-}
-
-template <int HT>
-__device__ __forceinline__ float from_half_bits(uint32_t b);
-template <>
-__device__ __forceinline__ float from_half_bits<1>(uint32_t b) {
-  return __uint_as_float(b << 16);
-}
-template <>
-__device__ __forceinline__ float from_half_bits<2>(uint32_t b) {
-  return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
-}
-
-template <int HT>
-__device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
-  if constexpr (HT == 1)
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0,
-                                                  0, 0);
-}
-
-// power-of-two scale that maps a row maximum mx into [2^14, 2^15); returns the multiplier
-// applied before rounding (`up`) and its inverse (`down`)
-__device__ __forceinline__ void pow2_scale(float mx, float& up, float& down) {
-  if (!(mx > 0.f) || !isfinite(mx)) {
-    up = 1.f;
-    down = 1.f;
-    return;
-  }
-  int ex;
-  frexpf(mx, &ex);  // mx = f * 2^ex, f in [0.5, 1)
-  // rows whose largest entry is below 2^-111 keep the multiplier finite (<= 2^126); their
-  // scaled values then sit below 2^15 without filling the range, which is harmless
-  ex = ex < -111 ? -111 : ex;
-  up = ldexpf(1.f, 15 - ex);
-  down = ldexpf(1.f, ex - 15);
-}
 
 // ---------------------------------------------------------------------------------------------
 // Setup: quantize rows of float32 spectra.  staging[r][l][c] (complex, c < ncp stored, c < nc
@@ -1204,407 +1126,6 @@ hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const
                        : gemm_f_h<1, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
   return hterms == 2 ? gemm_f_h<2, 2, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st)
                      : gemm_f_h<2, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
-}
-
-// ---------------------------------------------------------------------------------------------
-// Conjugate-transposed half-precision GEMM per slot (the adjoint's per-bin products):
-//   out(row, b) = rowscale(row, l) * down(l, b) * sum_k conj(A(k, row)) * up(l, b) * X(k, b)
-// A is a half-precision store read transposed: A(k, row) at Aq + l*a_slot + k*a_k + row (32-bit
-// words re | im << 16, rows contiguous); rows < rows_alloc are readable, k < kvalid are real.
-// X is a complex64 activation X(k, b) at X + l*x_slot + k*x_k + b, split into H half terms in
-// registers after the optional power-of-two scale up(l, b).  The operator tile of a K step (16
-// k x RT rows) is staged through LDS (double-buffered) and read back as fragments of four
-// consecutive k; conjugation flips the sign of the imaginary halves, except in the packed real
-// slot 0 where the products are componentwise.  K may be split over workgroups (one partial
-// per split, out + split*o_split).
-struct TArgs {
-  const uint32_t* Aq;
-  int64_t a_slot, a_k;
-  int nrows, rows_alloc, kvalid, nks;  // nks: K steps of 16 over the padded K range
-  const float2* X;
-  int64_t x_slot, x_k;
-  int xk_alloc;
-  const float* up;                     // [l][bp] or null
-  const float* down;                   // [l][bp] or null
-  const float* rowscale;               // rowscale[row * rs_row + l * rs_l] or null
-  int64_t rs_row, rs_l;
-  float* out;
-  int64_t o_split, o_slot, o_row;      // float strides; column n = 2*b + (0 re, 1 im)
-  int B, bp, nrt, nct, splits;
-};
-
-template <int RT, int PER_T>
-__device__ __forceinline__ void gt_load(const TArgs& p, const uint32_t* Al, int ks, int row0, int tid, uint4* st) {
-  constexpr int A_U4 = 16 * RT / 4;
-#pragma unroll
-  for (int it = 0; it < PER_T; ++it) {
-    const int i = tid + 256 * it;
-    if (i < A_U4) {
-      const int kk = i / (RT / 4), rg = i % (RT / 4);
-      const int k = 16 * ks + kk;
-      const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
-      uint4 v = *reinterpret_cast<const uint4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
-      if (k >= p.kvalid) v = make_uint4(0u, 0u, 0u, 0u);
-      st[it] = v;
-    }
-  }
-}
-
-template <int RT, int LDA, int PER_T>
-__device__ __forceinline__ void gt_put(uint32_t* buf, int tid, const uint4* st) {
-  constexpr int A_U4 = 16 * RT / 4;
-#pragma unroll
-  for (int it = 0; it < PER_T; ++it) {
-    const int i = tid + 256 * it;
-    if (i < A_U4) {
-      const int kk = i / (RT / 4), rg = i % (RT / 4);
-      *reinterpret_cast<uint4*>(buf + kk * LDA + 4 * rg) = st[it];
-    }
-  }
-}
-
-template <int HT, int H, int MF, int NF, int WR, int WC>
-__global__ __launch_bounds__(256) void k_gemm_t(const TArgs p) {
-  static_assert(WR * WC == 4, "four waves");
-  constexpr int RT = 16 * MF * WR;        // rows per tile
-  constexpr int LDA = RT + 4;             // padded LDS row (words)
-  constexpr int PER_T = (16 * RT / 4 + 255) / 256;
-  __shared__ uint32_t lds[2][16 * LDA];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave / WC, wc = wave % WC;
-  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per_slot = p.nrt * p.nct * p.splits;
-  const int l = x + 8 * (q / per_slot);
-  int rem = q % per_slot;
-  const int split = rem % p.splits;
-  rem /= p.splits;
-  const int ct = rem % p.nct, rt = rem / p.nct;
-  const bool dc = (l == 0);
-  const uint32_t cmask = dc ? 0u : 0x80000000u;
-  const int ks0 = (int)((int64_t)p.nks * split / p.splits), ks1 = (int)((int64_t)p.nks * (split + 1) / p.splits);
-  const int row0 = rt * RT;
-  const int cb0 = (ct * WC + wc) * NF;
-  const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
-  const float2* Xl = p.X + (int64_t)l * p.x_slot;
-  int rup[NF], cim[NF];
-  float upv[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const int n = 16 * (cb0 + f) + (lane & 15);
-    rup[f] = min(n >> 1, p.bp - 1);
-    cim[f] = n & 1;
-    upv[f] = p.up ? p.up[(int64_t)l * p.bp + rup[f]] : 1.f;
-  }
-  f32x4 acc[MF][NF];
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (ks0 < ks1) {
-    uint4 st[PER_T];
-    gt_load<RT, PER_T>(p, Al, ks0, row0, tid, st);
-    gt_put<RT, LDA, PER_T>(lds[0], tid, st);
-    __syncthreads();
-    for (int ks = ks0; ks < ks1; ++ks) {
-      const int cur = (ks - ks0) & 1;
-      const bool more = ks + 1 < ks1;
-      if (more) gt_load<RT, PER_T>(p, Al, ks + 1, row0, tid, st);
-      uint4 av[MF];
-#pragma unroll
-      for (int a = 0; a < MF; ++a) {
-        const int r = 16 * (MF * wr + a) + (lane & 15);
-        const uint32_t* la = &lds[cur][(4 * (lane >> 4)) * LDA + r];
-        av[a] = make_uint4(la[0] ^ cmask, la[LDA] ^ cmask, la[2 * LDA] ^ cmask, la[3 * LDA] ^ cmask);
-      }
-      const int kb = 16 * ks + 4 * (lane >> 4);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        uint32_t hi[4], lo[4];
-#pragma unroll
-        for (int e2 = 0; e2 < 4; ++e2) {
-          const int k = kb + e2;
-          float2 v = Xl[(int64_t)min(k, p.xk_alloc - 1) * p.x_k + rup[f]];
-          if (k >= p.kvalid) v = make_float2(0.f, 0.f);
-          v.x *= upv[f];
-          v.y *= upv[f];
-          float v0, v1;
-          if (dc) {
-            v0 = cim[f] == 0 ? v.x : 0.f;
-            v1 = cim[f] == 0 ? 0.f : v.y;
-          } else {
-            v0 = cim[f] == 0 ? v.x : v.y;
-            v1 = cim[f] == 0 ? -v.y : v.x;
-          }
-          const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
-          hi[e2] = h0 | (h1 << 16);
-          if (H == 2)
-            lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) |
-                     (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
-        }
-        const uint4 bh = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-#pragma unroll
-        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
-        if (H == 2) {
-          const uint4 bl = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-#pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bl, acc[a][f]);
-        }
-      }
-      if (more) gt_put<RT, LDA, PER_T>(lds[cur ^ 1], tid, st);
-      __syncthreads();
-    }
-  }
-  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
-      if (row < p.nrows) {
-        const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const int n = 16 * (cb0 + f) + (lane & 15);
-          const int b = n >> 1;
-          if (b < p.B) {
-            const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
-            ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
-          }
-        }
-      }
-    }
-}
-
-// Eight-wave variant for the long-K product: a 256-row x 32*NF-column tile per workgroup (waves
-// 4 x 2, each 64 rows x 16*NF columns).  Per K step of 16 both operands pass through LDS, double
-// buffered with one barrier per step: the operator tile as [k][row] words, the activation
-// converted once per workgroup into MFMA B fragments (H terms) by threads that each own four
-// consecutive k of one rupture.  The next step's global loads are issued before the current
-// step's matrix products.
-template <int NF>
-struct T2Geo {
-  static constexpr int RT = 256, LDA = RT + 4, RB = 16 * NF;  // rows, LDS row words, ruptures per tile
-  static constexpr int NCB = 2 * NF;                           // 16-column blocks per tile
-};
-
-// One B-fragment granule per thread and term: lane L = 16*kg + c16 of column block cb holds the
-// four k = 4*kg + e of column n = 16*cb + c16 (rupture n/2; real part if n even, else imaginary).
-template <int HT, int H>
-__device__ __forceinline__ void t2_convert(const float2* v, float up, bool dc, int cim, uint4* dst) {
-  uint32_t hi[4], lo[4];
-#pragma unroll
-  for (int e2 = 0; e2 < 4; ++e2) {
-    const float x = v[e2].x * up, y = v[e2].y * up;
-    // column re: (x, -y) (DC: (x, 0)); column im: (y, x) (DC: (0, y))
-    const float c0 = cim ? (dc ? 0.f : y) : x;
-    const float c1 = cim ? (dc ? y : x) : (dc ? 0.f : -y);
-    hi[e2] = pack_half2<HT>(c0, c1);
-    if (H == 2)
-      lo[e2] = pack_half2<HT>(c0 - from_half_bits<HT>(hi[e2] & 0xffffu), c1 - from_half_bits<HT>(hi[e2] >> 16));
-  }
-  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-}
-
-template <int HT, int H, int NF>
-__global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
-  using Gm = T2Geo<NF>;
-  constexpr int RT = Gm::RT, LDA = Gm::LDA, RB = Gm::RB, NCB = Gm::NCB;
-  constexpr int MF = 4;
-  __shared__ uint32_t la_s[2][16 * LDA];
-  __shared__ uint4 lb_s[2][NCB * H * 64];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per_slot = p.nrt * p.nct * p.splits;
-  const int l = x + 8 * (q / per_slot);
-  int rem = q % per_slot;
-  const int split = rem % p.splits;
-  rem /= p.splits;
-  const int ct = rem % p.nct, rt = rem / p.nct;
-  const bool dc = (l == 0);
-  const uint32_t cmask = dc ? 0u : 0x80000000u;
-  const int ks0 = (int)((int64_t)p.nks * split / p.splits), ks1 = (int)((int64_t)p.nks * (split + 1) / p.splits);
-  const int row0 = rt * RT;
-  const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
-  const float2* Xl = p.X + (int64_t)l * p.x_slot;
-  // activation ownership: granule slot s = tid + 512 * rep -> column block s / 64, lane s % 64
-  constexpr int XSLOTS = NCB * 64, XREP = (XSLOTS + 511) / 512;
-  int bx[XREP], xkg[XREP];
-  float upx[XREP];
-#pragma unroll
-  for (int rp = 0; rp < XREP; ++rp) {
-    const int s = min(tid + 512 * rp, XSLOTS - 1);
-    const int L = s & 63;
-    xkg[rp] = L >> 4;
-    bx[rp] = min(ct * RB + 8 * (s >> 6) + ((L & 15) >> 1), p.bp - 1);
-    upx[rp] = p.up ? p.up[(int64_t)l * p.bp + bx[rp]] : 1.f;
-  }
-  f32x4 acc[MF][NF];
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-  uint4 ast[2];
-  float2 xv[XREP][4];
-  auto fetch = [&](int ks) {
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int i = tid + 512 * it;  // 16 k x 64 row groups
-      const int kk = i >> 6, rg = i & 63;
-      const int k = 16 * ks + kk;
-      const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
-      uint4 v = *reinterpret_cast<const uint4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
-      ast[it] = k < p.kvalid ? v : make_uint4(0u, 0u, 0u, 0u);
-    }
-#pragma unroll
-    for (int rp = 0; rp < XREP; ++rp)
-#pragma unroll
-      for (int e2 = 0; e2 < 4; ++e2) {
-        const int k = 16 * ks + 4 * xkg[rp] + e2;
-        const float2 v = Xl[(int64_t)min(k, p.xk_alloc - 1) * p.x_k + bx[rp]];
-        xv[rp][e2] = k < p.kvalid ? v : make_float2(0.f, 0.f);
-      }
-  };
-  auto stage = [&](int buf) {
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int i = tid + 512 * it;
-      const int kk = i >> 6, rg = i & 63;
-      *reinterpret_cast<uint4*>(&la_s[buf][kk * LDA + 4 * rg]) = ast[it];
-    }
-#pragma unroll
-    for (int rp = 0; rp < XREP; ++rp) {
-      const int s = tid + 512 * rp;
-      if (s < XSLOTS) t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, &lb_s[buf][(s >> 6) * H * 64 + (s & 63)]);
-    }
-  };
-  if (ks0 < ks1) {
-    fetch(ks0);
-    stage(0);
-    __syncthreads();
-    for (int ks = ks0; ks < ks1; ++ks) {
-      const int cur = (ks - ks0) & 1;
-      const bool more = ks + 1 < ks1;
-      if (more) fetch(ks + 1);
-      uint4 av[MF];
-#pragma unroll
-      for (int a = 0; a < MF; ++a) {
-        const int r = 16 * (MF * wr + a) + (lane & 15);
-        const uint32_t* la = &la_s[cur][(4 * (lane >> 4)) * LDA + r];
-        av[a] = make_uint4(la[0] ^ cmask, la[LDA] ^ cmask, la[2 * LDA] ^ cmask, la[3 * LDA] ^ cmask);
-      }
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const int cb = NF * wc + f;
-        const uint4 bh = lb_s[cur][cb * H * 64 + lane];
-#pragma unroll
-        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
-        if (H == 2) {
-          const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
-#pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
-        }
-      }
-      if (more) stage(cur ^ 1);
-      __syncthreads();
-    }
-  }
-  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
-      if (row < p.nrows) {
-        const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const int n = 2 * ct * RB + 16 * (NF * wc + f) + (lane & 15);
-          const int b = n >> 1;
-          if (b < p.B) {
-            const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
-            ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
-          }
-        }
-      }
-    }
-}
-
-// shape 0: 64 rows x 256 columns per workgroup (many rows, short K);
-// shape 1: 256 rows x 64 columns (few rows, long K);
-// shapes 2, 3, 4: eight waves, 256 rows x 64, 128 or 256 columns, both operands staged in LDS
-hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k, int nrows,
-                         int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
-                         int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
-                         int64_t rs_l, float* out, int64_t o_split, int64_t o_slot, int64_t o_row, int B, int bp,
-                         int M, int splits, hipStream_t st) {
-  constexpr int MF = 4, NF = 4;
-  if ((M & 7) || kpad % 16 || kpad < kvalid || kvalid < 1 || rows_alloc % 4 || rows_alloc < nrows || nrows < 1 ||
-      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || shape < 0 || shape > 4)
-    return hipErrorInvalidValue;
-  const int rt = shape == 0 ? 64 : 256;
-  const int ctc = shape == 0 ? 256 : shape == 1 ? 64 : shape == 2 ? 64 : shape == 3 ? 128 : 256;
-  TArgs a;
-  a.Aq = Aq;
-  a.a_slot = a_slot;
-  a.a_k = a_k;
-  a.nrows = nrows;
-  a.rows_alloc = rows_alloc;
-  a.kvalid = kvalid;
-  a.nks = kpad / 16;
-  a.X = X;
-  a.x_slot = x_slot;
-  a.x_k = x_k;
-  a.xk_alloc = xk_alloc;
-  a.up = up;
-  a.down = down;
-  a.rowscale = rowscale;
-  a.rs_row = rs_row;
-  a.rs_l = rs_l;
-  a.out = out;
-  a.o_split = o_split;
-  a.o_slot = o_slot;
-  a.o_row = o_row;
-  a.B = B;
-  a.bp = bp;
-  a.nrt = (nrows + rt - 1) / rt;
-  a.nct = (2 * B + ctc - 1) / ctc;
-  a.splits = std::min(splits, a.nks);
-  const int64_t blocks = (int64_t)M * a.nrt * a.nct * a.splits;
-  if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)blocks);
-#define S2W_GT(HT_, H_, WR_, WC_) hipLaunchKernelGGL((k_gemm_t<HT_, H_, MF, NF, WR_, WC_>), grid, dim3(256), 0, st, a)
-#define S2W_GT2(HT_, H_, NF_) hipLaunchKernelGGL((k_gemm_t2<HT_, H_, NF_>), grid, dim3(512), 0, st, a)
-#define S2W_GT2_NF(HT_, H_) \
-  do {                                                                        \
-    if (shape == 2) S2W_GT2(HT_, H_, 2);                                      \
-    else if (shape == 3) S2W_GT2(HT_, H_, 4);                                 \
-    else S2W_GT2(HT_, H_, 8);                                                 \
-  } while (0)
-  if (shape >= 2) {
-    if (ht == 1) {
-      if (hterms == 2) S2W_GT2_NF(1, 2); else S2W_GT2_NF(1, 1);
-    } else {
-      if (hterms == 2) S2W_GT2_NF(2, 2); else S2W_GT2_NF(2, 1);
-    }
-  } else if (shape == 0) {
-    if (ht == 1) {
-      if (hterms == 2) S2W_GT(1, 2, 1, 4); else S2W_GT(1, 1, 1, 4);
-    } else {
-      if (hterms == 2) S2W_GT(2, 2, 1, 4); else S2W_GT(2, 1, 1, 4);
-    }
-  } else {
-    if (ht == 1) {
-      if (hterms == 2) S2W_GT(1, 2, 4, 1); else S2W_GT(1, 1, 4, 1);
-    } else {
-      if (hterms == 2) S2W_GT(2, 2, 4, 1); else S2W_GT(2, 1, 4, 1);
-    }
-  }
-#undef S2W_GT
-#undef S2W_GT2
-#undef S2W_GT2_NF
-  return hipGetLastError();
 }
 
 hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int bp, float* sig_up, float* sig_down,

@@ -66,18 +66,18 @@ def test_graph_replays_match_eager(kind):
     g.replay()
     torch.cuda.synchronize()
     assert torch.equal(y, eager2)
-    if kind != "half":
-        r = to_dev(synth.normals(8, "r", 0, (B, cfg.nobs, cfg.nt)))
-        gs = torch.empty((B, cfg.nsub, cfg.nt), device="cuda:0")
-        adj = op.adjoint(r).clone()
-        ga = _capture(lambda: op.adjoint(r, out=gs))
-        for k in range(3):
-            gs.zero_()
-            op.forward(s2)
-            torch.cuda.synchronize()
-            ga.replay()
-            torch.cuda.synchronize()
-            assert torch.equal(gs, adj), f"adjoint replay {k}"
+    # every path's adjoint replays too
+    r = to_dev(synth.normals(8, "r", 0, (B, cfg.nobs, cfg.nt)))
+    gs = torch.empty((B, cfg.nsub, cfg.nt), device="cuda:0")
+    adj = op.adjoint(r).clone()
+    ga = _capture(lambda: op.adjoint(r, out=gs))
+    for k in range(3):
+        gs.zero_()
+        op.forward(s2)
+        torch.cuda.synchronize()
+        ga.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gs, adj), f"adjoint replay {k}"
 
 
 @pytest.mark.parametrize("kind", list(KINDS))
@@ -90,8 +90,12 @@ def test_autotune_keeps_results(kind, tmp_path):
     op = make_operator(cfg, max_batch=B, **KINDS[kind])
     if kind == "batched32":
         op.set_tuning(gemm32_splits=2, adj32_splits=2)    # fixed split counts: shapes alone vary
+    elif kind != "single":
+        op.set_tuning(adj32_splits=2)
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
+    r = to_dev(synth.normals(cfg.seed, "r", 0, (B, cfg.nobs, cfg.nt)))
     y0 = op.forward(s).clone()
+    g0 = op.adjoint(r).clone()
     cache = str(tmp_path / "tune.json")
     res = autotune(op, B, reps=2, cache_path=cache)
     assert not res["cached"] and len(res["results"]) > 1
@@ -101,5 +105,6 @@ def test_autotune_keeps_results(kind, tmp_path):
         np.testing.assert_allclose(y1.cpu().numpy(), y0.cpu().numpy(), rtol=0, atol=1e-5 * float(y0.abs().max()))
     else:
         assert torch.equal(y1, y0)
+        assert torch.equal(op.adjoint(r), g0)
     again = autotune(op, B, cache_path=cache)
     assert again["cached"] and again["best"] == res["best"]
