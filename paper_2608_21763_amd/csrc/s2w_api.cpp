@@ -166,8 +166,8 @@ Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, const
     L.fh = off;
     off = round_up(off + (uint64_t)g.ngrid * g.M * g.nop * c8, kAlign);
   } else {
-    L.gq = off;
-    off = round_up(off + (uint64_t)g.ngrid * g.M * h.nsq * 4, kAlign);
+    L.gq = off;  // row-block-major, grid rows padded to a multiple of 16
+    off = round_up(off + (uint64_t)h.ngq * g.M * h.nsq * 4, kAlign);
     L.sg = off;
     off = round_up(off + (uint64_t)g.ngrid * g.M * 4, kAlign);
     L.fq = off;
@@ -483,13 +483,13 @@ static s2w_status set_operators_half(s2w_plan* p, const float* G_chunk, const fl
     e = launch_rfft_rows(G_chunk + r * g.nsub * g.nt, n, g.nsub, h.nsq, stg, (int64_t)g.M * h.nsq, 1, h.nsq, g, 1.0f,
                          st);
     if (e == hipSuccess)
-      e = launch_quant_rows(h.ht_g, stg, n, g.M, g.nsub, h.nsq, Gq, row0 + r, (int64_t)g.M * h.nsq, h.nsq, 1, sG, st);
+      e = launch_quant_rows(h.ht_g, stg, n, g.M, g.nsub, h.nsq, Gq, row0 + r, 0, 0, 0, sG, h.ngq / 16, st);
     if (e != hipSuccess) return hip_fail(p, e, "set_operators: elastic transform/quantize");
     e = launch_rfft_rows(F_chunk + r * g.nobs * g.nt, n, g.nobs, h.noq, stg, (int64_t)g.M * h.noq, 1, h.noq, g, 1.0f,
                          st);
     if (e == hipSuccess)
       e = launch_quant_rows(h.ht_f, stg, n, g.M, g.nobs, h.noq, Fq, row0 + r, 1, (int64_t)h.noq * h.ngq, h.ngq, sF,
-                            st);
+                            0, st);
     if (e != hipSuccess) return hip_fail(p, e, "set_operators: acoustic transform/quantize");
   }
   return S2W_OK;
@@ -777,14 +777,15 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   // default tiles (sweep on the Cascadia-sized share): eight waves, 256 rows x 128 columns, and
   // 256 x 64 for batches of at most 32
   const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 2 : 3);
-  e = launch_gemm_t(h.ht_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, h.ngq, g.ngrid, h.ngq, g.nobs, h.noq, R,
+  e = launch_gemm_t(h.ht_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, 16 * (int64_t)h.ngq, h.ngq, 16, g.ngrid,
+                    h.ngq, g.nobs, h.noq, R,
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
                     (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
   e = launch_mid_batch(W, sG, B, bp, true, false, g, st);
   if (e == hipSuccess && sg16) e = launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
-  // part[split][l][j][n] = sum_{g in split} conj(Gq[g][l][j]) W'[g][l][b]
+  // part[split][l][j][n] = sum_{g in split} conj(G[g][l][j]) W'[g][l][b] (row-block-major store)
   const int64_t prow = 2 * (int64_t)bp;
   const int shape3 = p->tune.hadj_tile_g >= 0 ? p->tune.hadj_tile_g : (B <= 32 ? 2 : 3);
   const int cols3 = shape3 == 0 ? 256 : shape3 == 1 ? 64 : shape3 == 2 ? 64 : (shape3 == 3 ? 128 : 256);
@@ -795,7 +796,8 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   sa = std::min(std::min(std::min(sa, fit), 8), (g.ngrid + 15) / 16);
   e = mark(p->ev_begin, st);
   if (e == hipSuccess)
-    e = launch_gemm_t(h.ht_g, h.hterms_g, shape3, Gq, h.nsq, (int64_t)g.M * h.nsq, g.nsub, h.nsq, g.ngrid,
+    e = launch_gemm_t(h.ht_g, h.hterms_g, shape3, Gq, (int64_t)(h.ngq / 16) * h.nks * 256, (int64_t)h.nks * 256, 16,
+                      256, g.nsub, h.nsq, g.ngrid,
                       (g.ngrid + 15) / 16 * 16, W, bp, (int64_t)g.M * bp, g.ngrid, sg16 ? tau_up : nullptr,
                       sg16 ? tau_down : nullptr, nullptr, 0, 0, part, (int64_t)g.M * h.nsq * prow,
                       (int64_t)h.nsq * prow, prow, B, bp, g.M, sa, st);

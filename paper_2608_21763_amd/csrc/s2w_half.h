@@ -90,4 +90,11 @@ __device__ __forceinline__ void pow2_scale(float mx, float& up, float& down) {
   down = ldexpf(1.f, ex - 15);
 }
 
+// Row-block-major elastic store Gq[l][g/16][ks][g%16][16 words]: chunk 0 of grid row g (bin l)
+// at K step 0, as uint4; K step ks of the same row is ks * kGqStepU4 further on.
+constexpr int kGqStepU4 = 64;
+__device__ __forceinline__ const uint4* gq_row(const uint4* Gq, int g, int l, int ng16, int nks) {
+  return Gq + (((int64_t)l * ng16 + (g >> 4)) * nks * 16 + (g & 15)) * 4;
+}
+
 }  // namespace s2w

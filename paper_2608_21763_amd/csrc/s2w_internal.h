@@ -61,8 +61,10 @@ hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part
                                 const Geometry& g, hipStream_t st);
 
 // ---- batched path (matrix cores, half-precision stores); ht: 1 = bf16, 2 = f16 ----
+// ng16 > 0 selects the row-block-major layout of the elastic store (ng16 = blocks of 16 grid
+// rows; sg, sl, sc unused): word (((l*ng16 + g/16)*(ncp/16) + c/16)*16 + g%16)*16 + c%16.
 hipError_t launch_quant_rows(int ht, const float2* staging, int64_t nrows, int M, int nc, int ncp, uint32_t* out,
-                             int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, hipStream_t st);
+                             int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, int ng16, hipStream_t st);
 hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
                            int nsq, int B, int bp, int nks, int ncb, uint4* Bop, hipStream_t st);
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
@@ -99,7 +101,8 @@ hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int 
                             hipStream_t st);
 // Conjugate-transposed half-precision GEMM per slot (adjoint products); see the kernel.
 // shape 0: tall operator (many rows, short K); shape 1: few rows, long K.
-hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k, int nrows,
+hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k16, int64_t a_k,
+                         int64_t a_r16, int nrows,
                          int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
                          int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
                          int64_t rs_l, float* out, int64_t o_split, int64_t o_slot, int64_t o_row, int B, int bp,

@@ -11,8 +11,9 @@ namespace s2w {
 // ---------------------------------------------------------------------------------------------
 // Conjugate-transposed half-precision GEMM per slot (the adjoint's per-bin products):
 //   out(row, b) = rowscale(row, l) * down(l, b) * sum_k conj(A(k, row)) * up(l, b) * X(k, b)
-// A is a half-precision store read transposed: A(k, row) at Aq + l*a_slot + k*a_k + row (32-bit
-// words re | im << 16, rows contiguous); rows < rows_alloc are readable, k < kvalid are real.
+// A is a half-precision store read transposed: A(k, row) at Aq + l*a_slot + (k/16)*a_k16 +
+// (k%16)*a_k + (row/16)*a_r16 + row%16 (32-bit words re | im << 16; rows contiguous within
+// blocks of 16); rows < rows_alloc are readable, k < kvalid are real.
 // X is a complex64 activation X(k, b) at X + l*x_slot + k*x_k + b, split into H half terms in
 // registers after the optional power-of-two scale up(l, b).  The operator tile of a K step (16
 // k x RT rows) is staged through LDS (double-buffered) and read back as fragments of four
@@ -21,7 +22,7 @@ namespace s2w {
 // per split, out + split*o_split).
 struct TArgs {
   const uint32_t* Aq;
-  int64_t a_slot, a_k;
+  int64_t a_slot, a_k16, a_k, a_r16;
   int nrows, rows_alloc, kvalid, nks;  // nks: K steps of 16 over the padded K range
   const float2* X;
   int64_t x_slot, x_k;
@@ -35,6 +36,11 @@ struct TArgs {
   int B, bp, nrt, nct, splits;
 };
 
+// word offset of A(k, row) within a slot (row a multiple of 4: four rows are contiguous)
+__device__ __forceinline__ int64_t a_off(const TArgs& p, int k, int row) {
+  return (int64_t)(k >> 4) * p.a_k16 + (int64_t)(k & 15) * p.a_k + (int64_t)(row >> 4) * p.a_r16 + (row & 15);
+}
+
 template <int RT, int PER_T>
 __device__ __forceinline__ void gt_load(const TArgs& p, const uint32_t* Al, int ks, int row0, int tid, uint4* st) {
   constexpr int A_U4 = 16 * RT / 4;
@@ -45,7 +51,7 @@ __device__ __forceinline__ void gt_load(const TArgs& p, const uint32_t* Al, int 
       const int kk = i / (RT / 4), rg = i % (RT / 4);
       const int k = 16 * ks + kk;
       const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
-      uint4 v = *reinterpret_cast<const uint4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
+      uint4 v = *reinterpret_cast<const uint4*>(Al + a_off(p, min(k, p.kvalid - 1), row));
       if (k >= p.kvalid) v = make_uint4(0u, 0u, 0u, 0u);
       st[it] = v;
     }
@@ -256,7 +262,7 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
       const int kk = i >> 6, rg = i & 63;
       const int k = 16 * ks + kk;
       const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
-      uint4 v = *reinterpret_cast<const uint4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
+      uint4 v = *reinterpret_cast<const uint4*>(Al + a_off(p, min(k, p.kvalid - 1), row));
       ast[it] = k < p.kvalid ? v : make_uint4(0u, 0u, 0u, 0u);
     }
 #pragma unroll
@@ -336,7 +342,8 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
 // shape 0: 64 rows x 256 columns per workgroup (many rows, short K);
 // shape 1: 256 rows x 64 columns (few rows, long K);
 // shapes 2, 3, 4: eight waves, 256 rows x 64, 128 or 256 columns, both operands staged in LDS
-hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k, int nrows,
+hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k16, int64_t a_k,
+                         int64_t a_r16, int nrows,
                          int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
                          int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
                          int64_t rs_l, float* out, int64_t o_split, int64_t o_slot, int64_t o_row, int B, int bp,
@@ -350,7 +357,9 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
   TArgs a;
   a.Aq = Aq;
   a.a_slot = a_slot;
+  a.a_k16 = a_k16;
   a.a_k = a_k;
+  a.a_r16 = a_r16;
   a.nrows = nrows;
   a.rows_alloc = rows_alloc;
   a.kvalid = kvalid;

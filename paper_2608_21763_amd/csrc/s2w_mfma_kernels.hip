@@ -2,7 +2,10 @@
 //
 // Half-precision stores (HT = 1: bfloat16, HT = 2: float16), one 32-bit word per complex
 // value (low half = real part, high half = imaginary part):
-//   Gq[g][l][j]   elastic spectra, j padded to nsq (a multiple of 16, zeros)
+//   Gq            elastic spectra G[g][l][j], j padded to nsq (a multiple of 16, zeros), stored
+//                 row-block-major: Gq[l][g/16][j/16][g%16][j%16], so that the 16 x 16 block of
+//                 one K step of 16 grid rows is 1 KB of contiguous memory (grid rows padded to
+//                 a multiple of 16)
 //   Fq[l][o][g]   acoustic spectra, o padded to noq (multiple of 16), g padded to ngq (multiple of 16)
 //   sG[g][l], sF[g][l]  float32 power-of-two scales: true value = scale * stored value
 //
@@ -33,7 +36,7 @@ namespace s2w {
 template <int HT>
 __global__ __launch_bounds__(256) void k_quant_rows(const float2* __restrict__ staging, int M, int nc, int ncp,
                                                     uint32_t* __restrict__ out, int64_t row0, int64_t sg, int64_t sl,
-                                                    int64_t sc, float* __restrict__ scale) {
+                                                    int64_t sc, float* __restrict__ scale, int ng16) {
   __shared__ float red[256];
   const int r = blockIdx.x / M, l = blockIdx.x % M;
   const float2* row = staging + ((int64_t)r * M + l) * ncp;
@@ -52,6 +55,15 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float2* __restrict__ s
   pow2_scale(red[0], up, down);
   const int64_t g = row0 + r;
   if (threadIdx.x == 0) scale[g * M + l] = down;
+  if (ng16 > 0) {
+    // row-block-major store: word (((l * ng16 + g / 16) * (ncp / 16) + c / 16) * 16 + g % 16) * 16 + c % 16
+    uint32_t* o = out + (((int64_t)l * ng16 + (g >> 4)) * (ncp >> 4) * 16 + (g & 15)) * 16;
+    for (int c = threadIdx.x; c < ncp; c += 256) {
+      const float2 v = c < nc ? row[c] : make_float2(0.f, 0.f);
+      o[(int64_t)(c >> 4) * 256 + (c & 15)] = pack_half2<HT>(v.x * up, v.y * up);
+    }
+    return;
+  }
   uint32_t* o = out + g * sg + (int64_t)l * sl;
   for (int c = threadIdx.x; c < ncp; c += 256) {
     const float2 v = c < nc ? row[c] : make_float2(0.f, 0.f);
@@ -60,13 +72,16 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float2* __restrict__ s
 }
 
 hipError_t launch_quant_rows(int ht, const float2* staging, int64_t nrows, int M, int nc, int ncp, uint32_t* out,
-                             int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, hipStream_t st) {
+                             int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, int ng16, hipStream_t st) {
   if (nrows == 0) return hipSuccess;
+  if (ng16 > 0 && (ncp % 16)) return hipErrorInvalidValue;
   dim3 grid((unsigned)(nrows * M));
   if (ht == 1)
-    hipLaunchKernelGGL(k_quant_rows<1>, grid, dim3(256), 0, st, staging, M, nc, ncp, out, row0, sg, sl, sc, scale);
+    hipLaunchKernelGGL(k_quant_rows<1>, grid, dim3(256), 0, st, staging, M, nc, ncp, out, row0, sg, sl, sc, scale,
+                       ng16);
   else
-    hipLaunchKernelGGL(k_quant_rows<2>, grid, dim3(256), 0, st, staging, M, nc, ncp, out, row0, sg, sl, sc, scale);
+    hipLaunchKernelGGL(k_quant_rows<2>, grid, dim3(256), 0, st, staging, M, nc, ncp, out, row0, sg, sl, sc, scale,
+                       ng16);
   return hipGetLastError();
 }
 
@@ -182,7 +197,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
   const int slots_x = (M - x + nx - 1) / nx;
   const int64_t per_slot = (int64_t)nrb * nct;
   const int64_t items = (int64_t)slots_x * per_slot;
-  const int64_t row_u4 = (int64_t)nks * 4;  // uint4 per (g, l) row of Gq
+  const int ng16 = (ngrid + 15) >> 4;
   for (int64_t it = wi; it < items; it += nwx) {
     const int l = x + nx * (int)(it / per_slot);
     const int64_t rem = it % per_slot;
@@ -198,7 +213,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
 #pragma unroll
     for (int a = 0; a < MF; ++a) {
       const int g = min(g0 + 16 * a + (lane & 15), ngrid - 1);
-      arow[a] = Gq + ((int64_t)g * M + l) * row_u4 + (lane >> 4);
+      arow[a] = gq_row(Gq, g, l, ng16, nks) + (lane >> 4);
     }
     const uint4* bb = Bop + (int64_t)l * nks * ncb * H * 64 + lane;
     const bool colok = cb0 < ncb;
@@ -206,7 +221,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
     for (int ks = 0; ks < nks; ++ks) {
       uint4 av[MF], bv[NF][H];
 #pragma unroll
-      for (int a = 0; a < MF; ++a) av[a] = ntload(arow[a] + 4 * ks);
+      for (int a = 0; a < MF; ++a) av[a] = ntload(arow[a] + kGqStepU4 * ks);
 #pragma unroll
       for (int b = 0; b < NF; ++b)
 #pragma unroll
@@ -329,7 +344,7 @@ __global__ __launch_bounds__(256 * WR, WR == 1 ? 2 : 1) void k_gemm_g3(const uin
   const int slots_x = (M - x + nx - 1) / nx;
   const int64_t per_slot = (int64_t)nrb * nct;
   const int64_t items = (int64_t)slots_x * per_slot;
-  const int64_t row_u4 = (int64_t)nks * 4;
+  const int ng16 = (ngrid + 15) >> 4;
   for (int64_t it = wi; it < items; it += nwx) {
     const int l = x + nx * (int)(it / per_slot);
     const bool dc = (l == 0);
@@ -348,8 +363,8 @@ __global__ __launch_bounds__(256 * WR, WR == 1 ? 2 : 1) void k_gemm_g3(const uin
       if (i < A_U4) {
         const int r = i >> 2, cc = i & 3;
         const int g = min(g0 + r, ngrid - 1);
-        src[k] = Gq + ((int64_t)g * M + l) * row_u4 + cc;
-        sstep[k] = 4;
+        src[k] = gq_row(Gq, g, l, ng16, nks) + cc;
+        sstep[k] = kGqStepU4;
         dst[k] = swz(r, cc);
       } else {
         const int j = min(i - A_U4, B_U4 - 1);
@@ -455,7 +470,7 @@ __global__ __launch_bounds__(512, 1) void k_gemm_g2(const uint4* __restrict__ Gq
   const int slots_x = (M - x + nx - 1) / nx;
   const int64_t per_slot = (int64_t)nrb * nct;
   const int64_t items = (int64_t)slots_x * per_slot;
-  const int64_t row_u4 = (int64_t)nks * 4;
+  const int ng16 = (ngrid + 15) >> 4;
   for (int64_t it = wi; it < items; it += nwx) {
     const int l = x + nx * (int)(it / per_slot);
     const int64_t rem = it % per_slot;
@@ -475,8 +490,8 @@ __global__ __launch_bounds__(512, 1) void k_gemm_g2(const uint4* __restrict__ Gq
       if (i < A_U4) {
         const int r = i >> 2, c = i & 3;
         const int g = min(g0 + r, ngrid - 1);
-        src[k] = Gq + ((int64_t)g * M + l) * row_u4 + c;
-        sstep[k] = 4;
+        src[k] = gq_row(Gq, g, l, ng16, nks) + c;
+        sstep[k] = kGqStepU4;
         dst[k] = swz(r, c);
       } else {
         const int j = min(i - A_U4, B_U4 - 1);
@@ -626,7 +641,7 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
   const int slots_x = (M - x + nx - 1) / nx;
   const int64_t per_slot = (int64_t)nrb * nct;
   const int64_t items = (int64_t)slots_x * per_slot;
-  const int64_t row_u4 = (int64_t)nks * 4;
+  const int ng16 = (ngrid + 15) >> 4;
   // operator lanes: block row rr = lane/4, chunk c such that the linear LDS slot is swz(rr, c)
   const int a_rr = lane >> 2, a_c = (lane & 3) ^ ((a_rr >> 1) & 3);
   for (int64_t it = wi; it < items; it += nwx) {
@@ -643,8 +658,8 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
       const int blk = wave + NWAVE * q;
       if (blk < A_BLK) {
         const int g = min(g0 + 16 * blk + a_rr, ngrid - 1);
-        src[q] = Gq + ((int64_t)g * M + l) * row_u4 + a_c;
-        sstep[q] = 4;
+        src[q] = gq_row(Gq, g, l, ng16, nks) + a_c;
+        sstep[q] = kGqStepU4;
       } else {
         const int j = blk - A_BLK;
         const int cb = min(cbt0 + j / H, ncb - 1), h = j % H;
