@@ -576,6 +576,11 @@ static s2w_status check_call(s2w_plan* p, const void* in, int32_t B, const void*
   return S2W_OK;
 }
 
+// Floats of the half path's partial region (acoustic partials; scratch of the column scales).
+static int64_t part_floats(const s2w_plan* p) {
+  return (int64_t)std::max(p->hg.splits_max * p->hg.noq, p->hg.nsq) * p->geo.M * 2 * p->hg.bp;
+}
+
 // Batched forward on the matrix cores (half-precision stores).
 static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st) {
   const Geometry& g = p->geo;
@@ -631,7 +636,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   e = launch_mid_batch(U, sF, B, bp, false, packed, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
-    e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
+    e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
   }
   if (fstaged)
@@ -783,7 +788,7 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
                     (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
   e = launch_mid_batch(W, sG, B, bp, true, false, g, st);
-  if (e == hipSuccess && sg16) e = launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, st);
+  if (e == hipSuccess && sg16) e = launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(G[g][l][j]) W'[g][l][b] (row-block-major store)
   const int64_t prow = 2 * (int64_t)bp;

@@ -90,7 +90,7 @@ hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngri
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
                             const Geometry& g, hipStream_t st);
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
-                            hipStream_t st);
+                            float* part, int64_t part_floats, hipStream_t st);
 hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,
                          float* part, int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits,
                          hipStream_t st);

@@ -1152,20 +1152,43 @@ hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int 
 }
 
 // Column scales of the acoustic GEMM's activation (float16 operands only): for each (l, b),
-// a power of two mapping max_g |V[g][l][b]| into [2^14, 2^15).
-__global__ __launch_bounds__(256) void k_col_scale(const float2* __restrict__ V, int ngrid, int M, int B, int bp,
-                                                   float* __restrict__ tau_up, float* __restrict__ tau_down) {
+// a power of two mapping max_g |V[g][l][b]| (re, im) into [2^14, 2^15).  First pass: partial
+// maxima part[s][l][b] over grid-row ranges s (many workgroups, four loads in flight per
+// thread); second pass: the maximum over the ranges and the scale.
+__global__ __launch_bounds__(256) void k_col_max(const float2* __restrict__ V, int ngrid, int M, int B, int bp,
+                                                 int splits, float* __restrict__ part) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int s = blockIdx.y;
   if (i >= (int64_t)M * bp) return;
   const int l = (int)(i / bp), b = (int)(i - (int64_t)l * bp);
-  float mx = 0.f;
+  const int g0 = (int)((int64_t)ngrid * s / splits), g1 = (int)((int64_t)ngrid * (s + 1) / splits);
+  float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
   if (b < B) {
     const float2* v = V + (int64_t)l * bp + b;
-    for (int g = 0; g < ngrid; ++g) {
-      const float2 x = v[(int64_t)g * M * bp];
-      mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)));
+    const int64_t gs = (int64_t)M * bp;
+    int g = g0;
+    for (; g + 4 <= g1; g += 4) {
+      const float2 x0 = v[(int64_t)g * gs], x1 = v[(int64_t)(g + 1) * gs];
+      const float2 x2 = v[(int64_t)(g + 2) * gs], x3 = v[(int64_t)(g + 3) * gs];
+      m0 = fmaxf(m0, fmaxf(fabsf(x0.x), fabsf(x0.y)));
+      m1 = fmaxf(m1, fmaxf(fabsf(x1.x), fabsf(x1.y)));
+      m2 = fmaxf(m2, fmaxf(fabsf(x2.x), fabsf(x2.y)));
+      m3 = fmaxf(m3, fmaxf(fabsf(x3.x), fabsf(x3.y)));
+    }
+    for (; g < g1; ++g) {
+      const float2 x = v[(int64_t)g * gs];
+      m0 = fmaxf(m0, fmaxf(fabsf(x.x), fabsf(x.y)));
     }
   }
+  part[(int64_t)s * M * bp + i] = fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
+}
+
+__global__ __launch_bounds__(256) void k_col_scale_final(const float* __restrict__ part, int splits, int64_t n,
+                                                         float* __restrict__ tau_up, float* __restrict__ tau_down) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float mx = 0.f;
+  for (int s = 0; s < splits; ++s) mx = fmaxf(mx, part[(int64_t)s * n + i]);
   float up, down;
   pow2_scale(mx, up, down);
   tau_up[i] = up;
@@ -1173,10 +1196,16 @@ __global__ __launch_bounds__(256) void k_col_scale(const float2* __restrict__ V,
 }
 
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
-                            hipStream_t st) {
+                            float* part, int64_t part_floats, hipStream_t st) {
   const int64_t n = (int64_t)M * bp;
-  hipLaunchKernelGGL(k_col_scale, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, V, ngrid, M, B, bp, tau_up,
-                     tau_down);
+  const int64_t nblk = (n + 255) / 256;
+  int splits = (int)std::max<int64_t>(1, std::min<int64_t>(64, 8192 / std::max<int64_t>(1, nblk)));
+  splits = std::min(splits, std::max(1, ngrid));
+  while (splits > 1 && (int64_t)splits * n > part_floats) --splits;
+  if ((int64_t)splits * n > part_floats) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_col_max, dim3((unsigned)nblk, (unsigned)splits), dim3(256), 0, st, V, ngrid, M, B, bp, splits,
+                     part);
+  hipLaunchKernelGGL(k_col_scale_final, dim3((unsigned)nblk), dim3(256), 0, st, part, splits, n, tau_up, tau_down);
   return hipGetLastError();
 }
 
