@@ -472,11 +472,13 @@ hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part
 // sF[g][l] and write the result back in place: as complex64 (PACK = 0), or as bfloat16
 // high/low terms of the real and imaginary parts packed in two 32-bit words (PACK = 1), the
 // acoustic GEMM's operand format.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float v) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
+typedef float s2w_f2v_t __attribute__((ext_vector_type(2)));
+typedef __bf16 s2w_b2v_t __attribute__((ext_vector_type(2)));
+
+// (a, b) rounded to nearest even bfloat16 in one word, a in the low half (hardware conversion)
+__device__ __forceinline__ uint32_t bf16x2_rne(float a, float b) {
+  const s2w_f2v_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, s2w_b2v_t));
 }
 
 template <int PACK>
@@ -484,10 +486,9 @@ __device__ __forceinline__ void store_v(float2* dst, float2 v, float f) {
   v.x *= f;
   v.y *= f;
   if (PACK) {
-    const uint32_t hr = bf16_rne_bits(v.x), hi = bf16_rne_bits(v.y);
-    const uint32_t lr = bf16_rne_bits(v.x - __uint_as_float(hr << 16));
-    const uint32_t li = bf16_rne_bits(v.y - __uint_as_float(hi << 16));
-    *reinterpret_cast<uint2*>(dst) = make_uint2(hr | (hi << 16), lr | (li << 16));
+    const uint32_t h = bf16x2_rne(v.x, v.y);
+    const uint32_t lo = bf16x2_rne(v.x - __uint_as_float(h << 16), v.y - __uint_as_float(h & 0xffff0000u));
+    *reinterpret_cast<uint2*>(dst) = make_uint2(h, lo);
   } else {
     *dst = v;
   }
