@@ -79,9 +79,15 @@ def traffic_for(kernel: str):
     return d.get("bytes_per_launch")
 
 
-def elastic_kernel(B: int) -> str:
-    """Kernel of the batched elastic GEMM the library picks by default for a batch of B."""
-    return "k_gemm_g4"
+def elastic_kernel(cfg: int) -> str:
+    """Kernel of the batched half-precision elastic GEMM for tile setting `cfg` (-1 automatic)."""
+    if cfg in (-1, 10, 11, 12, 13, 14, 15, 16):
+        return "k_gemm_g4"
+    if cfg in (7, 8, 9):
+        return "k_gemm_g3"
+    if cfg in (5, 6):
+        return "k_gemm_g2"
+    return "k_gemm_g"
 
 
 def time_path(op, s_dev, steps: int, warmup: int, B: int):
@@ -128,6 +134,8 @@ def main():
     ap.add_argument("--batch-adj", type=int, default=64, help="residuals per call on the batched float32 adjoint")
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default tiles on the batched paths instead of the autotuner's choice")
     ap.add_argument("--ngrid", type=int, default=None, help="override the share size (testing only)")
     ap.add_argument("--cpu-ruptures", type=int, default=3, help="ruptures the oracle baseline runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -208,6 +216,17 @@ def main():
         bcfg = bcfg.replace(ngrid=args.ngrid)
     bref = {}
 
+    def tune(op, B, s=None, adjoint=False):
+        """Tile shapes of a batched path: the autotuner's choice (timed here), or the defaults."""
+        if args.no_autotune:
+            return None
+        from paper_2608_21763_amd import autotune
+        t = time.perf_counter()
+        res = autotune(op, B, reps=2, adjoint=adjoint, s=s)
+        log(f"autotune B={B}: {res['best']} ({res['ms']:.2f} ms, {len(res['results'])} shapes, "
+            f"{time.perf_counter() - t:.1f} s)")
+        return res["best"]
+
     def batch_oracle(s_host, picks):
         """FP64 oracle waveforms of ruptures `picks` of the ensemble (each with its own active columns)."""
         import oracle
@@ -228,11 +247,12 @@ def main():
         nb = 2
         s_host = synth.gen_slip_batch(bcfg, 0, nb * B)
         s_dev = torch.tensor(s_host, device=dev).reshape(nb, B, bcfg.nsub, bcfg.nt)
+        tuning = tune(op, B, s=s_dev[0])
         total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, B)
         ms_step = total_ms / args.steps
         kmean = float(np.mean(kern_ms))
         flops_g = 8.0 * bcfg.ngrid * bcfg.nsub * bcfg.nt * B
-        fp32b = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "kernel": "k_cgemm32",
+        fp32b = {"tuning": tuning, "ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "kernel": "k_cgemm32",
                  "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)), "algorithmic_flops": flops_g,
                  "achieved_TFLOPs": flops_g / (kmean * 1e9),
                  "mfma_frac": flops_g / (kmean * 1e9) / MFMA_PEAK["f32"], "setup_s": setup_s}
@@ -262,6 +282,7 @@ def main():
         nb = 2
         s_host = synth.gen_slip_batch(bcfg, 0, nb * B)
         s_dev = torch.tensor(s_host, device=dev).reshape(nb, B, bcfg.nsub, bcfg.nt)
+        tuning = tune(op, B, s=s_dev[0])
         total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, B)
         ms_step = total_ms / args.steps
         kmean = float(np.mean(kern_ms))
@@ -269,7 +290,8 @@ def main():
         terms = 1 if gdt == "f16" else 2                              # activation terms the matrix cores multiply
         hbytes = algorithmic_bytes(bcfg.nsub, bcfg.nobs, bcfg.ngrid, bcfg.nt, 2)
         res = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{fdt}",
-               "kernel": elastic_kernel(B), "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)),
+               "tuning": tuning, "kernel": elastic_kernel(op.get_tuning()["gemm_cfg"]), "kernel_ms": kmean,
+               "kernel_ms_min": float(np.min(kern_ms)),
                "algorithmic_flops": flops_g, "achieved_TFLOPs": flops_g / (kmean * 1e9),
                "activation_terms": terms, "issued_TFLOPs": terms * flops_g / (kmean * 1e9), "algorithmic_bytes": hbytes,
                "setup_s": setup_s}
@@ -304,6 +326,7 @@ def main():
         t = time.perf_counter()
         op.load_operators(*host_generators(acfg), chunk_rows=1024)
         setup_s = time.perf_counter() - t
+        tuning = tune(op, B, adjoint=True)
         r = torch.randn((B, acfg.nobs, acfg.nt), device=dev)
         gs = torch.empty((B, acfg.nsub, acfg.nt), device=dev)
         stream = torch.cuda.current_stream().cuda_stream
@@ -323,7 +346,7 @@ def main():
         kmean = float(np.mean([a.elapsed_ms(e) for a, e in evs]))
         flops = 8.0 * acfg.ngrid * acfg.nsub * acfg.nt * B
         res = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{gdt}",
-               "kernel": kernel, "kernel_ms": kmean, "achieved_TFLOPs": flops / (kmean * 1e9),
+               "tuning": tuning, "kernel": kernel, "kernel_ms": kmean, "achieved_TFLOPs": flops / (kmean * 1e9),
                "mfma_frac": flops / (kmean * 1e9) / peak, "setup_s": setup_s}
         log(f"{label} adjoint B={B}: {ms_step:.3f} ms/call, {res['ruptures_per_s']:.0f} gradients/s, "
             f"transposed elastic GEMM {kmean:.3f} ms = {res['achieved_TFLOPs']:.1f} TFLOP/s")
