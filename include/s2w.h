@@ -158,6 +158,7 @@ typedef struct s2w_tuning {
                                 rows x columns 64 x 256, 256 x 64 (four waves), 256 x 64, 256 x 128,
                                 256 x 256 (eight waves, both operands through LDS) */
   int32_t hadj_tile_g;       /* half-precision adjoint, transposed elastic GEMM tile: same values */
+  int32_t mid_rupts;         /* batched mid-chain (Nt = 256): ruptures per work unit, 16 or 32 */
 } s2w_tuning;
 
 s2w_status s2w_set_tuning(s2w_plan* plan, const s2w_tuning* t);

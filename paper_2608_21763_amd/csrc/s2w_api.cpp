@@ -322,6 +322,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.adj32_splits = 0;
   p->tune.hadj_tile_f = -1;
   p->tune.hadj_tile_g = -1;
+  p->tune.mid_rupts = 16;
   p->row_set.assign((size_t)d.ngrid, 0);
   p->rows_missing = d.ngrid;
   {
@@ -442,6 +443,10 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
   if (t->hadj_tile_f) {
     if (t->hadj_tile_f < -1 || t->hadj_tile_f > 5) return fail(p, S2W_EINVAL, "tuning: hadj_tile_f");
     n.hadj_tile_f = t->hadj_tile_f < 0 ? -1 : t->hadj_tile_f - 1;
+  }
+  if (t->mid_rupts) {
+    if (t->mid_rupts != 16 && t->mid_rupts != 32) return fail(p, S2W_EINVAL, "tuning: mid_rupts must be 16 or 32");
+    n.mid_rupts = t->mid_rupts;
   }
   if (t->hadj_tile_g) {
     if (t->hadj_tile_g < -1 || t->hadj_tile_g > 5) return fail(p, S2W_EINVAL, "tuning: hadj_tile_g");
@@ -633,7 +638,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
   const bool fscale = h.ht_f == 2;
-  e = launch_mid_batch(U, sF, B, bp, false, packed, g, st);
+  e = launch_mid_batch(U, sF, B, bp, false, packed, g, st, p->tune.mid_rupts);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
     e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
@@ -696,7 +701,7 @@ static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, 
                        st);
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
-  e = launch_mid_batch(U, nullptr, B, bp, false, false, g, st);
+  e = launch_mid_batch(U, nullptr, B, bp, false, false, g, st, p->tune.mid_rupts);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   // part[split][l][o][n] = sum_{g in split} Fs[l][o][g] V[g][l][b]
   const int cf = b32_cfg(p, B, true);
@@ -734,7 +739,7 @@ static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs,
                      (int64_t)f.nok * bp, f.nok, B, bp, (float*)W, 2 * (int64_t)g.M * bp, 2 * (int64_t)bp, 0, g.M, 1,
                      st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
-  e = launch_mid_batch(W, nullptr, B, bp, true, false, g, st);
+  e = launch_mid_batch(W, nullptr, B, bp, true, false, g, st, p->tune.mid_rupts);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(Gs[g][l][j]) W'[g][l][b]
   const int c3 = b32_cfg(p, B, true);
@@ -787,7 +792,7 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
                     (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
-  e = launch_mid_batch(W, sG, B, bp, true, false, g, st);
+  e = launch_mid_batch(W, sG, B, bp, true, false, g, st, p->tune.mid_rupts);
   if (e == hipSuccess && sg16) e = launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(G[g][l][j]) W'[g][l][b] (row-block-major store)

@@ -540,16 +540,16 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
 // M = 256: 16 ruptures of one grid row per unit, the next unit's rows prefetched into
 // registers while the current one is transformed; rows kept with a padded stride (257) so
 // that the strided LDS writes and reads of the gather and scatter are conflict-free.
-template <int PACK>
-__global__ __launch_bounds__(256) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
-                                                      int B, int bp, int nt, int mode, float mscale) {
-  constexpr int M = 256, R = 16, LD = 257;
+template <int PACK, int R>
+__global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF,
+                                                         int ngrid, int B, int bp, int nt, int mode, float mscale) {
+  constexpr int M = 256, LD = 257;
   __shared__ float2 X[R * LD];
   __shared__ float2 T[R * 16 * 17];
   __shared__ float2 twb[2 * M];
   const Twiddles tw = lds_twiddles(twb, M);
   const int tid = threadIdx.x;
-  const int r = tid & 15, lq = tid >> 4;  // gather/scatter: rupture r, slots lq + 16 k
+  const int r = tid % R, lq = tid / R;  // gather/scatter: rupture r, slots lq + 16 k
   const int nbb = (B + R - 1) / R;
   const int64_t units = (int64_t)ngrid * nbb;
   float2 pre[16];
@@ -591,21 +591,27 @@ __global__ __launch_bounds__(256) void k_mid_batch256(float2* __restrict__ U, co
 }
 
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
-                            const Geometry& g, hipStream_t st) {
+                            const Geometry& g, hipStream_t st, int rupts) {
   constexpr int R = 16;
   const int mode = g.diff ? (adjoint ? MID_BACKWARD_T : MID_BACKWARD) : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
   const int64_t units = (int64_t)g.ngrid * ((B + R - 1) / R);
   const int64_t nblk = std::min<int64_t>(units, 256 * 8);
   if (g.M == 256) {
-    const int64_t units256 = (int64_t)g.ngrid * ((B + 15) / 16);
+    // units of 16 or 32 ruptures of one grid row (32: 256-byte runs per slot, one 512-thread
+    // workgroup per CU)
+    const int ru = rupts == 32 ? 32 : 16;
+    const int64_t units256 = (int64_t)g.ngrid * ((B + ru - 1) / ru);
     const int64_t nb256 = std::min<int64_t>(units256, 256 * 8);
-    if (pack_bf16)
-      hipLaunchKernelGGL((k_mid_batch256<1>), dim3((unsigned)nb256), dim3(256), 0, st, U, sF, g.ngrid, B, bp, g.nt, mode,
-                         mscale);
-    else
-      hipLaunchKernelGGL((k_mid_batch256<0>), dim3((unsigned)nb256), dim3(256), 0, st, U, sF, g.ngrid, B, bp, g.nt, mode,
-                         mscale);
+#define S2W_MID256(P_, R_)                                                                                       \
+  hipLaunchKernelGGL((k_mid_batch256<P_, R_>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF, g.ngrid, B, bp, \
+                     g.nt, mode, mscale)
+    if (ru == 32) {
+      if (pack_bf16) S2W_MID256(1, 32); else S2W_MID256(0, 32);
+    } else {
+      if (pack_bf16) S2W_MID256(1, 16); else S2W_MID256(0, 16);
+    }
+#undef S2W_MID256
     return hipGetLastError();
   }
   const size_t lds = (2 * (size_t)g.M * (R + 1) + 2 * (size_t)g.M) * sizeof(float2);

@@ -87,8 +87,9 @@ inline int gemm_f2_col_tiles(int B) {
 }
 hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngrid, int ngq, int M, int noq, int B,
                           int bp, int splits, hipStream_t st);
+// rupts: ruptures per unit of the M = 256 kernel (16 or 32; other values mean 16)
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
-                            const Geometry& g, hipStream_t st);
+                            const Geometry& g, hipStream_t st, int rupts = 16);
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
                             float* part, int64_t part_floats, hipStream_t st);
 hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,

@@ -148,6 +148,28 @@ def test_half_adjoint_tile_shapes_agree(B):
     assert errs.max() <= BOUND[("bf16", "bf16")]
 
 
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_mid_chain_unit_sizes_agree(dtype):
+    # Nt = 256 takes the 256-slot mid-chain kernel; units of 16 and 32 ruptures give the same
+    # bits, forward and adjoint, and agree with the oracle
+    cfg = synth.SynthConfig(nsub=20, ngrid=90, nobs=6, nt=256, seed=105, slip_seed=106, op_kind="dense",
+                            slip_mode="dense")
+    B = 40
+    log_case("mid_units", dtype=dtype)
+    op = make_operator(cfg, max_batch=B, g_dtype=dtype, f_dtype=dtype)
+    s = synth.gen_slip_batch(cfg, 0, B)
+    r = synth.normals(cfg.seed, "r", 0, (B, cfg.nobs, cfg.nt))
+    out = {}
+    for mr in (16, 32):
+        op.set_tuning(mid_rupts=mr)
+        out[mr] = (op.forward(to_dev(s)).clone(), op.adjoint(to_dev(r)).clone())
+    assert torch.equal(out[16][0], out[32][0]) and torch.equal(out[16][1], out[32][1])
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    bound = BOUND[(dtype, dtype)]
+    assert oracle.rel_l2_per_rupture(out[16][0].cpu().numpy(), oracle.forward(G, F, s)).max() <= bound
+    assert oracle.rel_l2_per_rupture(out[16][1].cpu().numpy(), oracle.adjoint(G, F, r)).max() <= bound
+
+
 @pytest.mark.parametrize("B", [40, 130])
 def test_elastic_gemm_tile_shapes_agree(B):
     # every tile shape accumulates each output over the same K steps in the same order, so all
