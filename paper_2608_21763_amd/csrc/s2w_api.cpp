@@ -419,7 +419,10 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     if (t->gemm_cfg < -1 || t->gemm_cfg > 16) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
-  if (t->fgemm_lds) n.fgemm_lds = t->fgemm_lds > 0 ? 1 : 0;
+  if (t->fgemm_lds) {
+    if (t->fgemm_lds > 2) return fail(p, S2W_EINVAL, "tuning: fgemm_lds");
+    n.fgemm_lds = t->fgemm_lds > 0 ? t->fgemm_lds : 0;
+  }
   if (t->gemm32_cfg) {
     if (t->gemm32_cfg < -1 || t->gemm32_cfg > 4) return fail(p, S2W_EINVAL, "tuning: gemm32_cfg");
     n.gemm32_cfg = t->gemm32_cfg < 0 ? -1 : t->gemm32_cfg - 1;
@@ -608,11 +611,16 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
   if (cfg < 0) cfg = B <= 64 ? 12 : 10;
-  // acoustic GEMM: the LDS-staged kernel serves the packed bfloat16 activation when its tile fits
-  const bool packed = h.ht_f == 1 && h.hterms_f == 2;
-  const bool fstaged = packed && p->tune.fgemm_lds != 0 && gemm_f2_supported(h.noq, B);
-  const int zt = fstaged ? gemm_f2_col_tiles(B)
-                         : ((ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8);  // column tiles
+  // acoustic GEMM: fgemm_lds 1 takes the LDS-staged kernel for packed bfloat16 activations
+  // (when its tile fits) and the eight-wave kernel for float16; 2 takes the eight-wave kernel
+  // for both (the mid-chain then leaves complex64); 0 the register kernel
+  const bool bf16_act = h.ht_f == 1 && h.hterms_f == 2;
+  const bool wide = p->tune.fgemm_lds == 2 || (p->tune.fgemm_lds == 1 && !bf16_act);
+  const bool packed = bf16_act && !wide;
+  const bool fstaged = packed && p->tune.fgemm_lds == 1 && gemm_f2_supported(h.noq, B);
+  const int zt = wide ? ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B)
+                      : fstaged ? gemm_f2_col_tiles(B)
+                                : ((ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8);  // column tiles
   int splits = p->tune.fgemm_splits;
   if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
   splits = std::min(splits, h.splits_max);
@@ -644,7 +652,11 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
     e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
   }
-  if (fstaged)
+  if (wide) {
+    splits = std::min(splits, h.ngq / 16);
+    e = launch_gemm_fw(h.ht_f, h.hterms_f, (const uint32_t*)Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq,
+                       g.M, h.noq, g.nobs, B, bp, splits, st);
+  } else if (fstaged)
     e = launch_gemm_f2(Fq, (const uint2*)U, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, splits, st);
   else
     e = launch_gemm_f(h.ht_f, h.hterms_f, packed, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq,

@@ -90,6 +90,25 @@ __device__ __forceinline__ void pow2_scale(float mx, float& up, float& down) {
   down = ldexpf(1.f, ex - 15);
 }
 
+// One B-fragment granule per thread and term: lane L = 16*kg + c16 of column block cb holds the
+// four k = 4*kg + e of column n = 16*cb + c16 (rupture n/2; real part if n even, else imaginary).
+template <int HT, int H>
+__device__ __forceinline__ void t2_convert(const float2* v, float up, bool dc, int cim, uint4* dst) {
+  uint32_t hi[4], lo[4];
+#pragma unroll
+  for (int e2 = 0; e2 < 4; ++e2) {
+    const float x = v[e2].x * up, y = v[e2].y * up;
+    // column re: (x, -y) (DC: (x, 0)); column im: (y, x) (DC: (0, y))
+    const float c0 = cim ? (dc ? 0.f : y) : x;
+    const float c1 = cim ? (dc ? y : x) : (dc ? 0.f : -y);
+    hi[e2] = pack_half2<HT>(c0, c1);
+    if (H == 2)
+      lo[e2] = pack_half2<HT>(c0 - from_half_bits<HT>(hi[e2] & 0xffffu), c1 - from_half_bits<HT>(hi[e2] >> 16));
+  }
+  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+}
+
 // Row-block-major elastic store Gq[l][g/16][ks][g%16][16 words]: chunk 0 of grid row g (bin l)
 // at K step 0, as uint4; K step ks of the same row is ks * kGqStepU4 further on.
 constexpr int kGqStepU4 = 64;

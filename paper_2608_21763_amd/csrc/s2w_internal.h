@@ -85,6 +85,13 @@ inline int gemm_f2_col_tiles(int B) {
   const int nr = B > 64 ? 256 : 64;
   return (B + nr - 1) / nr;
 }
+// Acoustic GEMM with eight waves across the output columns, both operands staged in LDS:
+// part[split][l][o][n] (o < nobs, n < 2B) from complex64 V[g][l][b] (scaled by up[l][b] when
+// given, converted to hterms half terms).  Splits: grid-row ranges (clamped to the K steps).
+int gemm_fw_nf(int hterms, int B);
+inline int gemm_fw_col_tiles(int hterms, int B) { return (B + 64 * gemm_fw_nf(hterms, B) - 1) / (64 * gemm_fw_nf(hterms, B)); }
+hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* V, const float* up, float* part,
+                          int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, hipStream_t st);
 hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngrid, int ngq, int M, int noq, int B,
                           int bp, int splits, hipStream_t st);
 // rupts: ruptures per unit of the M = 256 kernel (16 or 32; other values mean 16)

@@ -195,25 +195,6 @@ struct T2Geo {
   static constexpr int NCB = 2 * NF;                           // 16-column blocks per tile
 };
 
-// One B-fragment granule per thread and term: lane L = 16*kg + c16 of column block cb holds the
-// four k = 4*kg + e of column n = 16*cb + c16 (rupture n/2; real part if n even, else imaginary).
-template <int HT, int H>
-__device__ __forceinline__ void t2_convert(const float2* v, float up, bool dc, int cim, uint4* dst) {
-  uint32_t hi[4], lo[4];
-#pragma unroll
-  for (int e2 = 0; e2 < 4; ++e2) {
-    const float x = v[e2].x * up, y = v[e2].y * up;
-    // column re: (x, -y) (DC: (x, 0)); column im: (y, x) (DC: (0, y))
-    const float c0 = cim ? (dc ? 0.f : y) : x;
-    const float c1 = cim ? (dc ? y : x) : (dc ? 0.f : -y);
-    hi[e2] = pack_half2<HT>(c0, c1);
-    if (H == 2)
-      lo[e2] = pack_half2<HT>(c0 - from_half_bits<HT>(hi[e2] & 0xffffu), c1 - from_half_bits<HT>(hi[e2] >> 16));
-  }
-  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-}
-
 template <int HT, int H, int NF>
 __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
   using Gm = T2Geo<NF>;

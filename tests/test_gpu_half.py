@@ -211,3 +211,23 @@ def test_acoustic_gemm_kernels_agree(B, nobs):
     errs = oracle.rel_l2_per_rupture(y1.cpu().numpy(), oracle.forward(G, F, s.cpu().numpy().astype(np.float64)))
     print("rel-L2 max", errs.max())
     assert errs.max() <= BOUND[("bf16", "bf16")]
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+@pytest.mark.parametrize("B,nobs", [(1, 5), (40, 20), (100, 70), (257, 50)])
+def test_acoustic_kernel_choices(dtype, B, nobs):
+    # the three acoustic GEMMs (LDS-staged, eight-wave, register) against the oracle; the
+    # eight-wave kernel covers one to four column tiles and observers beyond one 64-row tile
+    cfg = synth.SynthConfig(nsub=30, ngrid=333, nobs=nobs, nt=40, seed=107, slip_seed=108, op_kind="dense",
+                            slip_mode="dense")
+    log_case("half_acoustic_choices", dtype=dtype, B=B, nobs=nobs)
+    op = make_operator(cfg, max_batch=B, g_dtype=dtype, f_dtype=dtype)
+    s = synth.gen_slip_batch(cfg, 0, B)
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    ref = oracle.forward(G, F, s)
+    for sel in (1, 2, -1):
+        op.set_tuning(fgemm_lds=sel)
+        y = op.forward(to_dev(s)).cpu().numpy()
+        errs = oracle.rel_l2_per_rupture(y, ref)
+        print(dtype, "fgemm_lds", sel, "rel-L2 max", errs.max())
+        assert np.all(np.isfinite(y)) and errs.max() <= BOUND[(dtype, dtype)]
