@@ -924,6 +924,7 @@ struct s2w_bltt {
   int nrow_k = 0;         // rows padded to 8 (zeros in the transformed adjoint input)
   int bp = 8;             // max_batch padded to 8
   int splits_f = 1, splits_a = 1;
+  int ncu = 256;
   uint64_t op_total = 0, ws_total = 0;
   uint64_t o_fs = 0, o_s = 0, o_part = 0, o_yh = 0;
   char* op = nullptr;
@@ -980,6 +981,9 @@ s2w_status s2w_bltt_create(const s2w_bltt_desc* desc, int32_t device, s2w_bltt**
   if (!p) return S2W_ENOMEM;
   p->desc = d;
   p->device = device;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+    p->ncu = ncu;
   Geometry& g = p->geo;
   g = Geometry{};
   g.nsub = d.ncol;
@@ -1099,6 +1103,17 @@ s2w_status s2w_bltt_apply(s2w_bltt* p, const float* x, int32_t B, float* y, void
   float2* S = (float2*)(p->ws + p->o_s);
   float* part = (float*)(p->ws + p->o_part);
   float2* yh = (float2*)(p->ws + p->o_yh);
+  if (B <= 4) {
+    // few inputs: per-bin matrix-vector products streaming the store once (HBM-bound);
+    // inputs transformed as S[b][l][c]
+    hipError_t e = launch_rfft_rows(x, B, ncol, p->ncol_k, S, (int64_t)g.M * p->ncol_k, 1, p->ncol_k, g, 1.0f, st);
+    if (e != hipSuccess) return bhip(p, e, "apply: input transform");
+    e = launch_bltt_gemv(Fs, S, yh, nrow, g.M, p->ncol_k, B, p->ncu, st);
+    if (e != hipSuccess) return bhip(p, e, "apply: per-bin products");
+    e = launch_irfft_rows(yh, (int64_t)B * nrow, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+    if (e != hipSuccess) return bhip(p, e, "apply: output transform");
+    return S2W_OK;
+  }
   // S[l][c][b]
   hipError_t e = launch_rfft_rows(x, B, ncol, p->ncol_k, S, 1, bp, (int64_t)p->ncol_k * bp, g, 1.0f, st);
   if (e != hipSuccess) return bhip(p, e, "apply: input transform");

@@ -92,6 +92,10 @@ int gemm_fw_nf(int hterms, int B);
 inline int gemm_fw_col_tiles(int hterms, int B) { return (B + 64 * gemm_fw_nf(hterms, B) - 1) / (64 * gemm_fw_nf(hterms, B)); }
 hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* V, const float* up, float* part,
                           int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, hipStream_t st);
+// Few-input per-bin products of one BLTT operator (B <= 4), HBM-bound: yh[b][r][l] from the
+// store K[r][l][c] and inputs X[b][l][c] (c padded to an even ncp with zeros).
+hipError_t launch_bltt_gemv(const float2* K, const float2* X, float2* yh, int nrow, int M, int ncp, int B, int ncu,
+                            hipStream_t st);
 hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngrid, int ngq, int M, int noq, int B,
                           int bp, int splits, hipStream_t st);
 // rupts: ruptures per unit of the M = 256 kernel (16 or 32; other values mean 16)

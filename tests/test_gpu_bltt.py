@@ -43,7 +43,7 @@ SHAPES = [
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=[f"{a}x{b}x{c}" for a, b, c in SHAPES])
-@pytest.mark.parametrize("B", [1, 5, 70])
+@pytest.mark.parametrize("B", [1, 2, 3, 5, 70])
 def test_apply_and_adjoint_match_oracle(shape, B):
     nrow, ncol, nt = shape
     log_case("bltt", shape=shape, B=B)
