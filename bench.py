@@ -411,6 +411,7 @@ def main():
         nrup = max(args.steps, args.warmup, 1)
         s_host = synth.gen_slip_batch(scfg, 0, nrup)
         s_dev = torch.tensor(s_host, device=dev).reshape(nrup, 1, scfg.nsub, scfg.nt)
+        tuning = tune(op, 1, s=s_dev[0])
         total_ms, kern_ms, wall = time_path(op, s_dev, args.steps, args.warmup, 1)
         ms_step = total_ms / args.steps
         abytes = algorithmic_bytes(scfg.nsub, scfg.nobs, scfg.ngrid, scfg.nt, 4)
@@ -418,7 +419,7 @@ def main():
         sh = {"workload": f"{scfg.nsub}x{scfg.ngrid}x{scfg.nobs}x{scfg.nt}", "ruptures_per_s": 1000.0 / ms_step,
               "ms_per_step": ms_step, "kernel_ms": kmean, "algorithmic_bytes": abytes,
               "achieved_GBs": abytes / (kmean * 1e6), "hbm_frac": abytes / (kmean * 1e6) / HBM_PEAK_GBS,
-              "setup_s": setup_s}
+              "setup_s": setup_s, "tuning": tuning}
         log(f"{name}: {ms_step:.3f} ms/rupture, kernel {kmean:.3f} ms, {sh['achieved_GBs']:.0f} GB/s")
         result[key] = sh
         del op
