@@ -65,3 +65,32 @@ def test_largest_batch(path):
     eg = oracle.rel_l2_per_rupture(g, oracle.adjoint(G, F, r))
     print(path, "adjoint rel-L2 max", eg.max())
     assert eg.max() <= tol
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+def test_empty_batch_every_path(path):
+    # B = 0 is a valid call on every layout and store precision: nothing is enqueued and the
+    # outputs are empty; a following call still matches the oracle
+    kw, tol = PATHS[path]
+    cfg = synth.SynthConfig(nsub=9, ngrid=40, nobs=3, nt=20, seed=95, slip_seed=96, op_kind="dense",
+                            slip_mode="dense")
+    log_case("limits_empty", path=path)
+    op = make_operator(cfg, max_batch=4, **kw)
+    s0 = torch.empty((0, cfg.nsub, cfg.nt), device="cuda:0")
+    r0 = torch.empty((0, cfg.nobs, cfg.nt), device="cuda:0")
+    assert op.forward(s0).shape == (0, cfg.nobs, cfg.nt)
+    assert op.adjoint(r0).shape == (0, cfg.nsub, cfg.nt)
+    s = synth.gen_slip_batch(cfg, 0, 2)
+    G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
+    assert oracle.rel_l2_per_rupture(op.forward(to_dev(s)).cpu().numpy(), oracle.forward(G, F, s)).max() <= tol
+
+
+def test_empty_batch_bltt():
+    from paper_2608_21763_amd import BLTTOperator
+    K = synth.normals(96, "x", 0, (7, 5, 12)).astype(np.float32)
+    op = BLTTOperator(7, 5, 12, max_batch=3)
+    keep = op.set_blocks(to_dev(K), 0)
+    torch.cuda.synchronize()
+    del keep
+    assert op.apply(torch.empty((0, 5, 12), device="cuda:0")).shape == (0, 7, 12)
+    assert op.adjoint(torch.empty((0, 7, 12), device="cuda:0")).shape == (0, 5, 12)
