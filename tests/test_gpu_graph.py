@@ -18,6 +18,7 @@ KINDS = {
     "single": dict(layout="single"),
     "batched32": dict(layout="batched"),
     "half": dict(g_dtype="bf16", f_dtype="bf16"),
+    "half16": dict(g_dtype="f16", f_dtype="f16"),
 }
 
 
@@ -108,3 +109,30 @@ def test_autotune_keeps_results(kind, tmp_path):
         assert torch.equal(op.adjoint(r), g0)
     again = autotune(op, B, cache_path=cache)
     assert again["cached"] and again["best"] == res["best"]
+
+
+@pytest.mark.parametrize("B", [1, 6])
+def test_bltt_graph_replays(B):
+    # the standalone operator's apply (matrix-vector kernel for B <= 4, matrix cores beyond)
+    # and adjoint replay from a captured graph with the eager results
+    from paper_2608_21763_amd import BLTTOperator
+    nrow, ncol, nt = 50, 30, 40
+    K = synth.normals(87, "x", 0, (nrow, ncol, nt)).astype(np.float32)
+    op = BLTTOperator(nrow, ncol, nt, max_batch=B)
+    keep = op.set_blocks(to_dev(K), 0)
+    torch.cuda.synchronize()
+    del keep
+    x = to_dev(synth.normals(87, "y", 0, (B, ncol, nt)))
+    r = to_dev(synth.normals(87, "r", 0, (B, nrow, nt)))
+    y = torch.empty((B, nrow, nt), device="cuda:0")
+    g = torch.empty((B, ncol, nt), device="cuda:0")
+    ye, ge = op.apply(x).clone(), op.adjoint(r).clone()
+    graph = _capture(lambda: (op.apply(x, out=y), op.adjoint(r, out=g)))
+    for k in range(3):
+        y.zero_()
+        g.zero_()
+        op.apply(x)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ye) and torch.equal(g, ge), f"replay {k}"
