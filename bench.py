@@ -143,8 +143,8 @@ def main():
                     help="first run a plain device copy of this many MiB (counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the cross-GPU sum of partial waveforms "
-                                   "is outside it (see DESIGN.md for how the share would shard)"}))
+        print(json.dumps({"error": "the library measures one GPU's share only: each GPU computes its own partial "
+                                   "waveforms, and the cross-GPU sum of those partials is not implemented"}))
         sys.exit(2)
 
     import numpy as np
