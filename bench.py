@@ -193,6 +193,23 @@ def main():
                 "achieved_GBs": abytes / (kmean * 1e6), "hbm_frac": abytes / (kmean * 1e6) / HBM_PEAK_GBS,
                 "setup_s": setup_s}
         log(f"fp32: {ms_step:.3f} ms/rupture, kernel {kmean:.3f} ms, {fp32['achieved_GBs']:.0f} GB/s")
+        # the single-rupture adjoint (misfit gradient of one rupture) streams the same two stores
+        from paper_2608_21763_amd.hiprt import HipEvent
+        r1 = torch.randn((1, cfg.nobs, cfg.nt), device=dev)
+        g1 = torch.empty((1, cfg.nsub, cfg.nt), device=dev)
+        for _ in range(args.warmup):
+            op.adjoint(r1, out=g1)
+        torch.cuda.synchronize()
+        a0, a1 = HipEvent(), HipEvent()
+        a0.record(torch.cuda.current_stream().cuda_stream)
+        for _ in range(args.steps):
+            op.adjoint(r1, out=g1)
+        a1.record(torch.cuda.current_stream().cuda_stream)
+        a1.synchronize()
+        adj_ms = a0.elapsed_ms(a1) / args.steps
+        fp32["adjoint_ms_per_call"] = adj_ms
+        fp32["adjoint_GBs"] = abytes / (adj_ms * 1e6)
+        log(f"fp32 adjoint B=1: {adj_ms:.3f} ms/gradient, {fp32['adjoint_GBs']:.0f} GB/s (whole call)")
         result["fp32"] = fp32
         if not args.no_cpu_baseline:
             import oracle
