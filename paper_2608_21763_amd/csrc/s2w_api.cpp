@@ -646,10 +646,15 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
   const bool fscale = h.ht_f == 2;
-  e = launch_mid_batch(U, sF, B, bp, false, packed, g, st, p->tune.mid_rupts);
+  // float16 acoustic operands: the column scales come from maxima the mid-chain keeps as it
+  // writes (M = 256), else from a pass over U
+  int groups = 0;
+  e = launch_mid_batch(U, sF, B, bp, false, packed, g, st, p->tune.mid_rupts, fscale ? part : nullptr,
+                       part_floats(p), &groups);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
-    e = launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
+    e = groups > 0 ? launch_col_scale_final(part, groups, g.M, B, bp, tau_up, tau_down, st)
+                   : launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
   }
   if (wide) {
@@ -804,8 +809,12 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
                     (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: acoustic matrix-core stage");
-  e = launch_mid_batch(W, sG, B, bp, true, false, g, st, p->tune.mid_rupts);
-  if (e == hipSuccess && sg16) e = launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
+  int groups = 0;
+  e = launch_mid_batch(W, sG, B, bp, true, false, g, st, p->tune.mid_rupts, sg16 ? part : nullptr, part_floats(p),
+                       &groups);
+  if (e == hipSuccess && sg16)
+    e = groups > 0 ? launch_col_scale_final(part, groups, g.M, B, bp, tau_up, tau_down, st)
+                   : launch_col_scale(W, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(G[g][l][j]) W'[g][l][b] (row-block-major store)
   const int64_t prow = 2 * (int64_t)bp;

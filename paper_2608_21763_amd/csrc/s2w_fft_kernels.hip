@@ -540,9 +540,13 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
 // M = 256: 16 ruptures of one grid row per unit, the next unit's rows prefetched into
 // registers while the current one is transformed; rows kept with a padded stride (257) so
 // that the strided LDS writes and reads of the gather and scatter are conflict-free.
+// With cmax, the grid is a multiple of the rupture blocks per row (nbb), so a workgroup always
+// works on the same block of ruptures; it keeps the largest |Re|, |Im| of every (slot, rupture)
+// it writes and leaves them in cmax[blockIdx / nbb][l][b] (b < bp; zero for b >= B).
 template <int PACK, int R>
 __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF,
-                                                         int ngrid, int B, int bp, int nt, int mode, float mscale) {
+                                                         int ngrid, int B, int bp, int nt, int mode, float mscale,
+                                                         float* __restrict__ cmax) {
   constexpr int M = 256, LD = 257;
   __shared__ float2 X[R * LD];
   __shared__ float2 T[R * 16 * 17];
@@ -554,6 +558,9 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
   const int64_t units = (int64_t)ngrid * nbb;
   float2 pre[16];
   float fs[16];
+  float cmx[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) cmx[k] = 0.f;
   auto fetch = [&](int64_t u) {
     const int g = (int)(u / nbb);
     const int b = (int)(u % nbb) * R + r;
@@ -583,15 +590,27 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const int l = lq + 16 * k;
-        store_v<PACK>(dst + (int64_t)l * bp, T[r * LD + l], f[k]);
+        const float2 v = T[r * LD + l];
+        store_v<PACK>(dst + (int64_t)l * bp, v, f[k]);
+        if (cmax) cmx[k] = fmaxf(cmx[k], fmaxf(fabsf(v.x * f[k]), fabsf(v.y * f[k])));
       }
     }
     __syncthreads();
   }
+  if (cmax) {
+    const int b = (int)(blockIdx.x % nbb) * R + r;
+    if (b < bp) {
+      float* o = cmax + (int64_t)(blockIdx.x / nbb) * M * bp + b;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) o[(int64_t)(lq + 16 * k) * bp] = b < B ? cmx[k] : 0.f;
+    }
+  }
 }
 
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
-                            const Geometry& g, hipStream_t st, int rupts) {
+                            const Geometry& g, hipStream_t st, int rupts, float* cmax, int64_t cmax_floats,
+                            int* cmax_groups) {
+  if (cmax_groups) *cmax_groups = 0;
   constexpr int R = 16;
   const int mode = g.diff ? (adjoint ? MID_BACKWARD_T : MID_BACKWARD) : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
@@ -601,11 +620,20 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
     // units of 16 or 32 ruptures of one grid row (32: 256-byte runs per slot, one 512-thread
     // workgroup per CU)
     const int ru = rupts == 32 ? 32 : 16;
-    const int64_t units256 = (int64_t)g.ngrid * ((B + ru - 1) / ru);
-    const int64_t nb256 = std::min<int64_t>(units256, 256 * 8);
+    const int nbb = (B + ru - 1) / ru;
+    const int64_t units256 = (int64_t)g.ngrid * nbb;
+    int64_t nb256 = std::min<int64_t>(units256, 256 * 8);
+    if (cmax) {
+      // whole groups of nbb workgroups, as many groups as the partial maxima fit
+      const int64_t gmax = cmax_floats / ((int64_t)g.M * bp);
+      int64_t groups = std::min<int64_t>(std::max<int64_t>(1, nb256 / nbb), gmax);
+      if (groups < 1) return hipErrorInvalidValue;
+      nb256 = groups * nbb;
+      if (cmax_groups) *cmax_groups = (int)groups;
+    }
 #define S2W_MID256(P_, R_)                                                                                       \
   hipLaunchKernelGGL((k_mid_batch256<P_, R_>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF, g.ngrid, B, bp, \
-                     g.nt, mode, mscale)
+                     g.nt, mode, mscale, cmax)
     if (ru == 32) {
       if (pack_bf16) S2W_MID256(1, 32); else S2W_MID256(0, 32);
     } else {

@@ -98,9 +98,16 @@ hipError_t launch_bltt_gemv(const float2* K, const float2* X, float2* yh, int nr
                             hipStream_t st);
 hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngrid, int ngq, int M, int noq, int B,
                           int bp, int splits, hipStream_t st);
-// rupts: ruptures per unit of the M = 256 kernel (16 or 32; other values mean 16)
+// rupts: ruptures per unit of the M = 256 kernel (16 or 32; other values mean 16).  With cmax
+// (M = 256 only) the kernel also leaves per-(slot, rupture) maxima of |Re|, |Im| of what it
+// writes in cmax[group][l][b] (at most cmax_floats floats) and sets *cmax_groups to the group
+// count; elsewhere *cmax_groups is 0 and no maxima are produced.
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
-                            const Geometry& g, hipStream_t st, int rupts = 16);
+                            const Geometry& g, hipStream_t st, int rupts = 16, float* cmax = nullptr,
+                            int64_t cmax_floats = 0, int* cmax_groups = nullptr);
+// Power-of-two column scales from partial maxima part[s][l][b], s < splits (columns b >= B get 1).
+hipError_t launch_col_scale_final(const float* part, int splits, int M, int B, int bp, float* tau_up, float* tau_down,
+                                  hipStream_t st);
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
                             float* part, int64_t part_floats, hipStream_t st);
 hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,

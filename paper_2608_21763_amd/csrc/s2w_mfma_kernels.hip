@@ -1184,11 +1184,13 @@ __global__ __launch_bounds__(256) void k_col_max(const float2* __restrict__ V, i
 }
 
 __global__ __launch_bounds__(256) void k_col_scale_final(const float* __restrict__ part, int splits, int64_t n,
-                                                         float* __restrict__ tau_up, float* __restrict__ tau_down) {
+                                                         int B, int bp, float* __restrict__ tau_up,
+                                                         float* __restrict__ tau_down) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   float mx = 0.f;
-  for (int s = 0; s < splits; ++s) mx = fmaxf(mx, part[(int64_t)s * n + i]);
+  if ((int)(i % bp) < B)
+    for (int s = 0; s < splits; ++s) mx = fmaxf(mx, part[(int64_t)s * n + i]);
   float up, down;
   pow2_scale(mx, up, down);
   tau_up[i] = up;
@@ -1205,7 +1207,16 @@ hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, fl
   if ((int64_t)splits * n > part_floats) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_col_max, dim3((unsigned)nblk, (unsigned)splits), dim3(256), 0, st, V, ngrid, M, B, bp, splits,
                      part);
-  hipLaunchKernelGGL(k_col_scale_final, dim3((unsigned)nblk), dim3(256), 0, st, part, splits, n, tau_up, tau_down);
+  hipLaunchKernelGGL(k_col_scale_final, dim3((unsigned)nblk), dim3(256), 0, st, part, splits, n, B, bp, tau_up,
+                     tau_down);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_scale_final(const float* part, int splits, int M, int B, int bp, float* tau_up, float* tau_down,
+                                  hipStream_t st) {
+  const int64_t n = (int64_t)M * bp;
+  hipLaunchKernelGGL(k_col_scale_final, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, splits, n, B, bp,
+                     tau_up, tau_down);
   return hipGetLastError();
 }
 
