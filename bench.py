@@ -119,6 +119,42 @@ def time_path(op, s_dev, steps: int, warmup: int, B: int):
     return total_ms, kern_ms, wall
 
 
+def time_graph(op, s_dev, steps: int, B: int) -> float:
+    """ms per replay of captured forward calls (one graph per input buffer, replayed in turn)."""
+    import torch
+    from paper_2608_21763_amd.hiprt import HipEvent
+
+    nb = s_dev.shape[0]
+    out = torch.empty((B, op.nobs, op.nt), dtype=torch.float32, device=s_dev.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for k in range(nb):
+            op.forward(s_dev[k], out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graphs = []
+    for k in range(nb):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            op.forward(s_dev[k], out=out)
+        graphs.append(g)
+    torch.cuda.synchronize()
+    for g in graphs:
+        g.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream().cuda_stream
+    t0, t1 = HipEvent(), HipEvent()
+    t0.record(stream)
+    for k in range(steps):
+        graphs[k % nb].replay()
+    t1.record(stream)
+    t1.synchronize()
+    ms = t0.elapsed_ms(t1) / steps
+    del graphs
+    return ms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +171,7 @@ def main():
     ap.add_argument("--batch-adj", type=int, default=64, help="residuals per call on the batched float32 adjoint")
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-graph replay timing of the half paths")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the library's default tiles on the batched paths instead of the autotuner's choice")
     ap.add_argument("--ngrid", type=int, default=None, help="override the share size (testing only)")
@@ -315,6 +352,9 @@ def main():
                "setup_s": setup_s}
         log(f"half {gdt}/{fdt} B={B}: {ms_step:.3f} ms/call, {res['ruptures_per_s']:.0f} ruptures/s, "
             f"elastic GEMM {kmean:.3f} ms = {res['achieved_TFLOPs']:.0f} TFLOP/s algorithmic")
+        if not args.no_graph:
+            res["graph_ms_per_step"] = time_graph(op, s_dev, args.steps, B)
+            log(f"half {gdt}/{fdt} B={B}: {res['graph_ms_per_step']:.3f} ms per captured-graph replay")
         if not args.no_cpu_baseline:
             y = op.forward(s_dev[0]).cpu().numpy().astype(np.float64)
             act = [int(np.count_nonzero(np.any(s_host[b] != 0, axis=1))) for b in range(B)]
