@@ -15,9 +15,9 @@
  * the time axis and diagonalising it with a real FFT (Alg. 2), the seafloor
  * field staying on the device between them (Alg. 1).
  *
- * D_t: the paper names only a "temporal-difference stencil".  S2W_DIFF_BACKWARD
- * applies v_n = (m_n - m_{n-1})/dt with m_{-1} = 0 (causal, Toeplitz);
- * S2W_DIFF_NONE makes D_t the identity.
+ * D_t: the paper leaves the difference stencil unspecified (Sec. II-B2).
+ * S2W_DIFF_BACKWARD applies v_n = (m_n - m_{n-1})/dt with m_{-1} = 0 (causal,
+ * Toeplitz); S2W_DIFF_NONE makes D_t the identity.
  *
  * Conventions for every entry point:
  *  - All device pointers must be 256-byte aligned and distinct.  The caller
