@@ -277,7 +277,7 @@ def main():
             return None
         from paper_2608_21763_amd import autotune
         t = time.perf_counter()
-        res = autotune(op, B, reps=2, adjoint=adjoint, s=s)
+        res = autotune(op, B, reps=2 if B > 1 else 8, adjoint=adjoint, s=s)
         log(f"autotune B={B}: {res['best']} ({res['ms']:.2f} ms, {len(res['results'])} shapes, "
             f"{time.perf_counter() - t:.1f} s)")
         return res["best"]
