@@ -157,11 +157,24 @@ __global__ __launch_bounds__(256) void k_prep_act(const float2* __restrict__ S, 
   if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
 }
 
+// Unit scales: bfloat16 activations keep float32's exponent range, so they are split without
+// a range scale (scaling by a power of two would change no rounding).
+__global__ __launch_bounds__(256) void k_unit_scale(int64_t n, float* __restrict__ sig_up, float* __restrict__ sig_down) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    sig_up[i] = 1.f;
+    sig_down[i] = 1.f;
+  }
+}
+
 hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
                            int nsq, int B, int bp, int nks, int ncb, uint4* Bop, hipStream_t st) {
   const int64_t ns = (int64_t)M * bp;
-  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp, sig_up,
-                     sig_down);
+  if (ht == 1)
+    hipLaunchKernelGGL(k_unit_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns, sig_up, sig_down);
+  else
+    hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp,
+                       sig_up, sig_down);
   const int64_t total = (int64_t)M * nks * ncb * 64;
   dim3 grid((unsigned)((total + 255) / 256));
 #define S2W_PREP(HT_, H_) \
