@@ -82,7 +82,7 @@ def traffic_for(kernel: str):
 
 def elastic_kernel(cfg: int) -> str:
     """Kernel of the batched half-precision elastic GEMM for tile setting `cfg` (-1 automatic)."""
-    if cfg in (-1, 10, 11, 12, 13, 14, 15, 16):
+    if cfg in (-1, 10, 11, 12, 13, 14, 15, 16, 17, 18):
         return "k_gemm_g4"
     if cfg in (7, 8, 9):
         return "k_gemm_g3"

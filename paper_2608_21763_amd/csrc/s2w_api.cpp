@@ -416,7 +416,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
   }
   if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
   if (t->gemm_cfg) {
-    if (t->gemm_cfg < -1 || t->gemm_cfg > 16) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    if (t->gemm_cfg < -1 || t->gemm_cfg > 18) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) {
@@ -610,7 +610,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int bp = h.bp;
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
-  if (cfg < 0) cfg = B <= 64 ? 12 : 10;
+  if (cfg < 0) cfg = B <= 64 ? 12 : 17;
   // acoustic GEMM: fgemm_lds 1 takes the LDS-staged kernel for packed bfloat16 activations
   // (when its tile fits) and the eight-wave kernel for float16; 2 takes the eight-wave kernel
   // for both (the mid-chain then leaves complex64); 0 the register kernel
@@ -629,6 +629,9 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (e == hipSuccess) {
     if (compact)
       e = launch_prep_act_compact(h.ht_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (uint2*)Bop, st);
+    else if (cfg == 17 || cfg == 18)
+      e = launch_prep_act_re(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (B + 15) / 16,
+                             Bop, st);
     else
       e = launch_prep_act(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, ncb, Bop, st);
   }

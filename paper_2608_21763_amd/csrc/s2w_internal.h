@@ -67,6 +67,10 @@ hipError_t launch_quant_rows(int ht, const float2* staging, int64_t nrows, int M
                              int64_t row0, int64_t sg, int64_t sl, int64_t sc, float* scale, int ng16, hipStream_t st);
 hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
                            int nsq, int B, int bp, int nks, int ncb, uint4* Bop, hipStream_t st);
+// Real-column activation fragments for the elastic GEMM tiles 17 and 18: Bre[l][ks][rcb][h][lane]
+// with rcb < (B + 15) / 16 blocks of 16 ruptures (half the size of Bop).
+hipError_t launch_prep_act_re(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
+                              int nsq, int B, int bp, int nks, int nrcb, uint4* Bre, hipStream_t st);
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
                          hipStream_t st);

@@ -188,6 +188,72 @@ hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, f
   return hipGetLastError();
 }
 
+// Real-column activation fragments: Bre[l][ks][rcb][h][lane] (16 bytes each) hold only the
+// real-part output column of rupture 16*rcb + lane%16 (K entries (Re s, -Im s) of subfaults
+// 16*ks + 4*(lane/16) .. +3; slot 0: (Re s, Im s)).  The imaginary-part column (Im s, Re s)
+// (slot 0: (0, Im s)) is formed from it in registers, so the store and its copies are half the
+// size of Bop.  The words equal those of k_prep_act for the same columns.
+template <int HT, int H>
+__global__ __launch_bounds__(256) void k_prep_act_re(const float2* __restrict__ S, const float* __restrict__ sig_up,
+                                                     int M, int nsub, int nsq, int B, int bp, int nks, int nrcb,
+                                                     uint4* __restrict__ Bre) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)M * nks * nrcb * 64;
+  if (i >= total) return;
+  const int lane = (int)(i & 63);
+  int64_t q = i >> 6;
+  const int rcb = (int)(q % nrcb);
+  q /= nrcb;
+  const int ks = (int)(q % nks);
+  const int l = (int)(q / nks);
+  const int b = 16 * rcb + (lane & 15);
+  const bool dc = (l == 0);
+  uint32_t hi[4], lo[4];
+#pragma unroll
+  for (int e2 = 0; e2 < 4; ++e2) {
+    const int j = 16 * ks + 4 * (lane >> 4) + e2;
+    float2 s = make_float2(0.f, 0.f);
+    if (b < B && j < nsub) {
+      s = S[((int64_t)l * nsq + j) * bp + b];
+      const float u = sig_up[(int64_t)l * bp + b];
+      s.x *= u;
+      s.y *= u;
+    }
+    const float v0 = s.x, v1 = dc ? s.y : -s.y;
+    const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
+    hi[e2] = h0 | (h1 << 16);
+    if (H == 2) {
+      const uint32_t l0 = to_half_bits<HT>(v0 - from_half_bits<HT>(h0));
+      const uint32_t l1 = to_half_bits<HT>(v1 - from_half_bits<HT>(h1));
+      lo[e2] = l0 | (l1 << 16);
+    }
+  }
+  uint4* dst = Bre + (((int64_t)l * nks + ks) * nrcb + rcb) * H * 64 + lane;
+  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+}
+
+hipError_t launch_prep_act_re(int ht, int hterms, const float2* S, float* sig_up, float* sig_down, int M, int nsub,
+                              int nsq, int B, int bp, int nks, int nrcb, uint4* Bre, hipStream_t st) {
+  const int64_t ns = (int64_t)M * bp;
+  if (ht == 1)
+    hipLaunchKernelGGL(k_unit_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns, sig_up, sig_down);
+  else
+    hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp,
+                       sig_up, sig_down);
+  const int64_t total = (int64_t)M * nks * nrcb * 64;
+  dim3 grid((unsigned)((total + 255) / 256));
+#define S2W_PREPR(HT_, H_) \
+  hipLaunchKernelGGL((k_prep_act_re<HT_, H_>), grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, nrcb, Bre)
+  if (ht == 1) {
+    if (hterms == 2) S2W_PREPR(1, 2); else S2W_PREPR(1, 1);
+  } else {
+    if (hterms == 2) S2W_PREPR(2, 2); else S2W_PREPR(2, 1);
+  }
+#undef S2W_PREPR
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------------------------
 // Elastic GEMM per bin (eq. 1, Alg. 2 step 3, batched):
 //   U[g][l][b] = sG[g][l] * sig_down[l][b] * sum_j Gq[g][l][j] (x) Sq[l][j][b]
@@ -623,7 +689,40 @@ __device__ __forceinline__ void g4_compute(const uint4* cur, f32x4 (&acc)[MF][NF
   (void)WC;
 }
 
-template <int HT, int H, int MW, int NW, int NS, int WR, int WC, int MINB = 1>
+// Products of one K step from real-column fragments (layout of k_prep_act_re): for rupture
+// block q of this wave, the stored fragment gives the real-part columns and, with its halves
+// swapped and the new low half negated (slot 0: masked), the imaginary-part columns; tiles
+// 2q and 2q + 1 of acc take them.  Every tile accumulates its terms in the same order as
+// g4_compute does for the same output columns.
+__device__ __forceinline__ uint32_t im_word(uint32_t w, bool dc) {
+  return dc ? (w & 0xffff0000u) : (((w >> 16) | (w << 16)) ^ 0x8000u);
+}
+
+template <int HT, int H, int MF, int NF, int MW, int A_BLK, int WC>
+__device__ __forceinline__ void g4_compute_re(const uint4* cur, f32x4 (&acc)[MF][NF], int wr, int wc, int lane,
+                                              bool dc) {
+  const uint4* lb = cur + A_BLK * 64;
+  uint4 av[MF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a) av[a] = cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+  for (int q = 0; q < NF / 2; ++q)
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint4 w = lb[((wc * (NF / 2) + q) * H + h) * 64 + lane];
+      const uint4 re = dc ? make_uint4(w.x & 0xffffu, w.y & 0xffffu, w.z & 0xffffu, w.w & 0xffffu) : w;
+      const uint4 im = make_uint4(im_word(w.x, dc), im_word(w.y, dc), im_word(w.z, dc), im_word(w.w, dc));
+#pragma unroll
+      for (int a = 0; a < MF; ++a) acc[a][2 * q] = mfma16<HT>(av[a], re, acc[a][2 * q]);
+#pragma unroll
+      for (int a = 0; a < MF; ++a) acc[a][2 * q + 1] = mfma16<HT>(av[a], im, acc[a][2 * q + 1]);
+    }
+  (void)WC;
+}
+
+// RE: the activation store is the real-column layout of k_prep_act_re (ncb then counts its
+// 16-rupture blocks) and the imaginary-part columns are formed in registers.
+template <int HT, int H, int MW, int NW, int NS, int WR, int WC, int MINB = 1, bool RE = false>
 __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __restrict__ Gq, const float* __restrict__ sG,
                                                     const uint4* __restrict__ Bop, const float* __restrict__ sig_down,
                                                     float* __restrict__ U, int ngrid, int M, int nks, int ncb, int B,
@@ -633,7 +732,8 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
   constexpr int RT = WR * MW;                // rows per tile
   constexpr int CBT = WC * NF;               // column blocks per tile
   constexpr int A_BLK = RT / 16;             // 1 KB copy blocks of the operator tile per K step
-  constexpr int B_BLK = CBT * H;             // 1 KB copy blocks of the activation tile per K step
+  constexpr int B_BLK = (RE ? CBT / 2 : CBT) * H;  // 1 KB copy blocks of the activation tile per K step
+  static_assert(!RE || (NF % 2 == 0), "real-column fragments cover whole 16-rupture blocks");
   constexpr int NBLK = A_BLK + B_BLK;
   constexpr int PER_W = NBLK / NWAVE;        // copy instructions per wave per K step
   constexpr int STAGE = NBLK * 64;           // uint4 per stage
@@ -675,7 +775,7 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
         sstep[q] = kGqStepU4;
       } else {
         const int j = blk - A_BLK;
-        const int cb = min(cbt0 + j / H, ncb - 1), h = j % H;
+        const int cb = min((RE ? cbt0 / 2 : cbt0) + j / H, ncb - 1), h = j % H;
         src[q] = Bop + (((int64_t)l * nks * ncb + cb) * H + h) * 64 + lane;
         sstep[q] = (int64_t)ncb * H * 64;
       }
@@ -696,7 +796,10 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
   do {                                                                  \
     g4_sync<PENDING>();                                                 \
     g4_issue<PER_W, NWAVE>(src, sstep, (K) + NS - 1, nks, NEXT, wave);  \
-    if ((K) < nks) g4_compute<HT, H, MF, NF, MW, A_BLK, WC>(CUR, acc, wr, wc, lane); \
+    if ((K) < nks) {                                                  \
+      if (RE) g4_compute_re<HT, H, MF, NF, MW, A_BLK, WC>(CUR, acc, wr, wc, lane, l == 0); \
+      else g4_compute<HT, H, MF, NF, MW, A_BLK, WC>(CUR, acc, wr, wc, lane); \
+    }                                                                   \
   } while (0)
     for (int k0 = 0; k0 < nks; k0 += NS) {
       if (NS == 2) {
@@ -723,12 +826,20 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
         const float sg = sG[(int64_t)g * M + l];
 #pragma unroll
         for (int b = 0; b < NF; ++b) {
-          const int cb = cbt0 + wc * NF + b;
-          const int n = 16 * cb + (lane & 15);
-          const int rup = n >> 1;
-          if (cb < ncb && rup < B)
-            U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
-                acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+          if (RE) {
+            const int rcb = cbt0 / 2 + wc * (NF / 2) + (b >> 1);
+            const int rup = 16 * rcb + (lane & 15);
+            if (rcb < ncb && rup < B)
+              U[(((int64_t)g * M + l) * bp + rup) * 2 + (b & 1)] =
+                  acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+          } else {
+            const int cb = cbt0 + wc * NF + b;
+            const int n = 16 * cb + (lane & 15);
+            const int rup = n >> 1;
+            if (cb < ncb && rup < B)
+              U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
+                  acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+          }
         }
       }
   }
@@ -763,6 +874,21 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
       else
         hipLaunchKernelGGL((k_gemm_g2<HT, H, 64, 128>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
                            nks, ncb, B, bp, nrb, nct);
+      break;
+    }
+    case 17:
+    case 18: {
+      // tile 10 on real-column activation fragments (k_prep_act_re): 17 with four stages of
+      // 32 KB, 18 with three
+      const int nrcb = (B + 15) / 16;
+      const int nrb = (ngrid + 255) / 256;
+      const int nct = (nrcb + 7) / 8;
+      if (cfg == 17)
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 4, 2, 4, 1, true>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop,
+                           sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
+      else
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 3, 2, 4, 1, true>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop,
+                           sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
       break;
     }
     case 10:

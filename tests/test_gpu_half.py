@@ -180,7 +180,7 @@ def test_elastic_gemm_tile_shapes_agree(B):
     op = make_operator(cfg, max_batch=B, g_dtype="f16", f_dtype="f16")
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
     outs = {}
-    for c in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16):
+    for c in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18):
         op.set_tuning(gemm_cfg=c)
         outs[c] = op.forward(s).clone()
     for c in outs:
