@@ -610,7 +610,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int bp = h.bp;
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
-  if (cfg < 0) cfg = B <= 64 ? 12 : 17;
+  if (cfg < 0) cfg = B <= 64 ? 12 : 18;
   // acoustic GEMM: fgemm_lds 1 takes the LDS-staged kernel for packed bfloat16 activations
   // (when its tile fits) and the eight-wave kernel for float16; 2 takes the eight-wave kernel
   // for both (the mid-chain then leaves complex64); 0 the register kernel
