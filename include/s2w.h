@@ -155,9 +155,11 @@ typedef struct s2w_tuning {
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
   int32_t adj32_splits;      /* batched adjoint (float32 and half stores), transposed elastic GEMM: grid-row
                                 splits (1..8; half stores may clamp to what the partial region holds) */
-  int32_t hadj_tile_f;       /* half-precision adjoint, transposed acoustic GEMM tile: -1 automatic, 1..5 =
+  int32_t hadj_tile_f;       /* half-precision adjoint, transposed acoustic GEMM tile: -1 automatic, 1..8 =
                                 rows x columns 64 x 256, 256 x 64 (four waves), 256 x 64, 256 x 128,
-                                256 x 256 (eight waves, both operands through LDS) */
+                                256 x 256 (eight waves, both operands through LDS), then 6..8 = tiles
+                                3..5 holding only real-column activation fragments in LDS (same
+                                results bit for bit) */
   int32_t hadj_tile_g;       /* half-precision adjoint, transposed elastic GEMM tile: same values */
   int32_t mid_rupts;         /* batched mid-chain (Nt = 256): ruptures per work unit, 16 or 32 */
 } s2w_tuning;

@@ -24,7 +24,8 @@ def candidates(op, adjoint: bool = False) -> list[dict]:
     """Tuning dictionaries worth timing for this operator's path (forward, or adjoint)."""
     if adjoint:
         if op.g_dtype != "f32":
-            return [{"hadj_tile_f": a, "hadj_tile_g": b} for a in (1, 3, 4, 5) for b in (3, 4, 5)]
+            return [{"hadj_tile_f": a, "hadj_tile_g": b} for a in (1, 3, 4, 5, 6, 7, 8)
+                    for b in (3, 4, 5, 6, 7, 8)]
         if op.plan_layout() == "batched":
             return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
         return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]

@@ -444,7 +444,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.fgemm_splits = t->fgemm_splits;
   }
   if (t->hadj_tile_f) {
-    if (t->hadj_tile_f < -1 || t->hadj_tile_f > 5) return fail(p, S2W_EINVAL, "tuning: hadj_tile_f");
+    if (t->hadj_tile_f < -1 || t->hadj_tile_f > 8) return fail(p, S2W_EINVAL, "tuning: hadj_tile_f");
     n.hadj_tile_f = t->hadj_tile_f < 0 ? -1 : t->hadj_tile_f - 1;
   }
   if (t->mid_rupts) {
@@ -452,7 +452,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.mid_rupts = t->mid_rupts;
   }
   if (t->hadj_tile_g) {
-    if (t->hadj_tile_g < -1 || t->hadj_tile_g > 5) return fail(p, S2W_EINVAL, "tuning: hadj_tile_g");
+    if (t->hadj_tile_g < -1 || t->hadj_tile_g > 8) return fail(p, S2W_EINVAL, "tuning: hadj_tile_g");
     n.hadj_tile_g = t->hadj_tile_g < 0 ? -1 : t->hadj_tile_g - 1;
   }
   p->tune = n;
@@ -804,9 +804,9 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   if (e == hipSuccess && sf16) e = launch_act_scale(R, g.M, g.nobs, g.nobs, B, bp, sig_up, sig_down, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
   // W[g][l][b] = sF[g][l] * sum_o conj(Fq[l][o][g]) R[l][o][b]
-  // default tiles (sweep on the Cascadia-sized share): eight waves, 256 rows x 128 columns, and
-  // 256 x 64 for batches of at most 32
-  const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 2 : 3);
+  // default tiles (sweep on the Cascadia-sized share): eight waves on real-column activation
+  // fragments, 256 rows x 128 columns, and 256 x 64 for batches of at most 32
+  const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 5 : 6);
   e = launch_gemm_t(h.ht_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, 16 * (int64_t)h.ngq, h.ngq, 16, g.ngrid,
                     h.ngq, g.nobs, h.noq, R,
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
@@ -821,8 +821,11 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(G[g][l][j]) W'[g][l][b] (row-block-major store)
   const int64_t prow = 2 * (int64_t)bp;
-  const int shape3 = p->tune.hadj_tile_g >= 0 ? p->tune.hadj_tile_g : (B <= 32 ? 2 : 3);
-  const int cols3 = shape3 == 0 ? 256 : shape3 == 1 ? 64 : shape3 == 2 ? 64 : (shape3 == 3 ? 128 : 256);
+  // the float16 store (one term) takes 256 x 256 tiles for large batches
+  const int shape3 =
+      p->tune.hadj_tile_g >= 0 ? p->tune.hadj_tile_g : (B <= 32 ? 5 : (sg16 && B > 128) ? 7 : 6);
+  const int sh3 = shape3 >= 5 ? shape3 - 3 : shape3;
+  const int cols3 = sh3 == 0 ? 256 : sh3 == 1 ? 64 : sh3 == 2 ? 64 : (sh3 == 3 ? 128 : 256);
   const int rows3 = shape3 == 0 ? 64 : 256;
   const int tiles = g.M * ((g.nsub + rows3 - 1) / rows3) * ((2 * B + cols3 - 1) / cols3);
   const int fit = std::max(1, std::max(h.splits_max * h.noq, h.nsq) / h.nsq);

@@ -183,6 +183,30 @@ __global__ __launch_bounds__(256) void k_gemm_t(const TArgs p) {
     }
 }
 
+// Real-column granule for the RE layout: lane L = 16*kg + c16 of block rb holds the four
+// k = 4*kg + e of rupture 16*rb + c16 as words (x, -y), or (x, y) on the DC bin.
+template <int HT, int H>
+__device__ __forceinline__ void t2_convert_re(const float2* v, float up, bool dc, uint4* dst) {
+  uint32_t hi[4], lo[4];
+#pragma unroll
+  for (int e2 = 0; e2 < 4; ++e2) {
+    const float c0 = v[e2].x * up, y = v[e2].y * up;
+    const float c1 = dc ? y : -y;
+    hi[e2] = pack_half2<HT>(c0, c1);
+    if (H == 2)
+      lo[e2] = pack_half2<HT>(c0 - from_half_bits<HT>(hi[e2] & 0xffffu), c1 - from_half_bits<HT>(hi[e2] >> 16));
+  }
+  dst[0] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  if (H == 2) dst[64] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+}
+
+// Imaginary-column word from a stored real-column word: (x, -y) -> (y, x) off the DC bin
+// (rounding to half is sign-symmetric, so this is the word (y, x) converts to), (x, y) -> (0, y)
+// on it.
+__device__ __forceinline__ uint32_t t2_im_word(uint32_t w, bool dc) {
+  return dc ? (w & 0xffff0000u) : (((w >> 16) | (w << 16)) ^ 0x8000u);
+}
+
 // Eight-wave variant for the long-K product: a 256-row x 32*NF-column tile per workgroup (waves
 // 4 x 2, each 64 rows x 16*NF columns).  Per K step of 16 both operands pass through LDS, double
 // buffered with one barrier per step: the operator tile as [k][row] words, the activation
@@ -195,13 +219,20 @@ struct T2Geo {
   static constexpr int NCB = 2 * NF;                           // 16-column blocks per tile
 };
 
-template <int HT, int H, int NF>
-__global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
+// RE = true keeps only the real-column fragments in LDS (one granule per rupture and four k):
+// off the DC bin the stored word is (x, -y) and the imaginary column (y, x) is that word with its
+// halves swapped and the new low half negated; on the DC bin the stored word is (x, y) and the two
+// columns are its halves masked.  Both columns are then the same bits as the RE = false layout
+// converts, so the products and their accumulation order are unchanged, while the activation
+// copies, LDS writes and LDS fragment reads halve.
+template <int HT, int H, int NF, bool RE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4 : 2))) void k_gemm_t2(const TArgs p) {
   using Gm = T2Geo<NF>;
   constexpr int RT = Gm::RT, LDA = Gm::LDA, RB = Gm::RB, NCB = Gm::NCB;
   constexpr int MF = 4;
+  constexpr int NBS = RE ? NCB / 2 : NCB;  // fragment blocks held in LDS per step
   __shared__ uint32_t la_s[2][16 * LDA];
-  __shared__ uint4 lb_s[2][NCB * H * 64];
+  __shared__ uint4 lb_s[2][NBS * H * 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
@@ -218,7 +249,7 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
   const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
   const float2* Xl = p.X + (int64_t)l * p.x_slot;
   // activation ownership: granule slot s = tid + 512 * rep -> column block s / 64, lane s % 64
-  constexpr int XSLOTS = NCB * 64, XREP = (XSLOTS + 511) / 512;
+  constexpr int XSLOTS = NBS * 64, XREP = (XSLOTS + 511) / 512;
   int bx[XREP], xkg[XREP];
   float upx[XREP];
 #pragma unroll
@@ -226,7 +257,8 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
     const int s = min(tid + 512 * rp, XSLOTS - 1);
     const int L = s & 63;
     xkg[rp] = L >> 4;
-    bx[rp] = min(ct * RB + 8 * (s >> 6) + ((L & 15) >> 1), p.bp - 1);
+    bx[rp] = RE ? min(ct * RB + 16 * (s >> 6) + (L & 15), p.bp - 1)
+                : min(ct * RB + 8 * (s >> 6) + ((L & 15) >> 1), p.bp - 1);
     upx[rp] = p.up ? p.up[(int64_t)l * p.bp + bx[rp]] : 1.f;
   }
   f32x4 acc[MF][NF];
@@ -248,6 +280,7 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
     }
 #pragma unroll
     for (int rp = 0; rp < XREP; ++rp)
+      if (XSLOTS % 512 == 0 || tid + 512 * rp < XSLOTS)  // whole waves without a granule skip the loads
 #pragma unroll
       for (int e2 = 0; e2 < 4; ++e2) {
         const int k = 16 * ks + 4 * xkg[rp] + e2;
@@ -265,9 +298,15 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
 #pragma unroll
     for (int rp = 0; rp < XREP; ++rp) {
       const int s = tid + 512 * rp;
-      if (s < XSLOTS) t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, &lb_s[buf][(s >> 6) * H * 64 + (s & 63)]);
+      if (s < XSLOTS) {
+        uint4* dst = &lb_s[buf][(s >> 6) * H * 64 + (s & 63)];
+        if (RE) t2_convert_re<HT, H>(xv[rp], upx[rp], dc, dst);
+        else t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, dst);
+      }
     }
   };
+  // RE: masks that take the real and imaginary column out of a stored word
+  const uint32_t mre = dc ? 0x0000ffffu : 0xffffffffu;
   if (ks0 < ks1) {
     fetch(ks0);
     stage(0);
@@ -283,16 +322,34 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
         const uint32_t* la = &la_s[cur][(4 * (lane >> 4)) * LDA + r];
         av[a] = make_uint4(la[0] ^ cmask, la[LDA] ^ cmask, la[2 * LDA] ^ cmask, la[3 * LDA] ^ cmask);
       }
+      if (RE) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const int cb = NF * wc + f;
-        const uint4 bh = lb_s[cur][cb * H * 64 + lane];
+        for (int fr = 0; fr < NF / 2; ++fr) {
+          const int cb = (NF / 2) * wc + fr;
 #pragma unroll
-        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
-        if (H == 2) {
-          const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
+          for (int t = 0; t < H; ++t) {
+            const uint4 w = lb_s[cur][cb * H * 64 + 64 * t + lane];
+            const uint4 br = make_uint4(w.x & mre, w.y & mre, w.z & mre, w.w & mre);
+            const uint4 bi = make_uint4(t2_im_word(w.x, dc), t2_im_word(w.y, dc), t2_im_word(w.z, dc),
+                                        t2_im_word(w.w, dc));
 #pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr] = mfma16<HT>(av[a], br, acc[a][2 * fr]);
+#pragma unroll
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr + 1] = mfma16<HT>(av[a], bi, acc[a][2 * fr + 1]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int cb = NF * wc + f;
+          const uint4 bh = lb_s[cur][cb * H * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
+          if (H == 2) {
+            const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
+#pragma unroll
+            for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+          }
         }
       }
       if (more) stage(cur ^ 1);
@@ -307,13 +364,25 @@ __global__ __launch_bounds__(512) void k_gemm_t2(const TArgs p) {
       const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
       if (row < p.nrows) {
         const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
+        if (RE) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const int n = 2 * ct * RB + 16 * (NF * wc + f) + (lane & 15);
-          const int b = n >> 1;
-          if (b < p.B) {
-            const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
-            ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
+          for (int fr = 0; fr < NF / 2; ++fr) {
+            const int b = ct * RB + 16 * ((NF / 2) * wc + fr) + (lane & 15);
+            if (b < p.B) {
+              const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
+              *reinterpret_cast<float2*>(&ow[(int64_t)row * p.o_row + 2 * b]) =
+                  make_float2(acc[a][2 * fr][r] * rs * dn, acc[a][2 * fr + 1][r] * rs * dn);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const int n = 2 * ct * RB + 16 * (NF * wc + f) + (lane & 15);
+            const int b = n >> 1;
+            if (b < p.B) {
+              const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
+              ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
+            }
           }
         }
       }
@@ -331,10 +400,12 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
                          int M, int splits, hipStream_t st) {
   constexpr int MF = 4, NF = 4;
   if ((M & 7) || kpad % 16 || kpad < kvalid || kvalid < 1 || rows_alloc % 4 || rows_alloc < nrows || nrows < 1 ||
-      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || shape < 0 || shape > 4)
+      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || shape < 0 || shape > 7 || (o_row & 1) ||
+      (o_slot & 1) || (o_split & 1))
     return hipErrorInvalidValue;
   const int rt = shape == 0 ? 64 : 256;
-  const int ctc = shape == 0 ? 256 : shape == 1 ? 64 : shape == 2 ? 64 : shape == 3 ? 128 : 256;
+  const int sh = shape >= 5 ? shape - 3 : shape;  // shapes 5, 6, 7: shapes 2, 3, 4 on real-column fragments
+  const int ctc = sh == 0 ? 256 : sh == 1 ? 64 : sh == 2 ? 64 : sh == 3 ? 128 : 256;
   TArgs a;
   a.Aq = Aq;
   a.a_slot = a_slot;
@@ -367,12 +438,15 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
 #define S2W_GT(HT_, H_, WR_, WC_) hipLaunchKernelGGL((k_gemm_t<HT_, H_, MF, NF, WR_, WC_>), grid, dim3(256), 0, st, a)
-#define S2W_GT2(HT_, H_, NF_) hipLaunchKernelGGL((k_gemm_t2<HT_, H_, NF_>), grid, dim3(512), 0, st, a)
+#define S2W_GT2(HT_, H_, NF_, RE_) hipLaunchKernelGGL((k_gemm_t2<HT_, H_, NF_, RE_>), grid, dim3(512), 0, st, a)
 #define S2W_GT2_NF(HT_, H_) \
   do {                                                                        \
-    if (shape == 2) S2W_GT2(HT_, H_, 2);                                      \
-    else if (shape == 3) S2W_GT2(HT_, H_, 4);                                 \
-    else S2W_GT2(HT_, H_, 8);                                                 \
+    if (shape == 2) S2W_GT2(HT_, H_, 2, false);                               \
+    else if (shape == 3) S2W_GT2(HT_, H_, 4, false);                          \
+    else if (shape == 4) S2W_GT2(HT_, H_, 8, false);                          \
+    else if (shape == 5) S2W_GT2(HT_, H_, 2, true);                           \
+    else if (shape == 6) S2W_GT2(HT_, H_, 4, true);                           \
+    else S2W_GT2(HT_, H_, 8, true);                                           \
   } while (0)
   if (shape >= 2) {
     if (ht == 1) {
