@@ -49,8 +49,8 @@ KERNEL_SOURCES = {
     "k_gemm_g2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
     "k_gemm_g4": ["s2w_mfma_kernels.hip", "s2w_half.h"],
     "k_gemm_f2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
-    "k_gemm_t2": ["s2w_mfma_adj_kernels.hip", "s2w_half.h"],
-    "k_gemm_fw": ["s2w_mfma_fw_kernels.hip", "s2w_half.h"],
+    "k_gemm_t2": ["s2w_mfma_adj_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
+    "k_gemm_fw": ["s2w_mfma_fw_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
     "k_cgemm32": ["s2w_mfma32_kernels.hip"],
 }
 

@@ -146,8 +146,12 @@ typedef struct s2w_tuning {
   int32_t batch_path_min_b;  /* smallest B that takes the batched matrix-core path */
   int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..18 fixed shapes, 4 = narrow */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
-  int32_t fgemm_lds;         /* batched acoustic GEMM: 1 LDS-staged (bf16: packed activations; f16: eight
-                                waves), 2 eight-wave kernel for both, -1 register kernel */
+  int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (eight-wave kernel on real-column
+                                activation fragments for f16 and for bf16 with B > 64, else the
+                                LDS-staged kernel), 2 eight-wave kernel on full fragments, 3 eight-wave
+                                kernel on real-column fragments (2 and 3 give the same results bit for
+                                bit), 4 LDS-staged kernel on packed bf16 activations (f16: as 3),
+                                -1 register kernel */
   int32_t gemm32_cfg;        /* batched float32 GEMMs over grid rows (forward elastic, adjoint acoustic): tile,
                                 -1 automatic, 1..4 = rows x ruptures 64 x 128, 128 x 32, 256 x 8, 64 x 64 */
   int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint

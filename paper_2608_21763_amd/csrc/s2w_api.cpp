@@ -420,7 +420,7 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) {
-    if (t->fgemm_lds > 2) return fail(p, S2W_EINVAL, "tuning: fgemm_lds");
+    if (t->fgemm_lds > 4) return fail(p, S2W_EINVAL, "tuning: fgemm_lds");
     n.fgemm_lds = t->fgemm_lds > 0 ? t->fgemm_lds : 0;
   }
   if (t->gemm32_cfg) {
@@ -611,13 +611,19 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
   if (cfg < 0) cfg = B <= 64 ? 12 : 18;
-  // acoustic GEMM: fgemm_lds 1 takes the LDS-staged kernel for packed bfloat16 activations
-  // (when its tile fits) and the eight-wave kernel for float16; 2 takes the eight-wave kernel
-  // for both (the mid-chain then leaves complex64); 0 the register kernel
+  // acoustic GEMM: fgemm_lds 2 takes the eight-wave kernel on full activation fragments, 3 the
+  // eight-wave kernel on real-column fragments (with either the mid-chain leaves complex64),
+  // 4 the LDS-staged kernel for packed bfloat16 activations (when its tile fits; float16: as
+  // 3), 0 the register kernel, and 1 chooses: the real-column eight-wave kernel for float16
+  // and for bfloat16 batches that give each wave two column blocks (B > 64; Cascadia-sized
+  // share, bf16: 26.9 against 30.4 ms per call at B = 128, 51.3 against 52.5 ms at B = 256),
+  // the LDS-staged kernel for smaller bfloat16 batches
+  const int fl = p->tune.fgemm_lds;
   const bool bf16_act = h.ht_f == 1 && h.hterms_f == 2;
-  const bool wide = p->tune.fgemm_lds == 2 || (p->tune.fgemm_lds == 1 && !bf16_act);
+  const bool wide = fl == 2 || fl == 3 || ((fl == 1 || fl == 4) && !bf16_act) || (fl == 1 && B > 64);
+  const bool wide_re = wide && fl != 2;
   const bool packed = bf16_act && !wide;
-  const bool fstaged = packed && p->tune.fgemm_lds == 1 && gemm_f2_supported(h.noq, B);
+  const bool fstaged = packed && (fl == 1 || fl == 4) && gemm_f2_supported(h.noq, B);
   const int zt = wide ? ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B)
                       : fstaged ? gemm_f2_col_tiles(B)
                                 : ((ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8);  // column tiles
@@ -663,7 +669,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (wide) {
     splits = std::min(splits, h.ngq / 16);
     e = launch_gemm_fw(h.ht_f, h.hterms_f, (const uint32_t*)Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq,
-                       g.M, h.noq, g.nobs, B, bp, splits, st);
+                       g.M, h.noq, g.nobs, B, bp, splits, wide_re, st);
   } else if (fstaged)
     e = launch_gemm_f2(Fq, (const uint2*)U, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, splits, st);
   else

@@ -95,7 +95,7 @@ inline int gemm_f2_col_tiles(int B) {
 int gemm_fw_nf(int hterms, int B);
 inline int gemm_fw_col_tiles(int hterms, int B) { return (B + 64 * gemm_fw_nf(hterms, B) - 1) / (64 * gemm_fw_nf(hterms, B)); }
 hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* V, const float* up, float* part,
-                          int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, hipStream_t st);
+                          int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, bool re, hipStream_t st);
 // Few-input per-bin products of one BLTT operator (B <= 4), HBM-bound: yh[b][r][l] from the
 // store K[r][l][c] and inputs X[b][l][c] (c padded to an even ncp with zeros).
 hipError_t launch_bltt_gemv(const float2* K, const float2* X, float2* yh, int nrow, int M, int ncp, int B, int ncu,

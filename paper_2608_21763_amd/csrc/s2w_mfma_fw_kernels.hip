@@ -11,6 +11,7 @@
 #include <algorithm>
 
 #include "s2w_half.h"
+#include "s2w_half_re.h"
 #include "s2w_internal.h"
 
 namespace s2w {
@@ -23,12 +24,17 @@ struct FWArgs {
   int ngrid, ngq, noq, nobs, M, B, bp, nks, nrt, nct, splits;
 };
 
-template <int HT, int H, int NF>
-__global__ __launch_bounds__(512) void k_gemm_fw(const FWArgs p) {
+// RE = true (NF even) keeps only the real-column fragments in LDS, one block of 16 ruptures
+// per pair of output column blocks, and forms the imaginary columns in registers (same bits,
+// same products in the same order).
+template <int HT, int H, int NF, bool RE>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RE ? 4 : 1))) void k_gemm_fw(const FWArgs p) {
+  static_assert(!RE || NF % 2 == 0, "real-column fragments pair the column blocks of a wave");
   constexpr int MF = 4, RT = 64, NCB = 8 * NF, RB = 64 * NF;
-  constexpr int XSLOTS = NCB * 64, XREP = (XSLOTS + 511) / 512;
+  constexpr int NBS = RE ? NCB / 2 : NCB;  // fragment blocks held in LDS per step
+  constexpr int XSLOTS = NBS * 64, XREP = (XSLOTS + 511) / 512;
   __shared__ uint4 la_s[2][MF * 64];
-  __shared__ uint4 lb_s[2][NCB * H * 64];
+  __shared__ uint4 lb_s[2][NBS * H * 64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
   const int per_slot = p.nrt * p.nct * p.splits;
@@ -53,7 +59,8 @@ __global__ __launch_bounds__(512) void k_gemm_fw(const FWArgs p) {
     const int s = min(tid + 512 * rp, XSLOTS - 1);
     const int L = s & 63;
     xkg[rp] = L >> 4;
-    bx[rp] = min(ct * RB + 8 * (s >> 6) + ((L & 15) >> 1), p.bp - 1);
+    bx[rp] = RE ? min(ct * RB + 16 * (s >> 6) + (L & 15), p.bp - 1)
+                : min(ct * RB + 8 * (s >> 6) + ((L & 15) >> 1), p.bp - 1);
     upx[rp] = p.up ? p.up[(int64_t)l * p.bp + bx[rp]] : 1.f;
   }
   const float2* Vl = p.V + (int64_t)l * p.bp;
@@ -69,6 +76,7 @@ __global__ __launch_bounds__(512) void k_gemm_fw(const FWArgs p) {
     if (aown) ast = *reinterpret_cast<const uint4*>(Arow + 16 * ks);
 #pragma unroll
     for (int rp = 0; rp < XREP; ++rp)
+      if (XSLOTS % 512 == 0 || tid + 512 * rp < XSLOTS)  // whole waves without a granule skip the loads
 #pragma unroll
       for (int e2 = 0; e2 < 4; ++e2) {
         const int g = 16 * ks + 4 * xkg[rp] + e2;
@@ -81,9 +89,14 @@ __global__ __launch_bounds__(512) void k_gemm_fw(const FWArgs p) {
 #pragma unroll
     for (int rp = 0; rp < XREP; ++rp) {
       const int s = tid + 512 * rp;
-      if (s < XSLOTS) t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, &lb_s[buf][(s >> 6) * H * 64 + (s & 63)]);
+      if (s < XSLOTS) {
+        uint4* dst = &lb_s[buf][(s >> 6) * H * 64 + (s & 63)];
+        if (RE) t2_convert_re<HT, H>(xv[rp], upx[rp], dc, dst);
+        else t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, dst);
+      }
     }
   };
+  const uint32_t mre = dc ? 0x0000ffffu : 0xffffffffu;  // RE: real column of a stored word
   if (ks0 < ks1) {
     fetch(ks0);
     stage(0);
@@ -95,16 +108,34 @@ __global__ __launch_bounds__(512) void k_gemm_fw(const FWArgs p) {
       uint4 av[MF];
 #pragma unroll
       for (int a = 0; a < MF; ++a) av[a] = la_s[cur][a * 64 + lane];
+      if (RE) {
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const int cb = NF * wave + f;
-        const uint4 bh = lb_s[cur][cb * H * 64 + lane];
+        for (int fr = 0; fr < NF / 2; ++fr) {
+          const int cb = (NF / 2) * wave + fr;
 #pragma unroll
-        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
-        if (H == 2) {
-          const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
+          for (int t = 0; t < H; ++t) {
+            const uint4 w = lb_s[cur][cb * H * 64 + 64 * t + lane];
+            const uint4 br = make_uint4(w.x & mre, w.y & mre, w.z & mre, w.w & mre);
+            const uint4 bi = make_uint4(t2_im_word(w.x, dc), t2_im_word(w.y, dc), t2_im_word(w.z, dc),
+                                        t2_im_word(w.w, dc));
 #pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr] = mfma16<HT>(av[a], br, acc[a][2 * fr]);
+#pragma unroll
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr + 1] = mfma16<HT>(av[a], bi, acc[a][2 * fr + 1]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int cb = NF * wave + f;
+          const uint4 bh = lb_s[cur][cb * H * 64 + lane];
+#pragma unroll
+          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
+          if (H == 2) {
+            const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
+#pragma unroll
+            for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+          }
         }
       }
       if (more) stage(cur ^ 1);
@@ -118,10 +149,20 @@ __global__ __launch_bounds__(512) void k_gemm_fw(const FWArgs p) {
     for (int r = 0; r < 4; ++r) {
       const int o = row0 + 16 * a + 4 * (lane >> 4) + r;
       if (o < p.nobs) {
+        if (RE) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const int n = 2 * ct * RB + 16 * (NF * wave + f) + (lane & 15);
-          if ((n >> 1) < p.B) ow[(int64_t)o * (2 * p.bp) + n] = acc[a][f][r];
+          for (int fr = 0; fr < NF / 2; ++fr) {
+            const int b = ct * RB + 16 * ((NF / 2) * wave + fr) + (lane & 15);
+            if (b < p.B)
+              *reinterpret_cast<float2*>(&ow[(int64_t)o * (2 * p.bp) + 2 * b]) =
+                  make_float2(acc[a][2 * fr][r], acc[a][2 * fr + 1][r]);
+          }
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) {
+            const int n = 2 * ct * RB + 16 * (NF * wave + f) + (lane & 15);
+            if ((n >> 1) < p.B) ow[(int64_t)o * (2 * p.bp) + n] = acc[a][f][r];
+          }
         }
       }
     }
@@ -134,8 +175,10 @@ int gemm_fw_nf(int hterms, int B) {
 }
 
 hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* V, const float* up, float* part,
-                          int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, hipStream_t st) {
+                          int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, bool re,
+                          hipStream_t st) {
   const int nf = gemm_fw_nf(hterms, B);
+  re = re && nf >= 2;  // one column block per wave has no pair to share fragments
   if ((M & 7) || ngq % 16 || ngq < ngrid || noq % 16 || nobs > noq || B < 1 || B > bp || splits < 1)
     return hipErrorInvalidValue;
   FWArgs a;
@@ -157,7 +200,14 @@ hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* 
   const int64_t blocks = (int64_t)M * a.nrt * a.nct * a.splits;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
-#define S2W_FW(HT_, H_, NF_) hipLaunchKernelGGL((k_gemm_fw<HT_, H_, NF_>), grid, dim3(512), 0, st, a)
+#define S2W_FW1(HT_, H_, NF_, RE_) hipLaunchKernelGGL((k_gemm_fw<HT_, H_, NF_, RE_>), grid, dim3(512), 0, st, a)
+#define S2W_FW(HT_, H_, NF_)             \
+  do {                                   \
+    if (NF_ > 1 && re)                   \
+      S2W_FW1(HT_, H_, NF_, (NF_ > 1)); \
+    else                                 \
+      S2W_FW1(HT_, H_, NF_, false);      \
+  } while (0)
   if (ht == 1) {
     if (hterms == 2) {
       if (nf == 1) S2W_FW(1, 2, 1); else S2W_FW(1, 2, 2);
@@ -172,6 +222,7 @@ hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* 
     }
   }
 #undef S2W_FW
+#undef S2W_FW1
   return hipGetLastError();
 }
 

@@ -203,7 +203,7 @@ def test_acoustic_gemm_kernels_agree(B, nobs):
     log_case("half_acoustic", B=B, nobs=nobs)
     op = make_operator(cfg, max_batch=B, g_dtype="bf16", f_dtype="bf16")
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
-    op.set_tuning(fgemm_lds=1)
+    op.set_tuning(fgemm_lds=4)
     y1 = op.forward(s).clone()
     op.set_tuning(fgemm_lds=-1)
     y2 = op.forward(s).clone()
@@ -215,10 +215,11 @@ def test_acoustic_gemm_kernels_agree(B, nobs):
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
-@pytest.mark.parametrize("B,nobs", [(1, 5), (40, 20), (100, 70), (257, 50)])
+@pytest.mark.parametrize("B,nobs", [(1, 5), (40, 20), (100, 70), (200, 20), (257, 50)])
 def test_acoustic_kernel_choices(dtype, B, nobs):
     # the three acoustic GEMMs (LDS-staged, eight-wave, register) against the oracle; the
-    # eight-wave kernel covers one to four column tiles and observers beyond one 64-row tile
+    # eight-wave kernel covers one to four column tiles and observers beyond one 64-row tile,
+    # and gives the same bits on full (2) and real-column (3) activation fragments
     cfg = synth.SynthConfig(nsub=30, ngrid=333, nobs=nobs, nt=40, seed=107, slip_seed=108, op_kind="dense",
                             slip_mode="dense")
     log_case("half_acoustic_choices", dtype=dtype, B=B, nobs=nobs)
@@ -226,9 +227,18 @@ def test_acoustic_kernel_choices(dtype, B, nobs):
     s = synth.gen_slip_batch(cfg, 0, B)
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
     ref = oracle.forward(G, F, s)
-    for sel in (1, 2, -1):
+    ys = {}
+    for sel in (1, 2, 3, 4, -1):
         op.set_tuning(fgemm_lds=sel)
         y = op.forward(to_dev(s)).cpu().numpy()
+        ys[sel] = y
         errs = oracle.rel_l2_per_rupture(y, ref)
         print(dtype, "fgemm_lds", sel, "rel-L2 max", errs.max())
         assert np.all(np.isfinite(y)) and errs.max() <= BOUND[(dtype, dtype)]
+    assert np.array_equal(ys[2], ys[3])
+    if dtype == "f16" or B > 64:  # the automatic choice is the real-column eight-wave kernel
+        assert np.array_equal(ys[1], ys[3])
+    else:  # the LDS-staged kernel
+        assert np.array_equal(ys[1], ys[4])
+    if dtype == "f16":
+        assert np.array_equal(ys[4], ys[3])
