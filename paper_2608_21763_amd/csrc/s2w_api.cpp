@@ -624,7 +624,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const bool wide_re = wide && fl != 2;
   const bool packed = bf16_act && !wide;
   const bool fstaged = packed && (fl == 1 || fl == 4) && gemm_f2_supported(h.noq, B);
-  const int zt = wide ? ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B)
+  const int zt = wide ? ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B, wide_re)
                       : fstaged ? gemm_f2_col_tiles(B)
                                 : ((ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8);  // column tiles
   int splits = p->tune.fgemm_splits;

@@ -92,8 +92,10 @@ inline int gemm_f2_col_tiles(int B) {
 // Acoustic GEMM with eight waves across the output columns, both operands staged in LDS:
 // part[split][l][o][n] (o < nobs, n < 2B) from complex64 V[g][l][b] (scaled by up[l][b] when
 // given, converted to hterms half terms).  Splits: grid-row ranges (clamped to the K steps).
-int gemm_fw_nf(int hterms, int B);
-inline int gemm_fw_col_tiles(int hterms, int B) { return (B + 64 * gemm_fw_nf(hterms, B) - 1) / (64 * gemm_fw_nf(hterms, B)); }
+int gemm_fw_nf(int hterms, int B, bool re);
+inline int gemm_fw_col_tiles(int hterms, int B, bool re) {
+  return (B + 64 * gemm_fw_nf(hterms, B, re) - 1) / (64 * gemm_fw_nf(hterms, B, re));
+}
 hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* V, const float* up, float* part,
                           int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, bool re, hipStream_t st);
 // Few-input per-bin products of one BLTT operator (B <= 4), HBM-bound: yh[b][r][l] from the

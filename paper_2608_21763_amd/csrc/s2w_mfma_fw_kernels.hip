@@ -168,16 +168,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RE ? 4 : 1)
     }
 }
 
-int gemm_fw_nf(int hterms, int B) {
+int gemm_fw_nf(int hterms, int B, bool re) {
   if (B <= 64) return 1;
-  if (B <= 128 || hterms == 2) return 2;
+  if (B <= 128 || (hterms == 2 && !re)) return 2;
   return 4;
 }
 
 hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* V, const float* up, float* part,
                           int ngrid, int ngq, int M, int noq, int nobs, int B, int bp, int splits, bool re,
                           hipStream_t st) {
-  const int nf = gemm_fw_nf(hterms, B);
+  const int nf = gemm_fw_nf(hterms, B, re);
   re = re && nf >= 2;  // one column block per wave has no pair to share fragments
   if ((M & 7) || ngq % 16 || ngq < ngrid || noq % 16 || nobs > noq || B < 1 || B > bp || splits < 1)
     return hipErrorInvalidValue;
@@ -210,13 +210,13 @@ hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* 
   } while (0)
   if (ht == 1) {
     if (hterms == 2) {
-      if (nf == 1) S2W_FW(1, 2, 1); else S2W_FW(1, 2, 2);
+      if (nf == 1) S2W_FW(1, 2, 1); else if (nf == 2) S2W_FW(1, 2, 2); else S2W_FW1(1, 2, 4, true);
     } else {
       if (nf == 1) S2W_FW(1, 1, 1); else if (nf == 2) S2W_FW(1, 1, 2); else S2W_FW(1, 1, 4);
     }
   } else {
     if (hterms == 2) {
-      if (nf == 1) S2W_FW(2, 2, 1); else S2W_FW(2, 2, 2);
+      if (nf == 1) S2W_FW(2, 2, 1); else if (nf == 2) S2W_FW(2, 2, 2); else S2W_FW1(2, 2, 4, true);
     } else {
       if (nf == 1) S2W_FW(2, 1, 1); else if (nf == 2) S2W_FW(2, 1, 2); else S2W_FW(2, 1, 4);
     }
