@@ -194,13 +194,37 @@ def adjoint_synth(cfg, r, cols=None, dt: float | None = None, diff: int = DIFF_B
 
 
 def rel_l2(y, yref) -> float:
-    """||y - yref||_2 / ||yref||_2 accumulated in float64."""
+    """||y - yref||_2 / ||yref||_2 over every entry, accumulated in float64.
+
+    The denominator is the reference's norm, never the tested result's.  When the
+    reference is identically zero there is nothing to be relative to: the value
+    returned is then the absolute norm ||y||_2, and a caller bounds it with an
+    absolute bound of its own.
+    """
     y, yref = _d(y), _d(yref)
     den = np.sqrt(np.sum(yref * yref))
     return float(np.sqrt(np.sum((y - yref) ** 2)) / den) if den > 0 else float(np.sqrt(np.sum(y * y)))
 
 
 def rel_l2_per_rupture(y, yref) -> np.ndarray:
-    """rel-L2 of each rupture (leading axis) over its (o, n) entries."""
+    """rel-L2 of each rupture (leading axis) over its own (o, n) entries."""
     y, yref = _d(y), _d(yref)
     return np.array([rel_l2(y[b], yref[b]) for b in range(y.shape[0])])
+
+
+def max_abs_rel(y, yref) -> float:
+    """Element-wise error max |y - yref| / max |yref|, in float64.
+
+    Unlike rel-L2, one wrong sample cannot hide in a large norm: it shows at its
+    full size.  A zero reference gives the absolute max |y|, as in rel_l2.
+    """
+    y, yref = _d(y), _d(yref)
+    den = float(np.max(np.abs(yref))) if yref.size else 0.0
+    num = float(np.max(np.abs(y - yref))) if y.size else 0.0
+    return num / den if den > 0 else (float(np.max(np.abs(y))) if y.size else 0.0)
+
+
+def max_abs_rel_per_rupture(y, yref) -> np.ndarray:
+    """max_abs_rel of each rupture (leading axis) over its own (o, n) entries."""
+    y, yref = _d(y), _d(yref)
+    return np.array([max_abs_rel(y[b], yref[b]) for b in range(y.shape[0])])

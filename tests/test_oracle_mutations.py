@@ -1,13 +1,16 @@
-"""Plant plausible mistakes in a private copy of the oracle's C source and check the pins catch each.
+"""Plant plausible mistakes in private copies of the oracle and check the pins catch each.
 
-Every mutant is compiled on the CPU into a temporary library; the pins used
-here are the brute-force dense-matrix checks (explicit BLTT block matrices)
-and the dot-product identity.  A mutant that survives would mean the pins
-cannot tell that mistake from the paper's definition.
+Mistakes in the C source are compiled on the CPU into a temporary library and
+checked by the brute-force dense-matrix pins (explicit BLTT block matrices) and
+the dot-product identity.  Mistakes in the comparison helpers (rel-L2 and the
+element-wise error, on which every parity bound rests) are planted in a copy of
+the Python module and checked by the helper pins.  A mutant that survives would
+mean the pins cannot tell that mistake from the definition.
 """
 import ctypes
 import os
 import subprocess
+import types
 
 import numpy as np
 import pytest
@@ -16,6 +19,7 @@ from bltt_dense import chain_matrix, to_time_major, from_time_major
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "s2w_oracle.c")
+PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
 
 MUTANTS = {
     "eq1_dropped_last_lag": ("for (int64_t n = k; n < nt; n++) m[n] += gv * sj[n - k];",
@@ -86,3 +90,43 @@ def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     L = _build(tmp_path, name, old, new)
     assert not _pins_hold(L), f"planted mistake '{name}' survived the pins"
+
+
+# planted mistakes in the comparison helpers of the Python module
+HELPER_MUTANTS = {
+    "rel_l2_squared_ratio": ("return float(np.sqrt(np.sum((y - yref) ** 2)) / den) if den > 0",
+                             "return float(np.sum((y - yref) ** 2) / den ** 2) if den > 0"),
+    "rel_l2_result_denominator": ("den = np.sqrt(np.sum(yref * yref))",
+                                  "den = np.sqrt(np.sum(y * y))"),
+    "rel_l2_sum_denominator": ("den = np.sqrt(np.sum(yref * yref))",
+                               "den = np.sqrt(np.sum(yref * yref) + np.sum(y * y))"),
+    "rel_l2_zero_reference_passes": ("else float(np.sqrt(np.sum(y * y)))", "else 0.0"),
+    "rel_l2_no_square_root": ("return float(np.sqrt(np.sum((y - yref) ** 2)) / den) if den > 0",
+                              "return float(np.sum(np.abs(y - yref)) / den) if den > 0"),
+    "per_rupture_pooled": ("np.array([rel_l2(y[b], yref[b]) for b in range(y.shape[0])])",
+                           "np.array([rel_l2(y, yref) for b in range(y.shape[0])])"),
+    "max_abs_mean_not_max": ("num = float(np.max(np.abs(y - yref))) if y.size else 0.0",
+                             "num = float(np.mean(np.abs(y - yref))) if y.size else 0.0"),
+    "max_abs_result_denominator": ("den = float(np.max(np.abs(yref))) if yref.size else 0.0",
+                                   "den = float(np.max(np.abs(y))) if yref.size else 0.0"),
+}
+
+
+def _helper_module(name, old, new):
+    src = open(PY_SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not unique in the oracle module"
+    ns = {"__name__": f"oracle_mutant_{name}", "__file__": PY_SRC}
+    exec(compile(src.replace(old, new), f"<{name}>", "exec"), ns)
+    return types.SimpleNamespace(**ns)
+
+
+def test_unmutated_helpers_pass():
+    from metric_pins import failures
+    assert failures(_helper_module("clean", "import ctypes", "import ctypes")) == []
+
+
+@pytest.mark.parametrize("name", sorted(HELPER_MUTANTS))
+def test_helper_mutant_is_caught(name):
+    from metric_pins import failures
+    old, new = HELPER_MUTANTS[name]
+    assert failures(_helper_module(name, old, new)), f"planted mistake '{name}' survived the helper pins"
