@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define S2W_ABI_VERSION 3
+#define S2W_ABI_VERSION 4
 
 typedef struct s2w_plan s2w_plan;
 
@@ -136,6 +136,27 @@ s2w_status s2w_forward(s2w_plan* plan, const float* s, int32_t B, float* y, void
  * the forward map (a high and a low bfloat16 term, or one scaled float16 term), so the
  * adjoint's error is of the forward map's order. */
 s2w_status s2w_adjoint(s2w_plan* plan, const float* r, int32_t B, float* gs, void* stream);
+
+/* Forward map without the bound workspace, for callers that cannot allocate device memory
+ * or call into an allocator at all (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and validation as s2w_forward,
+ * bit for bit; the operator store must still be bound and set.  Its scratch (the source
+ * spectrum, the per-workgroup partial spectra of the fused kernel and their sum) lives in a
+ * fixed device array of S2W_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on until the process ends; no call allocates or frees anything.
+ * Limits: single-layout (float32) plans whose fused kernel fits the array, i.e.
+ * (M*nsp + nwg*M*nop + nop*M) * 8 bytes, each term rounded up to 256, is at most
+ * S2W_NOALLOC_SCRATCH_BYTES, with M = L/2 slots, nsp / nop = nsub / nobs rounded up to even,
+ * nwg = compute units x fused_wg_per_cu (the Cascadia-sized share, 963 x 37,760 x 64 x 256
+ * at one workgroup per CU, needs 35.6 MB); larger plans, batched or half-precision plans and
+ * plans whose observers need the unfused kernel get S2W_EUNSUPPORTED with the byte count in
+ * s2w_last_error, before anything is enqueued.
+ * Concurrency: every call on one GPU shares that GPU's array, so calls that overlap on one
+ * GPU (two streams, or two plans, at once) race and corrupt each other's results; serialize
+ * them.  Nothing in the array needs clearing between calls: each call writes every byte it
+ * reads before reading it. */
+#define S2W_NOALLOC_SCRATCH_BYTES (64u << 20)
+s2w_status s2w_forward_noalloc(s2w_plan* plan, const float* s, int32_t B, float* y, void* stream);
 
 /* Kernel-shape controls for the tuner.  Zero fields keep the library default. */
 typedef struct s2w_tuning {

@@ -50,7 +50,7 @@ EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_c
            "s2w_query_sizes", "s2w_bind_memory", "s2w_set_operators", "s2w_forward", "s2w_adjoint",
            "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events", "s2w_plan_layout",
            "s2w_bltt_create", "s2w_bltt_destroy", "s2w_bltt_query_sizes", "s2w_bltt_bind_memory",
-           "s2w_bltt_set_blocks", "s2w_bltt_apply", "s2w_bltt_adjoint", "s2w_bltt_last_error"]
+           "s2w_bltt_set_blocks", "s2w_bltt_apply", "s2w_bltt_adjoint", "s2w_bltt_last_error", "s2w_forward_noalloc"]
 
 _lib = None
 
@@ -78,6 +78,7 @@ def load_library(path: str | None = None):
     lib.s2w_set_operators.argtypes = [plan_p, vp, vp, i64, i64, vp]
     lib.s2w_forward.argtypes = [plan_p, vp, i32, vp, vp]
     lib.s2w_adjoint.argtypes = [plan_p, vp, i32, vp, vp]
+    lib.s2w_forward_noalloc.argtypes = [plan_p, vp, i32, vp, vp]
     lib.s2w_set_tuning.argtypes = [plan_p, P(Tuning)]
     lib.s2w_get_tuning.argtypes = [plan_p, P(Tuning)]
     lib.s2w_transform_length.argtypes = [plan_p, P(i32)]
@@ -156,6 +157,9 @@ class Plan:
 
     def adjoint(self, r_ptr: int, B: int, gs_ptr: int, stream: int = 0):
         self._check(self.lib.s2w_adjoint(self.handle, r_ptr, B, gs_ptr, stream), "s2w_adjoint")
+
+    def forward_noalloc(self, s_ptr: int, B: int, y_ptr: int, stream: int = 0):
+        self._check(self.lib.s2w_forward_noalloc(self.handle, s_ptr, B, y_ptr, stream), "s2w_forward_noalloc")
 
     def set_profile_events(self, begin: int = 0, end: int = 0):
         """hipEvent_t handles (ints) recorded around the dominant kernel of later calls; 0, 0 stops."""

@@ -50,6 +50,7 @@ struct Layout {
   uint64_t ws_total;
 };
 
+
 // Extra geometry of the batched float32 path.
 struct BatchGeo32 {
   bool on = false;
@@ -121,6 +122,41 @@ hipError_t ensure_twiddles(int device) {
   hipError_t e = upload_twiddles(device);
   if (e == hipSuccess) g_tw_done[device] = 1;
   return e;
+}
+
+// Fixed device scratch of s2w_forward_noalloc, for callers that cannot allocate.  Each GPU
+// the library runs on holds its own copy until the process ends.  In host code the array's
+// name is only a stand-in: its device address, per device, comes from hipGetSymbolAddress
+// at plan creation and is the only handle host code passes on.
+static __device__ __align__(256) unsigned char scratch[S2W_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mutex;
+std::vector<void*> g_scratch_ptr;       // per device; nullptr until looked up
+std::vector<hipError_t> g_scratch_err;  // per device: result of the lookup
+
+// With `device` current: look up this device's copy of the scratch array (once).
+void ensure_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if ((int)g_scratch_ptr.size() <= device) {
+    g_scratch_ptr.resize(device + 1, nullptr);
+    g_scratch_err.resize(device + 1, hipErrorNotReady);
+  }
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  if (e == hipSuccess && ptr && ((uintptr_t)ptr % kAlign) == 0) g_scratch_ptr[device] = ptr;
+}
+
+// This device's scratch address, or nullptr with the lookup's error in *err.
+void* scratch_ptr(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (device < 0 || device >= (int)g_scratch_ptr.size()) {
+    *err = hipErrorNotReady;
+    return nullptr;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
 }
 
 // Scoped switch to the plan's device.
@@ -335,6 +371,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
       delete p;
       return S2W_EHIP;
     }
+    ensure_scratch(device);  // a failed lookup only disables s2w_forward_noalloc, which reports it
   }
   *out = p;
   return S2W_OK;
@@ -852,22 +889,69 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   return S2W_OK;
 }
 
+static s2w_status forward_single(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st, float2* Sh,
+                                 float2* part, float2* yh, float2* Vh);
+
 s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
   s2w_status cs = check_call(p, s, B, y, "forward");
   if (cs != S2W_OK || B == 0) return cs;
-  const Geometry& g = p->geo;
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "forward: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
   if (p->hg.on) return forward_half(p, s, B, y, st);
   if (p->fb.on) return forward_b32(p, s, B, y, st);
+  return forward_single(p, s, B, y, st, (float2*)(p->ws + p->lay.sh), (float2*)(p->ws + p->lay.part),
+                        (float2*)(p->ws + p->lay.yh), (float2*)(p->ws + p->lay.wp));
+}
+
+// Bytes of scratch the single-layout forward needs for its source spectrum, the fused
+// kernel's per-workgroup partial spectra and their sum (the fused kernel only).
+static uint64_t single_fused_scratch(const s2w_plan* p, uint64_t* o_part, uint64_t* o_yh) {
+  const Geometry& g = p->geo;
+  const uint64_t c8 = sizeof(float2);
+  const uint64_t nwg = (uint64_t)p->ncu * p->tune.fused_wg_per_cu;
+  uint64_t off = round_up((uint64_t)g.M * g.nsp * c8, kAlign);
+  *o_part = off;
+  off = round_up(off + nwg * g.M * g.nop * c8, kAlign);
+  *o_yh = off;
+  return round_up(off + (uint64_t)g.nop * g.M * c8, kAlign);
+}
+
+s2w_status s2w_forward_noalloc(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
+  s2w_status cs = check_call(p, s, B, y, "forward_noalloc");
+  if (cs != S2W_OK || B == 0) return cs;
+  if (p->hg.on || p->fb.on)
+    return fail(p, S2W_EUNSUPPORTED, "forward_noalloc: only plans with the single (float32) layout");
+  if (fused_forward_opt(p->geo) > 32)
+    return fail(p, S2W_EUNSUPPORTED, "forward_noalloc: %d observers at L = %d need the unfused path", p->geo.nobs,
+                p->geo.L);
+  uint64_t o_part = 0, o_yh = 0;
+  const uint64_t need = single_fused_scratch(p, &o_part, &o_yh);
+  if (need > (uint64_t)S2W_NOALLOC_SCRATCH_BYTES)
+    return fail(p, S2W_EUNSUPPORTED,
+                "forward_noalloc: needs %llu bytes of scratch (%d workgroups x %d observers x %d slots), the fixed "
+                "array holds %llu",
+                (unsigned long long)need, p->ncu * p->tune.fused_wg_per_cu, p->geo.nop, p->geo.M,
+                (unsigned long long)S2W_NOALLOC_SCRATCH_BYTES);
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(p, S2W_EHIP, "forward_noalloc: cannot select device %d", p->device);
+  hipError_t se = hipSuccess;
+  char* base = (char*)scratch_ptr(p->device, &se);
+  if (!base) return hip_fail(p, se == hipSuccess ? hipErrorInvalidSymbol : se, "forward_noalloc: scratch lookup");
+  return forward_single(p, s, B, y, (hipStream_t)stream, (float2*)base, (float2*)(base + o_part),
+                        (float2*)(base + o_yh), nullptr);
+}
+
+// Single-layout forward: B passes of the fused (or, for many observers, the unfused) kernel,
+// with the source spectrum in Sh, the partial spectra in part and their sum in yh; Vh holds
+// the unfused path's seafloor spectra.
+static s2w_status forward_single(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st, float2* Sh,
+                                 float2* part, float2* yh, float2* Vh) {
+  const Geometry& g = p->geo;
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
-  float2* Sh = (float2*)(p->ws + p->lay.sh);
-  float2* part = (float2*)(p->ws + p->lay.part);
-  float2* yh = (float2*)(p->ws + p->lay.yh);
-  float2* Vh = (float2*)(p->ws + p->lay.wp);
   const bool fused = fused_forward_opt(g) <= 32;
+  if (!fused && !Vh) return fail(p, S2W_EUNSUPPORTED, "forward: the unfused path needs the bound workspace");
   const int nwg = p->ncu * p->tune.fused_wg_per_cu;
   const float inv_l = 1.0f / (float)g.L;
   for (int b = 0; b < B; ++b) {
