@@ -11,6 +11,8 @@ slip histories are already resident in HBM.  Paths timed:
   fp32b   B ruptures per call, complex64 spectra, float32 matrix-core GEMMs
   half    B ruptures per call on the batched matrix-core path with bf16 spectra (headline)
   half16  the same with f16 spectra (single-term activations)
+  direct  single rupture per call evaluated in the time domain without FFT (eq. 4 form), float32
+          matrix cores: the paper's direct reference, timed beside the FFT path
   adj     the batched float32 adjoint (gradient of a waveform misfit), B = 64
   bltt    the elastic operator alone (seafloor displacement), one rupture
   strong / weak  the single-rupture path on the paper's strong- and weak-scaling shares
@@ -52,6 +54,7 @@ KERNEL_SOURCES = {
     "k_gemm_t2": ["s2w_mfma_adj_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
     "k_gemm_fw": ["s2w_mfma_fw_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
     "k_cgemm32": ["s2w_mfma32_kernels.hip"],
+    "k_direct": ["s2w_direct_kernels.hip"],
 }
 
 
@@ -161,13 +164,15 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,fp32b,half,half16,adj,hadj,bltt,strong,weak",
+    ap.add_argument("--paths", default="fp32,direct,fp32b,half,half16,adj,hadj,bltt,strong,weak",
                     help="fp32 (single rupture), fp32b (batched float32), half (batched half precision, --half-dtype), "
                          "half16 (batched float16 stores), adj (batched float32 adjoint), hadj (batched bfloat16 adjoint, "
                          "--batch residuals), "
+                         "direct (time-domain evaluation of eq. 4 on the float32 matrix cores, single rupture), "
                          "bltt (elastic operator alone: seafloor displacement), strong / weak (the float32 "
                          "single-rupture path on the strong- and weak-scaling per-GPU shares)")
     ap.add_argument("--batch32", type=int, default=256, help="ruptures per call on the batched float32 path")
+    ap.add_argument("--direct-steps", type=int, default=16, help="timed single-rupture calls of the direct path")
     ap.add_argument("--batch-adj", type=int, default=64, help="residuals per call on the batched float32 adjoint")
     ap.add_argument("--half-dtype", default="bf16", help="bf16, f16 or G/F pair such as bf16/f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -256,6 +261,7 @@ def main():
             y_ref = oracle.forward_synth(cfg, s_host[:nc])
             cpu_s = time.perf_counter() - t
             errs = [oracle.rel_l2(y_gpu[b], y_ref[b]) for b in range(nc)]
+            fp32["y_ref0"] = y_ref[0]
             fp32["rel_l2"] = max(errs)
             fp32["rel_l2_sampled"] = {str(b): e for b, e in enumerate(errs)}
             result["cpu_baseline"] = {
@@ -265,6 +271,42 @@ def main():
             log(f"oracle: {cpu_s / nc:.1f} s/rupture, fp32 rel-L2 " + " ".join(f"{e:.2e}" for e in errs))
         del op
         torch.cuda.empty_cache()
+
+    # ---------------- direct time-domain evaluation (eq. 4 form, no FFT), single rupture ----------------
+    if "direct" in paths:
+        op = S2WOperator(cfg.nsub, cfg.ngrid, cfg.nobs, cfg.nt, max_batch=1, dt=cfg.dt, device=0, layout="direct")
+        t = time.perf_counter()
+        op.load_operators(*host_generators(cfg), chunk_rows=1024)
+        setup_s = time.perf_counter() - t
+        nrup = max(args.direct_steps, args.warmup, 1)
+        s_host = synth.gen_slip_batch(cfg, 0, nrup)
+        s_dev = torch.tensor(s_host, device=dev).reshape(nrup, 1, cfg.nsub, cfg.nt)
+        total_ms, kern_ms, wall = time_path(op, s_dev, args.direct_steps, args.warmup, 1)
+        ms_step = total_ms / args.direct_steps
+        kmean = float(np.mean(kern_ms))
+        # lag products of the elastic sum: Ngrid x Nsub pairs, Nt (Nt + 1) / 2 products each, 2 flops
+        flops_g = 2.0 * cfg.ngrid * cfg.nsub * cfg.nt * (cfg.nt + 1) / 2
+        flops_all = flops_g * (cfg.nsub + cfg.nobs) / cfg.nsub
+        dres = {"ruptures_per_s": 1000.0 / ms_step, "ms_per_step": ms_step, "B": 1, "kernel": "k_direct<2>",
+                "kernel_ms": kmean, "algorithmic_flops_elastic": flops_g, "algorithmic_flops": flops_all,
+                "achieved_TFLOPs": flops_g / (kmean * 1e9),
+                "mfma_frac": flops_g / (kmean * 1e9) / MFMA_PEAK["f32"],
+                "whole_call_TFLOPs": flops_all / (ms_step * 1e9), "setup_s": setup_s}
+        log(f"direct B=1: {ms_step:.3f} ms/rupture, elastic product {kmean:.3f} ms = "
+            f"{dres['achieved_TFLOPs']:.1f} TFLOP/s ({100 * dres['mfma_frac']:.1f} % of fp32 matrix peak)")
+        if not args.no_cpu_baseline and "fp32" in result and "y_ref0" in result["fp32"]:
+            import oracle
+            y0 = op.forward(s_dev[0, 0]).cpu().numpy().astype(np.float64)
+            dres["rel_l2_sampled"] = {"0": oracle.rel_l2(y0, result["fp32"]["y_ref0"])}
+            log(f"direct rel-L2 on rupture 0: {dres['rel_l2_sampled']['0']:.2e}")
+        if "fp32" in result:
+            dres["fft_speedup_vs_direct"] = ms_step / result["fp32"]["ms_per_step"]
+            log(f"FFT path / direct: {dres['fft_speedup_vs_direct']:.2f}x faster per rupture")
+        result["direct"] = dres
+        del op
+        torch.cuda.empty_cache()
+    if "fp32" in result:
+        result["fp32"].pop("y_ref0", None)
 
     bcfg = synth.workload("cascadia_batch")
     if args.ngrid:
@@ -526,6 +568,8 @@ def main():
         "rel_l2": head.get("rel_l2"),
         "speedup_vs_fp32": (half["ruptures_per_s"] / fp32["ruptures_per_s"]) if (half and fp32) else None,
         "speedup_fp32_batched_vs_fp32": (fp32b["ruptures_per_s"] / fp32["ruptures_per_s"]) if (fp32b and fp32) else None,
+        "direct_ms_per_rupture": result["direct"]["ms_per_step"] if "direct" in result else None,
+        "fft_speedup_vs_direct": result["direct"].get("fft_speedup_vs_direct") if "direct" in result else None,
         "paths": {k: v for k, v in result.items() if k != "cpu_baseline"},
         "source_hash": src_hash,
     }

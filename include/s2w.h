@@ -71,8 +71,21 @@ typedef enum s2w_diff { S2W_DIFF_NONE = 0, S2W_DIFF_BACKWARD = 1 } s2w_diff;
  *  BATCHED  per-bin operator matrices (grid row, bin, column) for matrix-core GEMMs over all
  *           B ruptures of a call; the seafloor field of the batch goes through the workspace.
  *           The only layout of the half-precision stores.
+ *  DIRECT   float32 only, no FFT: the time-domain blocks are stored as given (each series
+ *           padded with zero lags to a multiple of 16) and forward/adjoint evaluate the
+ *           defining sums of eqs. (1)-(2) in the channel form of eq. (4), the paper's direct
+ *           reference evaluation (Sec. II-C2), on the float32 matrix cores: Nt(Nt+1)/2 lag
+ *           products per (row, column) pair instead of one complex product per bin, so about
+ *           2*Nt/(log2 L) times the FFT path's arithmetic.  The seafloor field is differenced
+ *           in the time domain between the two products; B ruptures run as B passes.
+ *           Operator store: (Nsub + Nobs) * Ngrid * ntp * 4 bytes, ntp = Nt rounded up to 16.
  *  AUTO     BATCHED for half-precision stores or max_batch >= 8, else SINGLE. */
-typedef enum s2w_layout { S2W_LAYOUT_AUTO = 0, S2W_LAYOUT_SINGLE = 1, S2W_LAYOUT_BATCHED = 2 } s2w_layout;
+typedef enum s2w_layout {
+  S2W_LAYOUT_AUTO = 0,
+  S2W_LAYOUT_SINGLE = 1,
+  S2W_LAYOUT_BATCHED = 2,
+  S2W_LAYOUT_DIRECT = 3
+} s2w_layout;
 
 /* Problem description.  Limits of this build: 1 <= nt <= 512, 1 <= nsub <= 1024,
  * 1 <= nobs <= 256, 1 <= ngrid, 0 <= max_batch <= 1024. */
@@ -125,6 +138,23 @@ s2w_status s2w_set_operators(s2w_plan* plan, const float* G_chunk, const float* 
  *   y[b][o][n]  this share's partial waveforms F_q^(r) D_t F_G^(r) s, float32 [B][nobs][nt] (device, overwritten)
  * Deterministic: identical inputs give bit-identical outputs. */
 s2w_status s2w_forward(s2w_plan* plan, const float* s, int32_t B, float* y, void* stream);
+
+/* Forward map that also returns the share's seafloor displacement, the intermediate field of
+ * eq. (1) (Sec. III-C shows it beside the waveforms), from the same pass: the displacement is
+ * written where the mid-chain forms it (the first product's inverse transform truncated to
+ * n < nt, before D_t; on the direct layout the time-domain sum), so the elastic store is read
+ * once for both outputs.
+ *   s[b][j][n]   as s2w_forward;  y[b][o][n] as s2w_forward
+ *   m[b][g][i]   float32 [B][ngrid][ntimes] (device, 256-byte aligned, distinct from s and y):
+ *                m_n at grid row g of the share, n = times[i]:
+ *                m_n = sum_j sum_{k<=n} [F_{G,k}]_{g,j} s_{j,n-k}
+ *   times        host array of ntimes steps, strictly increasing, each in [0, nt); or NULL with
+ *                ntimes = nt for every step.  Read during the call only.
+ * Every layout and store precision has it; the displacement carries the precision of the
+ * path's elastic store (float32, or the bf16/f16 rounding of a half store).  y is identical,
+ * bit for bit, to s2w_forward's.  Invalid time lists give S2W_EINVAL before any enqueue. */
+s2w_status s2w_forward_displacement(s2w_plan* plan, const float* s, int32_t B, float* y, float* m,
+                                    const int32_t* times, int32_t ntimes, void* stream);
 
 /* Adjoint (transpose) of the forward map as a real linear operator, including
  * the transpose of D_t: gs = A^T r, so that for L = 0.5 ||A s - y_obs||^2 the
@@ -240,7 +270,8 @@ s2w_status s2w_bltt_apply(s2w_bltt* op, const float* x, int32_t B, float* y, voi
 s2w_status s2w_bltt_adjoint(s2w_bltt* op, const float* y, int32_t B, float* x, void* stream);
 const char* s2w_bltt_last_error(const s2w_bltt* op);
 
-/* The layout the plan resolved S2W_LAYOUT_AUTO to: S2W_LAYOUT_SINGLE or S2W_LAYOUT_BATCHED. */
+/* The layout of the plan: S2W_LAYOUT_SINGLE, S2W_LAYOUT_BATCHED (AUTO resolves to one of these)
+ * or S2W_LAYOUT_DIRECT. */
 s2w_status s2w_plan_layout(const s2w_plan* plan, int32_t* layout);
 
 const char* s2w_status_string(s2w_status st);

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(_HERE, "libs2w.so")
 DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 DIFF_NONE = 0
 DIFF_BACKWARD = 1
-LAYOUTS = {"auto": 0, "single": 1, "batched": 2}
+LAYOUTS = {"auto": 0, "single": 1, "batched": 2, "direct": 3}
 
 STATUS = {0: "S2W_OK", 1: "S2W_EINVAL", 2: "S2W_ENOMEM", 3: "S2W_ESTATE", 4: "S2W_EUNSUPPORTED", 5: "S2W_EHIP"}
 
@@ -50,7 +50,8 @@ EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_c
            "s2w_query_sizes", "s2w_bind_memory", "s2w_set_operators", "s2w_forward", "s2w_adjoint",
            "s2w_set_tuning", "s2w_get_tuning", "s2w_transform_length", "s2w_set_profile_events", "s2w_plan_layout",
            "s2w_bltt_create", "s2w_bltt_destroy", "s2w_bltt_query_sizes", "s2w_bltt_bind_memory",
-           "s2w_bltt_set_blocks", "s2w_bltt_apply", "s2w_bltt_adjoint", "s2w_bltt_last_error", "s2w_forward_noalloc"]
+           "s2w_bltt_set_blocks", "s2w_bltt_apply", "s2w_bltt_adjoint", "s2w_bltt_last_error", "s2w_forward_noalloc",
+           "s2w_forward_displacement"]
 
 _lib = None
 
@@ -79,6 +80,7 @@ def load_library(path: str | None = None):
     lib.s2w_forward.argtypes = [plan_p, vp, i32, vp, vp]
     lib.s2w_adjoint.argtypes = [plan_p, vp, i32, vp, vp]
     lib.s2w_forward_noalloc.argtypes = [plan_p, vp, i32, vp, vp]
+    lib.s2w_forward_displacement.argtypes = [plan_p, vp, i32, vp, vp, P(i32), i32, vp]
     lib.s2w_set_tuning.argtypes = [plan_p, P(Tuning)]
     lib.s2w_get_tuning.argtypes = [plan_p, P(Tuning)]
     lib.s2w_transform_length.argtypes = [plan_p, P(i32)]
@@ -144,7 +146,7 @@ class Plan:
     def layout(self) -> str:
         v = ctypes.c_int32()
         self._check(self.lib.s2w_plan_layout(self.handle, ctypes.byref(v)), "s2w_plan_layout")
-        return {1: "single", 2: "batched"}[v.value]
+        return {1: "single", 2: "batched", 3: "direct"}[v.value]
 
     def bind(self, op_ptr: int, op_bytes: int, ws_ptr: int, ws_bytes: int):
         self._check(self.lib.s2w_bind_memory(self.handle, op_ptr, op_bytes, ws_ptr, ws_bytes), "s2w_bind_memory")
@@ -160,6 +162,16 @@ class Plan:
 
     def forward_noalloc(self, s_ptr: int, B: int, y_ptr: int, stream: int = 0):
         self._check(self.lib.s2w_forward_noalloc(self.handle, s_ptr, B, y_ptr, stream), "s2w_forward_noalloc")
+
+    def forward_displacement(self, s_ptr: int, B: int, y_ptr: int, m_ptr: int, times=None, ntimes: int = 0,
+                             stream: int = 0):
+        """times: a sequence of steps (marshalled to an int32 array), or None with ntimes = nt."""
+        arr = None
+        if times is not None:
+            arr = (ctypes.c_int32 * len(times))(*[int(t) for t in times])
+            ntimes = len(times)
+        self._check(self.lib.s2w_forward_displacement(self.handle, s_ptr, B, y_ptr, m_ptr, arr, ntimes, stream),
+                    "s2w_forward_displacement")
 
     def set_profile_events(self, begin: int = 0, end: int = 0):
         """hipEvent_t handles (ints) recorded around the dominant kernel of later calls; 0, 0 stops."""

@@ -33,6 +33,24 @@ inline int ilog2(int v) {
   return l;
 }
 
+// Channel splits of a direct-path product with `tiles` row tiles: the count (at most smax and
+// the channel count) that fills the `slots` concurrent workgroups in the most even rounds.
+int direct_splits(int64_t tiles, int nchan, int slots, int smax) {
+  smax = std::max(1, std::min(smax, nchan));
+  int best = 1;
+  double beff = -1.0;
+  for (int S = 1; S <= smax; ++S) {
+    const int64_t w = tiles * S;
+    const int64_t rounds = (w + slots - 1) / slots;
+    const double eff = (double)w / (double)(rounds * slots);
+    if (eff > beff + 1e-9) {
+      beff = eff;
+      best = S;
+    }
+  }
+  return best;
+}
+
 // Offsets of the regions carved out of the bound memory.
 struct Layout {
   // operator store (float32 path)
@@ -47,9 +65,19 @@ struct Layout {
   // operator store and workspace (batched float32 path)
   uint64_t gs, fs;
   uint64_t s32, u32, part32, yh32;
+  // operator store and workspace (direct time-domain path)
+  uint64_t gt, ft;
+  uint64_t dpart, dv, dout;
   uint64_t ws_total;
 };
 
+// Extra geometry of the direct time-domain path.
+struct DirectGeo {
+  bool on = false;
+  int ntp;                    // nt rounded up to 16 (zero lags at the end of every stored series)
+  int s_g, s_f;               // forward channel splits: elastic (over subfaults), acoustic (over grid rows)
+  int s_fa, s_ga;             // adjoint channel splits: acoustic (over observers), elastic (over grid rows)
+};
 
 // Extra geometry of the batched float32 path.
 struct BatchGeo32 {
@@ -80,6 +108,7 @@ struct s2w_plan {
   Geometry geo;
   HalfGeo hg;
   BatchGeo32 fb;
+  DirectGeo dg;
   Layout lay;
   s2w_tuning tune;
   char* op = nullptr;
@@ -172,10 +201,29 @@ struct DeviceGuard {
   }
 };
 
-Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, const BatchGeo32& f, int ncu) {
+Layout make_layout(const s2w_desc& d, const Geometry& g, const HalfGeo& h, const BatchGeo32& f,
+                   const DirectGeo& dg, int ncu) {
   Layout L{};
   const uint64_t c8 = sizeof(float2);
   uint64_t off = 0;
+  if (dg.on) {
+    const uint64_t ntp = (uint64_t)dg.ntp, f4 = 4;
+    L.gt = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.nsub * ntp * f4, kAlign);
+    L.ft = off;
+    off = round_up(off + (uint64_t)g.ngrid * g.nobs * ntp * f4, kAlign);
+    L.op_total = off;
+    off = 0;
+    L.dpart = off;  // grid-row partials of the first product (either direction)
+    off = round_up(off + (uint64_t)std::max(dg.s_g, dg.s_fa) * g.ngrid * ntp * f4, kAlign);
+    L.dv = off;     // the differenced seafloor field between the products
+    off = round_up(off + (uint64_t)g.ngrid * ntp * f4, kAlign);
+    L.dout = off;   // partials of the second product
+    off = round_up(off + (uint64_t)std::max((uint64_t)dg.s_f * g.nobs, (uint64_t)dg.s_ga * g.nsub) * ntp * f4,
+                   kAlign);
+    L.ws_total = off;
+    return L;
+  }
   if (f.on) {
     const uint64_t bp = (uint64_t)f.bp;
     L.gs = off;
@@ -290,10 +338,11 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   if (d.g_dtype < S2W_F32 || d.g_dtype > S2W_F16 || d.f_dtype < S2W_F32 || d.f_dtype > S2W_F16) return S2W_EINVAL;
   const bool half = d.g_dtype != S2W_F32 || d.f_dtype != S2W_F32;
   if (half && (d.g_dtype == S2W_F32 || d.f_dtype == S2W_F32)) return S2W_EUNSUPPORTED;
-  if (d.layout < S2W_LAYOUT_AUTO || d.layout > S2W_LAYOUT_BATCHED || d.reserved != 0) return S2W_EINVAL;
-  if (half && d.layout == S2W_LAYOUT_SINGLE) return S2W_EUNSUPPORTED;
+  if (d.layout < S2W_LAYOUT_AUTO || d.layout > S2W_LAYOUT_DIRECT || d.reserved != 0) return S2W_EINVAL;
+  if (half && (d.layout == S2W_LAYOUT_SINGLE || d.layout == S2W_LAYOUT_DIRECT)) return S2W_EUNSUPPORTED;
   const bool batched32 =
       !half && (d.layout == S2W_LAYOUT_BATCHED || (d.layout == S2W_LAYOUT_AUTO && d.max_batch >= 8));
+  const bool direct = d.layout == S2W_LAYOUT_DIRECT;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return S2W_EINVAL;
 
@@ -343,7 +392,19 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
     f.ngk = (d.ngrid + 7) / 8 * 8;
     f.bp = (std::max(d.max_batch, 1) + 7) / 8 * 8;
   }
-  p->lay = make_layout(d, g, h, p->fb, ncu);
+  if (direct) {
+    DirectGeo& dd = p->dg;
+    dd.on = true;
+    dd.ntp = (d.nt + 15) / 16 * 16;
+    const int nranges = (dd.ntp / 16 + 15) / 16;
+    const int slots = 2 * ncu;  // two workgroups of four waves per compute unit
+    auto tiles = [&](int rows, int rw) { return (int64_t)((rows + 64 * rw - 1) / (64 * rw)) * nranges; };
+    dd.s_g = direct_splits(tiles(d.ngrid, 2), d.nsub, slots, 16);
+    dd.s_f = direct_splits(tiles(d.nobs, 1), d.ngrid, slots, 1024);
+    dd.s_fa = direct_splits(tiles(d.ngrid, 2), d.nobs, slots, 16);
+    dd.s_ga = direct_splits(tiles(d.nsub, 2), d.ngrid, slots, 1024);
+  }
+  p->lay = make_layout(d, g, h, p->fb, p->dg, ncu);
   p->tune.fused_wg_per_cu = 1;
   p->tune.fused_rows = 8;
   p->tune.adj_cols = 16;
@@ -391,7 +452,7 @@ s2w_status s2w_query_sizes(const s2w_plan* p, uint64_t* operator_bytes, uint64_t
 
 s2w_status s2w_plan_layout(const s2w_plan* p, int32_t* layout) {
   if (!p || !layout) return S2W_EINVAL;
-  *layout = (p->hg.on || p->fb.on) ? S2W_LAYOUT_BATCHED : S2W_LAYOUT_SINGLE;
+  *layout = p->dg.on ? S2W_LAYOUT_DIRECT : (p->hg.on || p->fb.on) ? S2W_LAYOUT_BATCHED : S2W_LAYOUT_SINGLE;
   return S2W_OK;
 }
 
@@ -564,6 +625,20 @@ static s2w_status set_operators_b32(s2w_plan* p, const float* G_chunk, const flo
   return S2W_OK;
 }
 
+// Direct setup: the time-domain blocks are kept as given, each series padded with zero lags
+// to a multiple of 16: Gt[g][j][k], Ft[g][o][k].
+static s2w_status set_operators_direct(s2w_plan* p, const float* G_chunk, const float* F_chunk, int64_t row0,
+                                       int64_t nrows, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const int ntp = p->dg.ntp;
+  float* Gt = (float*)(p->op + p->lay.gt) + row0 * g.nsub * ntp;
+  float* Ft = (float*)(p->op + p->lay.ft) + row0 * g.nobs * ntp;
+  hipError_t e = launch_pad_series(G_chunk, nrows * g.nsub, g.nt, ntp, Gt, st);
+  if (e == hipSuccess) e = launch_pad_series(F_chunk, nrows * g.nobs, g.nt, ntp, Ft, st);
+  if (e != hipSuccess) return hip_fail(p, e, "set_operators: time-domain store");
+  return S2W_OK;
+}
+
 s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_chunk, int64_t row0, int64_t nrows,
                              void* stream) {
   if (!p) return S2W_EINVAL;
@@ -578,9 +653,10 @@ s2w_status s2w_set_operators(s2w_plan* p, const float* G_chunk, const float* F_c
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "set_operators: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
-  if (p->fb.on || p->hg.on) {
-    s2w_status hs = p->fb.on ? set_operators_b32(p, G_chunk, F_chunk, row0, nrows, st)
-                             : set_operators_half(p, G_chunk, F_chunk, row0, nrows, st);
+  if (p->fb.on || p->hg.on || p->dg.on) {
+    s2w_status hs = p->dg.on   ? set_operators_direct(p, G_chunk, F_chunk, row0, nrows, st)
+                    : p->fb.on ? set_operators_b32(p, G_chunk, F_chunk, row0, nrows, st)
+                               : set_operators_half(p, G_chunk, F_chunk, row0, nrows, st);
     if (hs != S2W_OK) return hs;
     for (int64_t r = row0; r < row0 + nrows; ++r) {
       if (!p->row_set[(size_t)r]) {
@@ -627,7 +703,8 @@ static int64_t part_floats(const s2w_plan* p) {
 }
 
 // Batched forward on the matrix cores (half-precision stores).
-static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st) {
+static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st,
+                               const DispOut* disp) {
   const Geometry& g = p->geo;
   const HalfGeo& h = p->hg;
   const Layout& L = p->lay;
@@ -696,7 +773,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   // writes (M = 256), else from a pass over U
   int groups = 0;
   e = launch_mid_batch(U, sF, B, bp, false, packed, g, st, p->tune.mid_rupts, fscale ? part : nullptr,
-                       part_floats(p), &groups);
+                       part_floats(p), &groups, disp);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
     e = groups > 0 ? launch_col_scale_final(part, groups, g.M, B, bp, tau_up, tau_down, st)
@@ -741,7 +818,8 @@ static int b32_splits(int tuned, int maxs, int M, int nrows, int B, int cfg) {
 }
 
 // Batched forward on the matrix cores (float32 stores).
-static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st) {
+static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st,
+                              const DispOut* disp) {
   const Geometry& g = p->geo;
   const BatchGeo32& f = p->fb;
   const Layout& L = p->lay;
@@ -764,7 +842,7 @@ static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, 
                        st);
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
-  e = launch_mid_batch(U, nullptr, B, bp, false, false, g, st, p->tune.mid_rupts);
+  e = launch_mid_batch(U, nullptr, B, bp, false, false, g, st, p->tune.mid_rupts, nullptr, 0, nullptr, disp);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   // part[split][l][o][n] = sum_{g in split} Fs[l][o][g] V[g][l][b]
   const int cf = b32_cfg(p, B, true);
@@ -889,8 +967,87 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   return S2W_OK;
 }
 
+// Direct forward (eq. 4 form of eqs. 1 and 2, no FFT), one rupture at a time: the elastic
+// product over subfaults into grid-row partials, their sum and D_t, the acoustic product over
+// grid rows into observer partials, their sum.
+static s2w_status forward_direct(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st,
+                                 const DispOut* disp) {
+  const Geometry& g = p->geo;
+  const DirectGeo& dd = p->dg;
+  const int64_t ntp = dd.ntp;
+  const float* Gt = (const float*)(p->op + p->lay.gt);
+  const float* Ft = (const float*)(p->op + p->lay.ft);
+  float* mpart = (float*)(p->ws + p->lay.dpart);
+  float* v = (float*)(p->ws + p->lay.dv);
+  float* ypart = (float*)(p->ws + p->lay.dout);
+  const float dscale = g.diff ? 1.0f / g.dt : 1.0f;
+  for (int b = 0; b < B; ++b) {
+    const float* sb = s + (int64_t)b * g.nsub * g.nt;
+    float* yb = y + (int64_t)b * g.nobs * g.nt;
+    hipError_t e = mark(p->ev_begin, st);
+    if (e == hipSuccess)
+      e = launch_direct(2, Gt, ntp, (int64_t)g.nsub * ntp, g.ngrid, g.nsub, sb, g.nt, false, mpart,
+                        (int64_t)g.ngrid * ntp, ntp, g.nt, dd.s_g, st);
+    if (e == hipSuccess) e = mark(p->ev_end, st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: direct elastic product");
+    DispOut db{};
+    if (disp) {
+      db = *disp;
+      db.base = disp->base + (int64_t)b * disp->row_stride;  // rupture b; rows are grid rows
+      db.row_stride = disp->grid_stride;
+      db.rows = g.ngrid;
+      db.scale = 1.0f;
+    }
+    e = launch_direct_reduce(mpart, dd.s_g, (int64_t)g.ngrid * ntp, ntp, g.ngrid, g.nt, false, g.diff != 0, dscale, v,
+                             ntp, st, disp ? &db : nullptr);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: direct seafloor sum and difference");
+    e = launch_direct(1, Ft, (int64_t)g.nobs * ntp, ntp, g.nobs, g.ngrid, v, ntp, false, ypart,
+                      (int64_t)g.nobs * ntp, ntp, g.nt, dd.s_f, st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: direct acoustic product");
+    e = launch_direct_reduce(ypart, dd.s_f, (int64_t)g.nobs * ntp, ntp, g.nobs, g.nt, false, false, 1.0f, yb, g.nt,
+                             st);
+    if (e != hipSuccess) return hip_fail(p, e, "forward: direct waveform sum");
+  }
+  return S2W_OK;
+}
+
+// Direct adjoint: the two correlations of the transpose as causal products on the time-reversed
+// axis (w_rev = F^T r_rev per grid row, D_t^T as the backward difference of w_rev, then
+// gs_rev = G^T w'_rev), reversed back in the final sum.
+static s2w_status adjoint_direct(s2w_plan* p, const float* r, int32_t B, float* gs, hipStream_t st) {
+  const Geometry& g = p->geo;
+  const DirectGeo& dd = p->dg;
+  const int64_t ntp = dd.ntp;
+  const float* Gt = (const float*)(p->op + p->lay.gt);
+  const float* Ft = (const float*)(p->op + p->lay.ft);
+  float* wpart = (float*)(p->ws + p->lay.dpart);
+  float* w = (float*)(p->ws + p->lay.dv);
+  float* gpart = (float*)(p->ws + p->lay.dout);
+  const float dscale = g.diff ? 1.0f / g.dt : 1.0f;
+  for (int b = 0; b < B; ++b) {
+    const float* rb = r + (int64_t)b * g.nobs * g.nt;
+    float* gb = gs + (int64_t)b * g.nsub * g.nt;
+    hipError_t e = launch_direct(2, Ft, ntp, (int64_t)g.nobs * ntp, g.ngrid, g.nobs, rb, g.nt, true, wpart,
+                                 (int64_t)g.ngrid * ntp, ntp, g.nt, dd.s_fa, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: direct acoustic correlation");
+    e = launch_direct_reduce(wpart, dd.s_fa, (int64_t)g.ngrid * ntp, ntp, g.ngrid, g.nt, false, g.diff != 0, dscale,
+                             w, ntp, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: direct seafloor sum and difference");
+    e = mark(p->ev_begin, st);
+    if (e == hipSuccess)
+      e = launch_direct(2, Gt, (int64_t)g.nsub * ntp, ntp, g.nsub, g.ngrid, w, ntp, false, gpart,
+                        (int64_t)g.nsub * ntp, ntp, g.nt, dd.s_ga, st);
+    if (e == hipSuccess) e = mark(p->ev_end, st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: direct elastic correlation");
+    e = launch_direct_reduce(gpart, dd.s_ga, (int64_t)g.nsub * ntp, ntp, g.nsub, g.nt, true, false, 1.0f, gb, g.nt,
+                             st);
+    if (e != hipSuccess) return hip_fail(p, e, "adjoint: direct slip-rate sum");
+  }
+  return S2W_OK;
+}
+
 static s2w_status forward_single(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st, float2* Sh,
-                                 float2* part, float2* yh, float2* Vh);
+                                 float2* part, float2* yh, float2* Vh, const DispOut* disp);
 
 s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
   s2w_status cs = check_call(p, s, B, y, "forward");
@@ -898,10 +1055,62 @@ s2w_status s2w_forward(s2w_plan* p, const float* s, int32_t B, float* y, void* s
   DeviceGuard dg(p->device);
   if (!dg.ok) return fail(p, S2W_EHIP, "forward: cannot select device %d", p->device);
   hipStream_t st = (hipStream_t)stream;
-  if (p->hg.on) return forward_half(p, s, B, y, st);
-  if (p->fb.on) return forward_b32(p, s, B, y, st);
+  if (p->hg.on) return forward_half(p, s, B, y, st, nullptr);
+  if (p->fb.on) return forward_b32(p, s, B, y, st, nullptr);
+  if (p->dg.on) return forward_direct(p, s, B, y, st, nullptr);
   return forward_single(p, s, B, y, st, (float2*)(p->ws + p->lay.sh), (float2*)(p->ws + p->lay.part),
-                        (float2*)(p->ws + p->lay.yh), (float2*)(p->ws + p->lay.wp));
+                        (float2*)(p->ws + p->lay.yh), (float2*)(p->ws + p->lay.wp), nullptr);
+}
+
+s2w_status s2w_forward_displacement(s2w_plan* p, const float* s, int32_t B, float* y, float* m,
+                                    const int32_t* times, int32_t ntimes, void* stream) {
+  s2w_status cs = check_call(p, s, B, y, "forward_displacement");
+  if (cs != S2W_OK) return cs;
+  const Geometry& g = p->geo;
+  DispOut d{};
+  if (times == nullptr) {
+    if (ntimes != g.nt)
+      return fail(p, S2W_EINVAL, "forward_displacement: without a time list ntimes must be nt = %d", g.nt);
+    d.all = 1;
+  } else {
+    if (ntimes < 1 || ntimes > g.nt)
+      return fail(p, S2W_EINVAL, "forward_displacement: ntimes=%d outside [1, %d]", ntimes, g.nt);
+    for (int i = 0; i < ntimes; ++i) {
+      const int t = times[i];
+      if (t < 0 || t >= g.nt) return fail(p, S2W_EINVAL, "forward_displacement: times[%d]=%d outside [0, %d)", i, t, g.nt);
+      if (i > 0 && t <= times[i - 1])
+        return fail(p, S2W_EINVAL, "forward_displacement: times must increase strictly (times[%d]=%d)", i, t);
+      d.bits[t >> 5] |= 1u << (t & 31);
+    }
+    d.all = ntimes == g.nt;
+  }
+  if (B == 0) return S2W_OK;
+  if (!m) return fail(p, S2W_EINVAL, "forward_displacement: null displacement pointer");
+  if (!aligned(m)) return fail(p, S2W_EINVAL, "forward_displacement: displacement pointer must be 256-byte aligned");
+  if ((const void*)m == (const void*)s || m == y)
+    return fail(p, S2W_EINVAL, "forward_displacement: displacement output must be distinct from s and y");
+  DeviceGuard dg(p->device);
+  if (!dg.ok) return fail(p, S2W_EHIP, "forward_displacement: cannot select device %d", p->device);
+  hipStream_t st = (hipStream_t)stream;
+  d.base = m;
+  d.scale = 1.0f / (float)g.L;
+  d.rows = 1 << 30;
+  if (p->hg.on || p->fb.on) {
+    // transform rows are the ruptures of one grid row
+    d.row_stride = (int64_t)g.ngrid * ntimes;
+    d.grid_stride = ntimes;
+    return p->hg.on ? forward_half(p, s, B, y, st, &d) : forward_b32(p, s, B, y, st, &d);
+  }
+  if (p->dg.on) {
+    d.row_stride = (int64_t)g.ngrid * ntimes;  // per rupture; the direct path re-strides by grid row
+    d.grid_stride = ntimes;
+    return forward_direct(p, s, B, y, st, &d);
+  }
+  // transform rows are grid rows; forward_single offsets the base per rupture
+  d.row_stride = ntimes;
+  d.grid_stride = (int64_t)g.ngrid * ntimes;
+  return forward_single(p, s, B, y, st, (float2*)(p->ws + p->lay.sh), (float2*)(p->ws + p->lay.part),
+                        (float2*)(p->ws + p->lay.yh), (float2*)(p->ws + p->lay.wp), &d);
 }
 
 // Bytes of scratch the single-layout forward needs for its source spectrum, the fused
@@ -920,7 +1129,7 @@ static uint64_t single_fused_scratch(const s2w_plan* p, uint64_t* o_part, uint64
 s2w_status s2w_forward_noalloc(s2w_plan* p, const float* s, int32_t B, float* y, void* stream) {
   s2w_status cs = check_call(p, s, B, y, "forward_noalloc");
   if (cs != S2W_OK || B == 0) return cs;
-  if (p->hg.on || p->fb.on)
+  if (p->hg.on || p->fb.on || p->dg.on)
     return fail(p, S2W_EUNSUPPORTED, "forward_noalloc: only plans with the single (float32) layout");
   if (fused_forward_opt(p->geo) > 32)
     return fail(p, S2W_EUNSUPPORTED, "forward_noalloc: %d observers at L = %d need the unfused path", p->geo.nobs,
@@ -939,14 +1148,14 @@ s2w_status s2w_forward_noalloc(s2w_plan* p, const float* s, int32_t B, float* y,
   char* base = (char*)scratch_ptr(p->device, &se);
   if (!base) return hip_fail(p, se == hipSuccess ? hipErrorInvalidSymbol : se, "forward_noalloc: scratch lookup");
   return forward_single(p, s, B, y, (hipStream_t)stream, (float2*)base, (float2*)(base + o_part),
-                        (float2*)(base + o_yh), nullptr);
+                        (float2*)(base + o_yh), nullptr, nullptr);
 }
 
 // Single-layout forward: B passes of the fused (or, for many observers, the unfused) kernel,
 // with the source spectrum in Sh, the partial spectra in part and their sum in yh; Vh holds
 // the unfused path's seafloor spectra.
 static s2w_status forward_single(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st, float2* Sh,
-                                 float2* part, float2* yh, float2* Vh) {
+                                 float2* part, float2* yh, float2* Vh, const DispOut* disp) {
   const Geometry& g = p->geo;
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
@@ -960,13 +1169,18 @@ static s2w_status forward_single(s2w_plan* p, const float* s, int32_t B, float* 
     hipError_t e = launch_rfft_rows(sb, 1, g.nsub, g.nsp, Sh, 0, g.M, 1, g, 1.0f, st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
     int nparts;
+    DispOut db{};
+    if (disp) {
+      db = *disp;
+      db.base = disp->base + (int64_t)b * disp->grid_stride;  // rupture b; rows are grid rows
+    }
     e = mark(p->ev_begin, st);
     if (fused) {
-      if (e == hipSuccess) e = launch_fused_forward(Gh, Fh, Sh, part, nwg, p->tune.fused_rows, g, st);
+      if (e == hipSuccess) e = launch_fused_forward(Gh, Fh, Sh, part, nwg, p->tune.fused_rows, g, st, db);
       if (e == hipSuccess) e = mark(p->ev_end, st);
       nparts = nwg;
     } else {
-      if (e == hipSuccess) e = launch_forward_rows(Gh, Sh, Vh, nwg, g, st);
+      if (e == hipSuccess) e = launch_forward_rows(Gh, Sh, Vh, nwg, g, st, db);
       if (e == hipSuccess) e = mark(p->ev_end, st);
       if (e == hipSuccess) e = launch_rows_acoustic(Fh, Vh, part, p->tune.adj_cols, p->tune.adj_splits, g, st);
       nparts = p->tune.adj_splits;
@@ -989,6 +1203,7 @@ s2w_status s2w_adjoint(s2w_plan* p, const float* r, int32_t B, float* gs, void* 
   hipStream_t st = (hipStream_t)stream;
   if (p->hg.on) return adjoint_half(p, r, B, gs, st);
   if (p->fb.on) return adjoint_b32(p, r, B, gs, st);
+  if (p->dg.on) return adjoint_direct(p, r, B, gs, st);
   const float2* Gh = (const float2*)(p->op + p->lay.gh);
   const float2* Fh = (const float2*)(p->op + p->lay.fh);
   float2* Rh = (float2*)(p->ws + p->lay.rh);

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "s2w_internal.h"
+
 namespace s2w {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -151,6 +153,28 @@ __device__ __forceinline__ float zsample(const float2* z, int m) {
 // Difference modes of the mid-chain round trip.
 enum MidMode { MID_NONE = 0, MID_BACKWARD = 1, MID_BACKWARD_T = 2 };
 
+// Output column of time step n, or -1 when n is not selected.
+__device__ __forceinline__ int disp_col(const DispOut& d, int n) {
+  if (d.all) return n;
+  const int w = n >> 5;
+  int col = 0;
+  uint32_t word = 0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i < w) col += __popc(d.bits[i]);
+    if (i == w) word = d.bits[i];
+  }
+  const uint32_t bit = 1u << (n & 31);
+  return (word & bit) ? col + __popc(word & (bit - 1u)) : -1;
+}
+
+__device__ __forceinline__ void disp_put(const DispOut* d, int r, int n, float lval) {
+  if (d && d->base && r < d->rows) {
+    const int c = disp_col(*d, n);
+    if (c >= 0) d->base[(int64_t)r * d->row_stride + c] = lval * d->scale;
+  }
+}
+
 // Mid-chain round trip for R rows (Alg. 2 steps 4-5 of the first product, D_t, and
 // steps 1-2 of the second): packed spectra in `X` [R][M] (LDS) -> inverse real FFT ->
 // keep samples n < nt -> temporal difference -> zero-pad -> forward real FFT -> packed
@@ -158,7 +182,7 @@ enum MidMode { MID_NONE = 0, MID_BACKWARD = 1, MID_BACKWARD_T = 2 };
 // and 1/dt of D_t).  `Y` is [R][M] LDS scratch.  Returns the buffer (X or Y) holding the
 // result.  All threads of the block call it; it ends after a barrier.
 __device__ __forceinline__ float2* lds_midchain2(float2* X, float2* Y, int R, int M, int logM, int nt, int mode,
-                                                 float scale, const Twiddles& tw) {
+                                                 float scale, const Twiddles& tw, const DispOut* disp = nullptr) {
   const int n = R * M;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int r = i >> logM, k = i & (M - 1);
@@ -177,6 +201,7 @@ __device__ __forceinline__ float2* lds_midchain2(float2* X, float2* Y, int R, in
       float val = 0.f;
       if (m < nt) {
         const float xm = zsample(zr, m);
+        disp_put(disp, r, m, xm);
         if (mode == MID_BACKWARD) {
           val = xm - (m > 0 ? zsample(zr, m - 1) : 0.f);
         } else if (mode == MID_BACKWARD_T) {
@@ -287,7 +312,8 @@ __device__ __forceinline__ void fft256_passA(float2 (&v)[16], int c, const float
 // Same arithmetic as lds_midchain2 (inverse real FFT, truncate to nt, D_t, zero-pad, forward
 // real FFT), with the complex transforms done as two 16-point passes in registers.
 __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int mode, float scale,
-                                       const Twiddles& tw, int ldx = 256, int ldt = 256) {
+                                       const Twiddles& tw, int ldx = 256, int ldt = 256,
+                                       const DispOut* disp = nullptr) {
   constexpr int M = 256;
   const int tid = threadIdx.x;
   const int r = tid >> 4, c = tid & 15;
@@ -319,6 +345,8 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int 
       const int n = 16 * n1 + c;
       const float2 z = Xr[n];
       const int m0 = 2 * n, m1 = m0 + 1;
+      if (act && m0 < nt) disp_put(disp, r, m0, z.x);
+      if (act && m1 < nt) disp_put(disp, r, m1, z.y);
       float a = 0.f, b = 0.f;
       if (mode == MID_BACKWARD) {
         const float xm1 = n > 0 ? Xr[n - 1].y : 0.f;

@@ -224,7 +224,7 @@ template <int T, int OPT>
 __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict__ Gh, const v4f* __restrict__ Fh,
                                                           const v4f* __restrict__ Sh, v4f* __restrict__ part,
                                                           int ngrid, int nsub, int nsp, int nobs, int nop, int M,
-                                                          int logM, int nt, int mode, float mscale) {
+                                                          int logM, int nt, int mode, float mscale, DispOut disp) {
   extern __shared__ float2 smem[];
   float2* U = smem;
   float2* BA = U + T * M;
@@ -232,6 +232,7 @@ __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict_
   const Twiddles tw = lds_twiddles(reinterpret_cast<float2*>(red + 256 * T), M);
   const int tid = threadIdx.x;
   const int NP = M >> 1, OG = 256 / NP;
+  float* const disp_m = disp.base;
   const int p = tid % NP, og = tid / NP;
   const bool dc = (p == 0);
   const int wg = blockIdx.x, nwg = gridDim.x;
@@ -243,7 +244,9 @@ __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict_
   for (int g0 = r0; g0 < r1; g0 += T) {
     const int tr = min(T, r1 - g0);
     contract_cols<T, false>(Gh, Sh, g0, tr, nsub, nsp, M, U, red);
-    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw);
+    disp.base = disp_m ? disp_m + (int64_t)g0 * disp.row_stride : nullptr;
+    disp.rows = tr;
+    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw, &disp);
     const v4f* fb = Fh + (int64_t)g0 * frow + p;
     for (int t = 0; t < tr; ++t) {
       const float2 va = Vt[t * M + 2 * p], vb = Vt[t * M + 2 * p + 1];
@@ -284,30 +287,30 @@ int fused_forward_opt(const Geometry& g) {
 
 template <int T, int OPT>
 static hipError_t fused_fwd_t(const float2* Gh, const float2* Fh, const float2* Sh, float2* part, int nwg,
-                              const Geometry& g, hipStream_t st) {
+                              const Geometry& g, hipStream_t st, const DispOut& disp) {
   const int mode = g.diff ? MID_BACKWARD : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
   hipLaunchKernelGGL((k_fused_forward<T, OPT>), dim3(nwg), dim3(256), tile_lds(T, g.M), st, (const v4f*)Gh,
                      (const v4f*)Fh, (const v4f*)Sh, (v4f*)part, g.ngrid, g.nsub, g.nsp, g.nobs, g.nop, g.M, g.logM,
-                     g.nt, mode, mscale);
+                     g.nt, mode, mscale, disp);
   return hipGetLastError();
 }
 
 template <int T>
 static hipError_t fused_fwd_rows(const float2* Gh, const float2* Fh, const float2* Sh, float2* part, int nwg,
-                                 const Geometry& g, hipStream_t st) {
+                                 const Geometry& g, hipStream_t st, const DispOut& disp) {
   const int need = fused_forward_opt(g);
-  if (need <= 4) return fused_fwd_t<T, 4>(Gh, Fh, Sh, part, nwg, g, st);
-  if (need <= 8) return fused_fwd_t<T, 8>(Gh, Fh, Sh, part, nwg, g, st);
-  if (need <= 16) return fused_fwd_t<T, 16>(Gh, Fh, Sh, part, nwg, g, st);
-  if (need <= 32) return fused_fwd_t<T, 32>(Gh, Fh, Sh, part, nwg, g, st);
+  if (need <= 4) return fused_fwd_t<T, 4>(Gh, Fh, Sh, part, nwg, g, st, disp);
+  if (need <= 8) return fused_fwd_t<T, 8>(Gh, Fh, Sh, part, nwg, g, st, disp);
+  if (need <= 16) return fused_fwd_t<T, 16>(Gh, Fh, Sh, part, nwg, g, st, disp);
+  if (need <= 32) return fused_fwd_t<T, 32>(Gh, Fh, Sh, part, nwg, g, st, disp);
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_fused_forward(const float2* Gh, const float2* Fh, const float2* Sh, float2* part, int nwg,
-                                int tile_rows, const Geometry& g, hipStream_t st) {
-  if (tile_rows == 4) return fused_fwd_rows<4>(Gh, Fh, Sh, part, nwg, g, st);
-  return fused_fwd_rows<8>(Gh, Fh, Sh, part, nwg, g, st);
+                                int tile_rows, const Geometry& g, hipStream_t st, const DispOut& disp) {
+  if (tile_rows == 4) return fused_fwd_rows<4>(Gh, Fh, Sh, part, nwg, g, st, disp);
+  return fused_fwd_rows<8>(Gh, Fh, Sh, part, nwg, g, st, disp);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -359,7 +362,7 @@ hipError_t launch_sum_parts(const float2* part, int nparts, int64_t items_c, flo
 template <int T, bool CONJ>
 __global__ __launch_bounds__(256) void k_rows_mid(const v4f* __restrict__ X, const v4f* __restrict__ Y,
                                                   float2* __restrict__ Out, int ngrid, int nc, int ncp, int M,
-                                                  int logM, int nt, int mode, float mscale) {
+                                                  int logM, int nt, int mode, float mscale, DispOut disp) {
   extern __shared__ float2 smem[];
   float2* U = smem;
   float2* BA = U + T * M;
@@ -367,10 +370,13 @@ __global__ __launch_bounds__(256) void k_rows_mid(const v4f* __restrict__ X, con
   const Twiddles tw = lds_twiddles(reinterpret_cast<float2*>(red + 256 * T), M);
   const int wg = blockIdx.x, nwg = gridDim.x;
   const int r0 = (int)((int64_t)ngrid * wg / nwg), r1 = (int)((int64_t)ngrid * (wg + 1) / nwg);
+  float* const disp_m = disp.base;
   for (int g0 = r0; g0 < r1; g0 += T) {
     const int tr = min(T, r1 - g0);
     contract_cols<T, CONJ>(X, Y, g0, tr, nc, ncp, M, U, red);
-    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw);
+    disp.base = disp_m ? disp_m + (int64_t)g0 * disp.row_stride : nullptr;
+    disp.rows = tr;
+    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw, &disp);
     for (int i = threadIdx.x; i < tr * M; i += blockDim.x) Out[(int64_t)g0 * M + i] = Vt[i];
     __syncthreads();
   }
@@ -382,19 +388,19 @@ hipError_t launch_adjoint_rows(const float2* Fh, const float2* Rh, float2* Wp, i
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
   if (tile_rows == 4)
     hipLaunchKernelGGL((k_rows_mid<4, true>), dim3(nwg), dim3(256), tile_lds(4, g.M), st, (const v4f*)Fh,
-                       (const v4f*)Rh, Wp, g.ngrid, g.nobs, g.nop, g.M, g.logM, g.nt, mode, mscale);
+                       (const v4f*)Rh, Wp, g.ngrid, g.nobs, g.nop, g.M, g.logM, g.nt, mode, mscale, DispOut{});
   else
     hipLaunchKernelGGL((k_rows_mid<8, true>), dim3(nwg), dim3(256), tile_lds(8, g.M), st, (const v4f*)Fh,
-                       (const v4f*)Rh, Wp, g.ngrid, g.nobs, g.nop, g.M, g.logM, g.nt, mode, mscale);
+                       (const v4f*)Rh, Wp, g.ngrid, g.nobs, g.nop, g.M, g.logM, g.nt, mode, mscale, DispOut{});
   return hipGetLastError();
 }
 
 hipError_t launch_forward_rows(const float2* Gh, const float2* Sh, float2* Vh, int nwg, const Geometry& g,
-                               hipStream_t st) {
+                               hipStream_t st, const DispOut& disp) {
   const int mode = g.diff ? MID_BACKWARD : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
   hipLaunchKernelGGL((k_rows_mid<8, false>), dim3(nwg), dim3(256), tile_lds(8, g.M), st, (const v4f*)Gh,
-                     (const v4f*)Sh, Vh, g.ngrid, g.nsub, g.nsp, g.M, g.logM, g.nt, mode, mscale);
+                     (const v4f*)Sh, Vh, g.ngrid, g.nsub, g.nsp, g.M, g.logM, g.nt, mode, mscale, disp);
   return hipGetLastError();
 }
 
@@ -497,7 +503,8 @@ __device__ __forceinline__ void store_v(float2* dst, float2 v, float f) {
 // General M: rows staged through a padded transposition buffer, generic LDS transforms.
 template <int R, int PACK>
 __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
-                                                   int B, int bp, int M, int logM, int nt, int mode, float mscale) {
+                                                   int B, int bp, int M, int logM, int nt, int mode, float mscale,
+                                                   DispOut disp) {
   extern __shared__ float2 smem[];
   // two buffers of M*(R+1) values: each serves as the row-major FFT buffer [R][M] and, while
   // free, as the padded transposition buffer [M][R+1] (conflict-free in both directions)
@@ -521,7 +528,10 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
       X[i] = Y[l * (R + 1) + r];
     }
     __syncthreads();
-    const float2* V = lds_midchain2(X, Y, R, M, logM, nt, mode, mscale, tw);
+    DispOut d = disp;
+    d.base = disp.base ? disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride : nullptr;
+    d.rows = B - b0;
+    const float2* V = lds_midchain2(X, Y, R, M, logM, nt, mode, mscale, tw, &d);
     float2* Tp = (V == X) ? Y : X;
     for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
       const int r = i >> logM, l = i & (M - 1);
@@ -546,7 +556,7 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
 template <int PACK, int R>
 __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF,
                                                          int ngrid, int B, int bp, int nt, int mode, float mscale,
-                                                         float* __restrict__ cmax) {
+                                                         float* __restrict__ cmax, DispOut disp) {
   constexpr int M = 256, LD = 257;
   __shared__ float2 X[R * LD];
   __shared__ float2 T[R * 16 * 17];
@@ -584,7 +594,11 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
     for (int k = 0; k < 16; ++k) f[k] = fs[k];
     __syncthreads();
     if (u + gridDim.x < units) fetch(u + gridDim.x);
-    mid256(X, T, R, nt, mode, mscale, tw, LD, LD);
+    DispOut d = disp;
+    const int b0 = (int)(u % nbb) * R;
+    d.base = disp.base ? disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride : nullptr;
+    d.rows = B - b0;
+    mid256(X, T, R, nt, mode, mscale, tw, LD, LD, &d);
     float2* dst = U + (int64_t)g * M * bp + b;
     if (b < B) {
 #pragma unroll
@@ -609,8 +623,9 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
 
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
                             const Geometry& g, hipStream_t st, int rupts, float* cmax, int64_t cmax_floats,
-                            int* cmax_groups) {
+                            int* cmax_groups, const DispOut* disp) {
   if (cmax_groups) *cmax_groups = 0;
+  const DispOut dd = disp ? *disp : DispOut{};
   constexpr int R = 16;
   const int mode = g.diff ? (adjoint ? MID_BACKWARD_T : MID_BACKWARD) : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
@@ -633,7 +648,7 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
     }
 #define S2W_MID256(P_, R_)                                                                                       \
   hipLaunchKernelGGL((k_mid_batch256<P_, R_>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF, g.ngrid, B, bp, \
-                     g.nt, mode, mscale, cmax)
+                     g.nt, mode, mscale, cmax, dd)
     if (ru == 32) {
       if (pack_bf16) S2W_MID256(1, 32); else S2W_MID256(0, 32);
     } else {
@@ -645,10 +660,10 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
   const size_t lds = (2 * (size_t)g.M * (R + 1) + 2 * (size_t)g.M) * sizeof(float2);
   if (pack_bf16)
     hipLaunchKernelGGL((k_mid_batch<R, 1>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M,
-                       g.logM, g.nt, mode, mscale);
+                       g.logM, g.nt, mode, mscale, dd);
   else
     hipLaunchKernelGGL((k_mid_batch<R, 0>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M,
-                       g.logM, g.nt, mode, mscale);
+                       g.logM, g.nt, mode, mscale, dd);
   return hipGetLastError();
 }
 

@@ -18,6 +18,24 @@ struct Geometry {
   float dt;
 };
 
+// Optional capture of the seafloor displacement m (eq. 1: the first product's inverse
+// transform, truncated to n < nt, before D_t) at selected time steps, written where the
+// mid-chain forms it.  Sample n of transform row r goes to
+//   base[r * row_stride + column(n)]   (rows r < rows only),
+// column(n) = n when every step is selected, else the rank of n among the selected steps
+// (bit n of `bits`).  `scale` turns the unnormalised inverse transform into m (1/L).
+// Kernels whose transform rows are ruptures of one grid row also take the grid-row stride
+// `grid_stride` and offset `base` themselves.
+struct DispOut {
+  float* base;          // nullptr: nothing captured
+  int64_t row_stride;
+  int64_t grid_stride;
+  int rows;
+  int all;
+  float scale;
+  uint32_t bits[16];    // steps 0 .. 511
+};
+
 // Twiddle table upload (once per device).
 hipError_t upload_twiddles(int device);
 
@@ -35,7 +53,7 @@ hipError_t launch_irfft_rows(const float2* in, int64_t nrows, int64_t in_row, in
 // source spectrum, runs the mid-chain round trip in LDS and accumulates its partial
 // observation spectra; part receives [nwg][nop][M] complex.
 hipError_t launch_fused_forward(const float2* Gh, const float2* Fh, const float2* Sh, float2* part, int nwg,
-                                int tile_rows, const Geometry& g, hipStream_t st);
+                                int tile_rows, const Geometry& g, hipStream_t st, const DispOut& disp);
 
 // Fixed-order sum of partial spectra: out[i] = sum_p part[p][i], i < items_c (complex values).
 hipError_t launch_sum_parts(const float2* part, int nparts, int64_t items_c, float2* out, hipStream_t st);
@@ -56,7 +74,7 @@ hipError_t launch_adjoint_elastic(const float2* Gh, const float2* Wp, float2* pa
 // Unfused forward: stage 1 writes the per-row mid-chain output Vh[g][l]; stage 2
 // contracts it with the acoustic store per bin, split over grid rows.
 hipError_t launch_forward_rows(const float2* Gh, const float2* Sh, float2* Vh, int nwg, const Geometry& g,
-                               hipStream_t st);
+                               hipStream_t st, const DispOut& disp);
 hipError_t launch_rows_acoustic(const float2* Fh, const float2* Vh, float2* part, int cols_per_thread, int splits,
                                 const Geometry& g, hipStream_t st);
 
@@ -110,7 +128,7 @@ hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngri
 // count; elsewhere *cmax_groups is 0 and no maxima are produced.
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
                             const Geometry& g, hipStream_t st, int rupts = 16, float* cmax = nullptr,
-                            int64_t cmax_floats = 0, int* cmax_groups = nullptr);
+                            int64_t cmax_floats = 0, int* cmax_groups = nullptr, const DispOut* disp = nullptr);
 // Power-of-two column scales from partial maxima part[s][l][b], s < splits (columns b >= B get 1).
 hipError_t launch_col_scale_final(const float* part, int splits, int M, int B, int bp, float* tau_up, float* tau_down,
                                   hipStream_t st);
@@ -146,5 +164,20 @@ hipError_t launch_cgemm32(int cfg, bool rcont, bool conj, const float2* A, int64
                           int64_t a_slot, int nrows, int rows_alloc, int kvalid, int kpad, const float2* X,
                           int64_t x_k, int64_t x_slot, int xk_alloc, int B, int bp, float* out, int64_t o_row,
                           int64_t o_slot, int64_t o_split, int M, int splits, hipStream_t st);
+
+// ---- direct time-domain path (float32 matrix cores, no FFT) ----
+// out[split][r][n] = sum over the split's channels c of sum_{k<=n} A(c, r, k) x_c[n - k], n < nt,
+// A(c, r, k) at A + c*a_c + r*a_r + k (16-byte aligned rows, zeros at k >= nt up to nt rounded to
+// 16), x_c[p] at X + c*x_c + (rev ? nt - 1 - p : p); rw = 1 or 2 row blocks of 16 per wave.
+int direct_rows_per_tile(int rw);
+hipError_t launch_direct(int rw, const float* A, int64_t a_c, int64_t a_r, int R, int nchan, const float* X,
+                         int64_t x_c, bool rev, float* out, int64_t o_s, int64_t o_r, int nt, int splits,
+                         hipStream_t st);
+// out[r*o_r + n] = scale * (S(r, n) - diff * S(r, n-1)), S(r, n) = sum_q part[q*p_s + r*p_r + (rev ? nt-1-n : n)]
+hipError_t launch_direct_reduce(const float* part, int parts, int64_t p_s, int64_t p_r, int R, int nt, bool rev,
+                                bool diff, float scale, float* out, int64_t o_r, hipStream_t st,
+                                const DispOut* disp = nullptr);
+// out[s][k] = in[s][k] (k < nt), 0 (nt <= k < ntp), for n series
+hipError_t launch_pad_series(const float* in, int64_t n, int nt, int ntp, float* out, hipStream_t st);
 
 }  // namespace s2w

@@ -97,7 +97,7 @@ class S2WOperator:
         torch.cuda.synchronize(self.device)
 
     def plan_layout(self) -> str:
-        """"single" or "batched": the storage layout the plan uses."""
+        """"single", "batched" or "direct": the storage layout the plan uses."""
         return self.plan.layout()
 
     def set_tuning(self, **kw):
@@ -116,6 +116,19 @@ class S2WOperator:
         assert y.is_contiguous() and _aligned(y) and y.shape == (B, self.nobs, self.nt)
         self.plan.forward(s.data_ptr(), B, y.data_ptr(), _stream_handle(self.device))
         return y[0] if squeeze else y
+
+    def forward_displacement(self, s: torch.Tensor, times=None):
+        """(y, m): the waveforms and the share's seafloor displacement m[B][ngrid][len(times)] at the
+        given steps (every step when None), both from one pass of the map."""
+        squeeze = s.dim() == 2
+        B = 1 if squeeze else s.shape[0]
+        s = _prep(s, (B, self.nsub, self.nt), self.device)
+        nts = self.nt if times is None else len(times)
+        y = torch.empty((B, self.nobs, self.nt), dtype=torch.float32, device=self.device)
+        m = torch.empty((B, self.ngrid, nts), dtype=torch.float32, device=self.device)
+        self.plan.forward_displacement(s.data_ptr(), B, y.data_ptr(), m.data_ptr(),
+                                       None if times is None else list(times), nts, _stream_handle(self.device))
+        return (y[0], m[0]) if squeeze else (y, m)
 
     def adjoint(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         """r[B][nobs][nt] (or [nobs][nt]) -> gs[B][nsub][nt] = A^T r on the current stream."""

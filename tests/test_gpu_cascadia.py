@@ -66,3 +66,27 @@ def test_dot_product_full_share(cascadia_op):
         rel = abs(lhs - rhs) / (np.linalg.norm(Ax[b]) * np.linalg.norm(w[b]))
         print("dot-product mismatch", rel)
         assert rel <= 1e-6
+
+
+@pytest.mark.timeout(600)
+def test_displacement_full_share_sampled_rows(cascadia_op):
+    # the seafloor displacement from the forward map's own pass, against the oracle's single
+    # BLTT of eq. (1) on sampled grid rows; y must not change
+    cfg, op = cascadia_op
+    log_case("cascadia_displacement", ruptures="0..1")
+    s = synth.gen_slip_batch(cfg, 0, 2)
+    sd = to_dev(s)
+    y_plain = op.forward(sd)
+    y, m = op.forward_displacement(sd)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y_plain)
+    rows = np.array([0, 1, 12345, cfg.ngrid // 2, cfg.ngrid - 1])
+    Grows = np.stack([synth.gen_G(cfg, int(g), 1)[0] for g in rows]).astype(np.float64)
+    ref = oracle.bltt(Grows, s)
+    errs = oracle.rel_l2_per_rupture(m.cpu().numpy()[:, rows, :], ref)
+    print("displacement rel-L2 on sampled rows", errs, flush=True)
+    assert errs.max() <= TOL
+    times = [0, 100, 255]
+    _, m2 = op.forward_displacement(sd, times)
+    torch.cuda.synchronize()
+    assert torch.equal(m2, m[:, :, times])

@@ -85,12 +85,15 @@ def _norm_error_scale(G, F, s, dt):
 
 
 def test_small_physical():
-    # Physically shaped operators put most of the output energy past the kept 32-step
-    # window (late arrivals), and some ruptures have no arrival inside it at all.  The
-    # complex64 spectra then carry an error of order eps_32 times the norm-wise scale of
-    # the products, which can exceed 1e-5 of the small kept part.  The bound is error <=
-    # 1e-5 times the larger of ||y|| and that scale; the plain rel-L2 is printed beside it.
-    # (The plain 1e-5 bound is asserted on dense operators and on the Cascadia-shaped share.)
+    # The FFT path does NOT meet the plain float32 bound (rel-L2 <= 1e-5) on this case: the
+    # physically shaped operators put most of the output energy past the kept 32-step window
+    # (late arrivals), so the kept waveform is small against the products that form it, and
+    # the complex64 spectra carry an error of order eps_32 times the norm-wise scale of those
+    # products (plain rel-L2 measured 5.0e-5 on rupture 1).  What is asserted here is a
+    # different bar, the norm-wise one: error <= 1e-5 x max(||y||, that scale).  Rupture 2 has
+    # no arrival in the window (its FP64 reference is exactly zero, so rel-L2 is undefined);
+    # it gets an absolute bound, ||y|| <= 1e-5 x its norm-wise scale.  The direct
+    # time-domain path meets the plain bound on the same ruptures (test_gpu_direct.py).
     cfg = synth.workload("small")
     log_case("small_physical")
     op = make_operator(cfg, max_batch=4)
@@ -101,8 +104,14 @@ def test_small_physical():
     scale = _norm_error_scale(G, F, s, cfg.dt)
     for b in range(4):
         err, ny = np.linalg.norm(y[b] - yr[b]), np.linalg.norm(yr[b])
-        print(f"rupture {b}: |err| {err:.2e}, rel-L2 {err / ny if ny else float('inf'):.2e}, "
-              f"vs norm-wise scale {err / scale[b]:.2e} (scale/||y|| = {scale[b] / ny if ny else float('inf'):.1f})")
+        if ny == 0.0:
+            print(f"rupture {b}: reference exactly zero; ||y|| {err:.2e} against the absolute bound "
+                  f"{TOL * scale[b]:.2e} (1e-5 x norm-wise scale)", flush=True)
+            assert err <= TOL * scale[b]
+            continue
+        plain = err / ny
+        print(f"rupture {b}: plain rel-L2 {plain:.2e} ({'meets' if plain <= TOL else 'does NOT meet'} 1e-5); "
+              f"norm-wise error {err / max(scale[b], ny):.2e} (scale/||y|| = {scale[b] / ny:.1f})", flush=True)
         assert err <= TOL * max(scale[b], ny)
 
 
