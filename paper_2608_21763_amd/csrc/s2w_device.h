@@ -168,9 +168,24 @@ __device__ __forceinline__ int disp_col(const DispOut& d, int n) {
   return (word & bit) ? col + __popc(word & (bit - 1u)) : -1;
 }
 
-__device__ __forceinline__ void disp_put(const DispOut* d, int r, int n, float lval) {
-  if (d && d->base && r < d->rows) {
-    const int c = disp_col(*d, n);
+// Output column of every step n < nt into an LDS table (-1: not selected); all threads of the
+// workgroup call it before the first capture, and a barrier follows before the table is read.
+__device__ __forceinline__ void disp_fill_cols(const DispOut& d, int nt, short* tab) {
+  for (int n = threadIdx.x; n < nt; n += blockDim.x) tab[n] = (short)disp_col(d, n);
+}
+
+// Where the transform rows of one tile or unit go: row r at base + r * row_stride, r < rows.
+struct DispRows {
+  float* base;
+  int64_t row_stride;
+  int rows;
+  float scale;
+};
+
+// Capture sample n of transform row r (unnormalised value lval) through the column table.
+__device__ __forceinline__ void disp_put(const DispRows* d, const short* tab, int r, int n, float lval) {
+  if (d && r < d->rows) {
+    const int c = tab[n];
     if (c >= 0) d->base[(int64_t)r * d->row_stride + c] = lval * d->scale;
   }
 }
@@ -182,7 +197,8 @@ __device__ __forceinline__ void disp_put(const DispOut* d, int r, int n, float l
 // and 1/dt of D_t).  `Y` is [R][M] LDS scratch.  Returns the buffer (X or Y) holding the
 // result.  All threads of the block call it; it ends after a barrier.
 __device__ __forceinline__ float2* lds_midchain2(float2* X, float2* Y, int R, int M, int logM, int nt, int mode,
-                                                 float scale, const Twiddles& tw, const DispOut* disp = nullptr) {
+                                                 float scale, const Twiddles& tw, const DispRows* disp = nullptr,
+                                                 const short* dtab = nullptr) {
   const int n = R * M;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int r = i >> logM, k = i & (M - 1);
@@ -201,7 +217,7 @@ __device__ __forceinline__ float2* lds_midchain2(float2* X, float2* Y, int R, in
       float val = 0.f;
       if (m < nt) {
         const float xm = zsample(zr, m);
-        disp_put(disp, r, m, xm);
+        disp_put(disp, dtab, r, m, xm);
         if (mode == MID_BACKWARD) {
           val = xm - (m > 0 ? zsample(zr, m - 1) : 0.f);
         } else if (mode == MID_BACKWARD_T) {
@@ -313,7 +329,7 @@ __device__ __forceinline__ void fft256_passA(float2 (&v)[16], int c, const float
 // real FFT), with the complex transforms done as two 16-point passes in registers.
 __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int mode, float scale,
                                        const Twiddles& tw, int ldx = 256, int ldt = 256,
-                                       const DispOut* disp = nullptr) {
+                                       const DispRows* disp = nullptr, const short* dtab = nullptr) {
   constexpr int M = 256;
   const int tid = threadIdx.x;
   const int r = tid >> 4, c = tid & 15;
@@ -345,8 +361,8 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int 
       const int n = 16 * n1 + c;
       const float2 z = Xr[n];
       const int m0 = 2 * n, m1 = m0 + 1;
-      if (act && m0 < nt) disp_put(disp, r, m0, z.x);
-      if (act && m1 < nt) disp_put(disp, r, m1, z.y);
+      if (m0 < nt) disp_put(disp, dtab, r, m0, z.x);
+      if (m1 < nt) disp_put(disp, dtab, r, m1, z.y);
       float a = 0.f, b = 0.f;
       if (mode == MID_BACKWARD) {
         const float xm1 = n > 0 ? Xr[n - 1].y : 0.f;

@@ -232,7 +232,10 @@ __global__ __launch_bounds__(256) void k_direct_reduce(const float* __restrict__
   const int t = rev ? nt - 1 - n : n;
   float s = 0.f;
   for (int q = 0; q < parts; ++q) s += pr[(int64_t)q * p_s + t];
-  disp_put(&disp, r, n, s);
+  if (disp.base && r < disp.rows) {
+    const int c = disp_col(disp, n);
+    if (c >= 0) disp.base[(int64_t)r * disp.row_stride + c] = s * disp.scale;
+  }
   if (diff && n > 0) {
     const int t1 = rev ? nt - n : n - 1;
     float s1 = 0.f;

@@ -220,7 +220,7 @@ __device__ __forceinline__ void contract_cols(const v4f* __restrict__ X, const v
 // The seafloor field never leaves the workgroup.  The accumulator (observers o = og + OG*i
 // for the thread's slot pair) is written once, as this workgroup's partial spectrum
 // part[w][o][l] (o < nop).
-template <int T, int OPT>
+template <int T, int OPT, bool DISP>
 __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict__ Gh, const v4f* __restrict__ Fh,
                                                           const v4f* __restrict__ Sh, v4f* __restrict__ part,
                                                           int ngrid, int nsub, int nsp, int nobs, int nop, int M,
@@ -233,6 +233,11 @@ __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict_
   const int tid = threadIdx.x;
   const int NP = M >> 1, OG = 256 / NP;
   float* const disp_m = disp.base;
+  __shared__ short dtab[DISP ? 512 : 1];
+  if (DISP) {
+    disp_fill_cols(disp, nt, dtab);
+    __syncthreads();
+  }
   const int p = tid % NP, og = tid / NP;
   const bool dc = (p == 0);
   const int wg = blockIdx.x, nwg = gridDim.x;
@@ -244,9 +249,8 @@ __global__ __launch_bounds__(256, 1) void k_fused_forward(const v4f* __restrict_
   for (int g0 = r0; g0 < r1; g0 += T) {
     const int tr = min(T, r1 - g0);
     contract_cols<T, false>(Gh, Sh, g0, tr, nsub, nsp, M, U, red);
-    disp.base = disp_m ? disp_m + (int64_t)g0 * disp.row_stride : nullptr;
-    disp.rows = tr;
-    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw, &disp);
+    const DispRows dr{disp_m + (int64_t)g0 * disp.row_stride, disp.row_stride, tr, disp.scale};
+    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw, DISP ? &dr : nullptr, dtab);
     const v4f* fb = Fh + (int64_t)g0 * frow + p;
     for (int t = 0; t < tr; ++t) {
       const float2 va = Vt[t * M + 2 * p], vb = Vt[t * M + 2 * p + 1];
@@ -290,9 +294,14 @@ static hipError_t fused_fwd_t(const float2* Gh, const float2* Fh, const float2* 
                               const Geometry& g, hipStream_t st, const DispOut& disp) {
   const int mode = g.diff ? MID_BACKWARD : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
-  hipLaunchKernelGGL((k_fused_forward<T, OPT>), dim3(nwg), dim3(256), tile_lds(T, g.M), st, (const v4f*)Gh,
-                     (const v4f*)Fh, (const v4f*)Sh, (v4f*)part, g.ngrid, g.nsub, g.nsp, g.nobs, g.nop, g.M, g.logM,
-                     g.nt, mode, mscale, disp);
+  if (disp.base)
+    hipLaunchKernelGGL((k_fused_forward<T, OPT, true>), dim3(nwg), dim3(256), tile_lds(T, g.M), st, (const v4f*)Gh,
+                       (const v4f*)Fh, (const v4f*)Sh, (v4f*)part, g.ngrid, g.nsub, g.nsp, g.nobs, g.nop, g.M, g.logM,
+                       g.nt, mode, mscale, disp);
+  else
+    hipLaunchKernelGGL((k_fused_forward<T, OPT, false>), dim3(nwg), dim3(256), tile_lds(T, g.M), st, (const v4f*)Gh,
+                       (const v4f*)Fh, (const v4f*)Sh, (v4f*)part, g.ngrid, g.nsub, g.nsp, g.nobs, g.nop, g.M, g.logM,
+                       g.nt, mode, mscale, disp);
   return hipGetLastError();
 }
 
@@ -359,7 +368,7 @@ hipError_t launch_sum_parts(const float2* part, int nparts, int64_t items_c, flo
 //   forward (CONJ = false):  Out = mid(sum_j Gh[g][j][l] Sh[j][l]),            D_t
 //   adjoint (CONJ = true):   Out = mid(sum_o conj(Fh[g][o][l]) Rh[o][l]),      D_t transposed
 // Used by the single-rupture adjoint and by the unfused forward.
-template <int T, bool CONJ>
+template <int T, bool CONJ, bool DISP = false>
 __global__ __launch_bounds__(256) void k_rows_mid(const v4f* __restrict__ X, const v4f* __restrict__ Y,
                                                   float2* __restrict__ Out, int ngrid, int nc, int ncp, int M,
                                                   int logM, int nt, int mode, float mscale, DispOut disp) {
@@ -371,12 +380,16 @@ __global__ __launch_bounds__(256) void k_rows_mid(const v4f* __restrict__ X, con
   const int wg = blockIdx.x, nwg = gridDim.x;
   const int r0 = (int)((int64_t)ngrid * wg / nwg), r1 = (int)((int64_t)ngrid * (wg + 1) / nwg);
   float* const disp_m = disp.base;
+  __shared__ short dtab[DISP ? 512 : 1];
+  if (DISP) {
+    disp_fill_cols(disp, nt, dtab);
+    __syncthreads();
+  }
   for (int g0 = r0; g0 < r1; g0 += T) {
     const int tr = min(T, r1 - g0);
     contract_cols<T, CONJ>(X, Y, g0, tr, nc, ncp, M, U, red);
-    disp.base = disp_m ? disp_m + (int64_t)g0 * disp.row_stride : nullptr;
-    disp.rows = tr;
-    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw, &disp);
+    const DispRows dr{disp_m + (int64_t)g0 * disp.row_stride, disp.row_stride, tr, disp.scale};
+    const float2* Vt = lds_midchain2(U, BA, T, M, logM, nt, mode, mscale, tw, DISP ? &dr : nullptr, dtab);
     for (int i = threadIdx.x; i < tr * M; i += blockDim.x) Out[(int64_t)g0 * M + i] = Vt[i];
     __syncthreads();
   }
@@ -399,8 +412,12 @@ hipError_t launch_forward_rows(const float2* Gh, const float2* Sh, float2* Vh, i
                                hipStream_t st, const DispOut& disp) {
   const int mode = g.diff ? MID_BACKWARD : MID_NONE;
   const float mscale = (float)(1.0 / ((double)g.L * (g.diff ? (double)g.dt : 1.0)));
-  hipLaunchKernelGGL((k_rows_mid<8, false>), dim3(nwg), dim3(256), tile_lds(8, g.M), st, (const v4f*)Gh,
-                     (const v4f*)Sh, Vh, g.ngrid, g.nsub, g.nsp, g.M, g.logM, g.nt, mode, mscale, disp);
+  if (disp.base)
+    hipLaunchKernelGGL((k_rows_mid<8, false, true>), dim3(nwg), dim3(256), tile_lds(8, g.M), st, (const v4f*)Gh,
+                       (const v4f*)Sh, Vh, g.ngrid, g.nsub, g.nsp, g.M, g.logM, g.nt, mode, mscale, disp);
+  else
+    hipLaunchKernelGGL((k_rows_mid<8, false, false>), dim3(nwg), dim3(256), tile_lds(8, g.M), st, (const v4f*)Gh,
+                       (const v4f*)Sh, Vh, g.ngrid, g.nsub, g.nsp, g.M, g.logM, g.nt, mode, mscale, disp);
   return hipGetLastError();
 }
 
@@ -501,7 +518,7 @@ __device__ __forceinline__ void store_v(float2* dst, float2 v, float f) {
 }
 
 // General M: rows staged through a padded transposition buffer, generic LDS transforms.
-template <int R, int PACK>
+template <int R, int PACK, bool DISP>
 __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const float* __restrict__ sF, int ngrid,
                                                    int B, int bp, int M, int logM, int nt, int mode, float mscale,
                                                    DispOut disp) {
@@ -514,6 +531,11 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
   const Twiddles tw = lds_twiddles(Y + BUF, M);
   const int nbb = (B + R - 1) / R;
   const int64_t units = (int64_t)ngrid * nbb;
+  __shared__ short dtab[DISP ? 512 : 1];
+  if (DISP) {
+    disp_fill_cols(disp, nt, dtab);
+    __syncthreads();
+  }
   for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
     const int g = (int)(u / nbb);
     const int b0 = (int)(u % nbb) * R;
@@ -528,10 +550,9 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
       X[i] = Y[l * (R + 1) + r];
     }
     __syncthreads();
-    DispOut d = disp;
-    d.base = disp.base ? disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride : nullptr;
-    d.rows = B - b0;
-    const float2* V = lds_midchain2(X, Y, R, M, logM, nt, mode, mscale, tw, &d);
+    const DispRows dr{disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride, disp.row_stride,
+                      B - b0, disp.scale};
+    const float2* V = lds_midchain2(X, Y, R, M, logM, nt, mode, mscale, tw, DISP ? &dr : nullptr, dtab);
     float2* Tp = (V == X) ? Y : X;
     for (int i = threadIdx.x; i < R * M; i += blockDim.x) {
       const int r = i >> logM, l = i & (M - 1);
@@ -553,7 +574,7 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
 // With cmax, the grid is a multiple of the rupture blocks per row (nbb), so a workgroup always
 // works on the same block of ruptures; it keeps the largest |Re|, |Im| of every (slot, rupture)
 // it writes and leaves them in cmax[blockIdx / nbb][l][b] (b < bp; zero for b >= B).
-template <int PACK, int R>
+template <int PACK, int R, bool DISP>
 __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF,
                                                          int ngrid, int B, int bp, int nt, int mode, float mscale,
                                                          float* __restrict__ cmax, DispOut disp) {
@@ -561,6 +582,8 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
   __shared__ float2 X[R * LD];
   __shared__ float2 T[R * 16 * 17];
   __shared__ float2 twb[2 * M];
+  __shared__ short dtab[DISP ? 512 : 1];
+  if (DISP) disp_fill_cols(disp, nt, dtab);  // the barrier in lds_twiddles orders it
   const Twiddles tw = lds_twiddles(twb, M);
   const int tid = threadIdx.x;
   const int r = tid % R, lq = tid / R;  // gather/scatter: rupture r, slots lq + 16 k
@@ -594,11 +617,10 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
     for (int k = 0; k < 16; ++k) f[k] = fs[k];
     __syncthreads();
     if (u + gridDim.x < units) fetch(u + gridDim.x);
-    DispOut d = disp;
     const int b0 = (int)(u % nbb) * R;
-    d.base = disp.base ? disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride : nullptr;
-    d.rows = B - b0;
-    mid256(X, T, R, nt, mode, mscale, tw, LD, LD, &d);
+    const DispRows dr{disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride, disp.row_stride,
+                      B - b0, disp.scale};
+    mid256(X, T, R, nt, mode, mscale, tw, LD, LD, DISP ? &dr : nullptr, dtab);
     float2* dst = U + (int64_t)g * M * bp + b;
     if (b < B) {
 #pragma unroll
@@ -647,8 +669,14 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
       if (cmax_groups) *cmax_groups = (int)groups;
     }
 #define S2W_MID256(P_, R_)                                                                                       \
-  hipLaunchKernelGGL((k_mid_batch256<P_, R_>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF, g.ngrid, B, bp, \
-                     g.nt, mode, mscale, cmax, dd)
+  do {                                                                                                            \
+    if (dd.base)                                                                                                  \
+      hipLaunchKernelGGL((k_mid_batch256<P_, R_, true>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF,        \
+                         g.ngrid, B, bp, g.nt, mode, mscale, cmax, dd);                                            \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_mid_batch256<P_, R_, false>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF,       \
+                         g.ngrid, B, bp, g.nt, mode, mscale, cmax, dd);                                            \
+  } while (0)
     if (ru == 32) {
       if (pack_bf16) S2W_MID256(1, 32); else S2W_MID256(0, 32);
     } else {
@@ -658,12 +686,15 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
     return hipGetLastError();
   }
   const size_t lds = (2 * (size_t)g.M * (R + 1) + 2 * (size_t)g.M) * sizeof(float2);
-  if (pack_bf16)
-    hipLaunchKernelGGL((k_mid_batch<R, 1>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M,
-                       g.logM, g.nt, mode, mscale, dd);
-  else
-    hipLaunchKernelGGL((k_mid_batch<R, 0>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M,
-                       g.logM, g.nt, mode, mscale, dd);
+#define S2W_MIDG(P_, D_)                                                                                        \
+  hipLaunchKernelGGL((k_mid_batch<R, P_, D_>), dim3((unsigned)nblk), dim3(256), lds, st, U, sF, g.ngrid, B, bp, g.M, \
+                     g.logM, g.nt, mode, mscale, dd)
+  if (pack_bf16) {
+    if (dd.base) S2W_MIDG(1, true); else S2W_MIDG(1, false);
+  } else {
+    if (dd.base) S2W_MIDG(0, true); else S2W_MIDG(0, false);
+  }
+#undef S2W_MIDG
   return hipGetLastError();
 }
 
