@@ -194,7 +194,7 @@ typedef struct s2w_tuning {
   int32_t fused_rows;        /* single-rupture fused kernel: grid rows per tile (4 or 8) */
   int32_t adj_cols;          /* grid-row contractions (adjoint elastic stage): columns per thread (8 or 16) */
   int32_t adj_splits;        /* single-rupture adjoint: grid splits of the transposed elastic stage */
-  int32_t batch_path_min_b;  /* smallest B that takes the batched matrix-core path */
+  int32_t batch_path_min_b;  /* reserved: ignored (the layout, fixed at plan creation, picks the path) */
   int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..18 fixed shapes, 4 = narrow */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
   int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (eight-wave kernel on real-column

@@ -409,7 +409,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.fused_rows = 8;
   p->tune.adj_cols = 16;
   p->tune.adj_splits = 16;
-  p->tune.batch_path_min_b = 1 << 30;
+  p->tune.batch_path_min_b = 0;
   p->tune.gemm_cfg = -1;
   p->tune.fgemm_splits = 0;
   p->tune.fgemm_lds = 1;
@@ -512,9 +512,8 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     if (t->adj_splits < 1 || t->adj_splits > kMaxSplits) return fail(p, S2W_EINVAL, "tuning: adj_splits");
     n.adj_splits = t->adj_splits;
   }
-  if (t->batch_path_min_b) n.batch_path_min_b = t->batch_path_min_b;
   if (t->gemm_cfg) {
-    if (t->gemm_cfg < -1 || t->gemm_cfg > 18) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    if (t->gemm_cfg < -1 || t->gemm_cfg > 20) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) {
@@ -560,6 +559,10 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
 s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   if (!p || !t) return S2W_EINVAL;
   *t = p->tune;
+  // internal codes back to the public ones, so that get -> set round-trips
+  t->gemm_cfg = p->tune.gemm_cfg == 0 ? 4 : p->tune.gemm_cfg;
+  t->fgemm_lds = p->tune.fgemm_lds == 0 ? -1 : p->tune.fgemm_lds;
+  t->batch_path_min_b = 0;
   t->gemm32_cfg = p->tune.gemm32_cfg < 0 ? -1 : p->tune.gemm32_cfg + 1;
   t->gemm32_cfg_k = p->tune.gemm32_cfg_k < 0 ? -1 : p->tune.gemm32_cfg_k + 1;
   t->hadj_tile_f = p->tune.hadj_tile_f < 0 ? -1 : p->tune.hadj_tile_f + 1;
@@ -749,7 +752,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (e == hipSuccess) {
     if (compact)
       e = launch_prep_act_compact(h.ht_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (uint2*)Bop, st);
-    else if (cfg == 17 || cfg == 18)
+    else if (cfg >= 17 && cfg <= 20)
       e = launch_prep_act_re(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (B + 15) / 16,
                              Bop, st);
     else

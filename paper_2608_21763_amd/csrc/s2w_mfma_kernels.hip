@@ -891,6 +891,23 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
                            sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
       break;
     }
+    case 19:
+    case 20: {
+      // one wave per SIMD with 128 x 128 wave tiles on real-column activation fragments, three
+      // stages: 19 = 256 rows x 256 columns (2 x 2 waves), 20 = 128 rows x 512 columns (1 x 4
+      // waves: 256 ruptures in one column tile, so the operator is read once per slot)
+      const int nrcb = (B + 15) / 16;
+      const int WR = cfg == 19 ? 2 : 1, WC = cfg == 19 ? 2 : 4;
+      const int nrb = (ngrid + 128 * WR - 1) / (128 * WR);
+      const int nct = (nrcb + 4 * WC - 1) / (4 * WC);
+      if (cfg == 19)
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 3, 2, 2, 1, true>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop,
+                           sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
+      else
+        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 3, 1, 4, 1, true>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop,
+                           sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
+      break;
+    }
     case 10:
     case 11:
     case 12: {
