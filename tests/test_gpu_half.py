@@ -1,9 +1,11 @@
 """Batched matrix-core path with half-precision operator spectra, through the C-ABI.
 
-Parity is stated as rel-L2 per rupture against the FP64 oracle (which uses the
-unquantized float32 operators, so quantization error is included).  Bounds:
-float16 stores <= 2e-3 (the half-precision bound); bfloat16 stores carry an
-8-bit mantissa and are checked against 1e-2 here, their rel-L2 being stated.
+Parity is stated as rel-L2 per rupture and as the element-wise error
+max |y - y_ref| / max |y_ref| against the FP64 oracle (which uses the unquantized
+float32 operators, so quantization error is included).  Float16 stores are held to the
+half-precision bound 2e-3 on both.  Stores with a bfloat16 operator do not meet 2e-3 on these
+dense iid operators; they are held to the regression ceiling of ``gpu_util.BF16_CEILING`` and
+every check prints whether 2e-3 is met.
 """
 import numpy as np
 import pytest
@@ -11,11 +13,11 @@ import torch
 
 import oracle
 import synth
-from gpu_util import log_case, make_operator, to_dev
+from gpu_util import half_limit, log_case, make_operator, report_half, to_dev
 
 pytestmark = pytest.mark.gpu
 
-BOUND = {("f16", "f16"): 2e-3, ("bf16", "f16"): 1e-2, ("f16", "bf16"): 1e-2, ("bf16", "bf16"): 1e-2}
+BOUND = {(g, f): half_limit(g, f) for g in ("bf16", "f16") for f in ("bf16", "f16")}
 
 
 @pytest.fixture(autouse=True)
@@ -30,9 +32,11 @@ def _check(cfg, op, B, dt, diff, first=0, dtypes=("bf16", "bf16")):
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
     yr = oracle.forward(G, F, s, dt=dt, diff=diff)
     errs = oracle.rel_l2_per_rupture(y, yr)
+    mabs = oracle.max_abs_rel_per_rupture(y, yr)
     print(dtypes, "B", B, "rel-L2 per rupture", " ".join(f"{e:.2e}" for e in errs))
+    report_half(f"{dtypes[0]}/{dtypes[1]} B={B}", errs, mabs)
     assert np.all(np.isfinite(y))
-    assert errs.max() <= BOUND[tuple(dtypes)]
+    assert errs.max() <= BOUND[tuple(dtypes)] and mabs.max() <= BOUND[tuple(dtypes)]
     return errs
 
 
@@ -74,10 +78,13 @@ def _check_adjoint(cfg, op, B, dt, dtypes, first=0):
     g = op.adjoint(to_dev(r)).cpu().numpy()
     y = op.forward(to_dev(s)).cpu().numpy()
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
-    errs = oracle.rel_l2_per_rupture(g, oracle.adjoint(G, F, r, dt=dt))
+    gr = oracle.adjoint(G, F, r, dt=dt)
+    errs = oracle.rel_l2_per_rupture(g, gr)
+    mabs = oracle.max_abs_rel_per_rupture(g, gr)
     print(dtypes, "adjoint B", B, "rel-L2 per rupture", " ".join(f"{e:.2e}" for e in errs))
+    report_half(f"{dtypes[0]}/{dtypes[1]} adjoint B={B}", errs, mabs)
     assert np.all(np.isfinite(g))
-    assert errs.max() <= BOUND[tuple(dtypes)]
+    assert errs.max() <= BOUND[tuple(dtypes)] and mabs.max() <= BOUND[tuple(dtypes)]
     for b in range(min(B, 4)):
         lhs = np.sum(y[b].astype(np.float64) * r[b])
         rhs = np.sum(s[b].astype(np.float64) * g[b])
@@ -171,17 +178,19 @@ def test_mid_chain_unit_sizes_agree(dtype):
     assert oracle.rel_l2_per_rupture(out[16][1].cpu().numpy(), oracle.adjoint(G, F, r)).max() <= bound
 
 
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
 @pytest.mark.parametrize("B", [40, 130])
-def test_elastic_gemm_tile_shapes_agree(B):
+def test_elastic_gemm_tile_shapes_agree(B, dtype):
     # every tile shape accumulates each output over the same K steps in the same order, so all
-    # shapes give bit-identical waveforms; the shared result is checked against the oracle
+    # shapes give bit-identical waveforms (bf16: both activation terms; f16: one); the shared
+    # result is checked against the oracle
     cfg = synth.SynthConfig(nsub=70, ngrid=300, nobs=20, nt=64, seed=93, slip_seed=94, op_kind="dense",
                             slip_mode="dense")
-    log_case("half_tiles", B=B)
-    op = make_operator(cfg, max_batch=B, g_dtype="f16", f_dtype="f16")
+    log_case("half_tiles", B=B, dtype=dtype)
+    op = make_operator(cfg, max_batch=B, g_dtype=dtype, f_dtype=dtype)
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
     outs = {}
-    for c in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18):
+    for c in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20):
         op.set_tuning(gemm_cfg=c)
         outs[c] = op.forward(s).clone()
     for c in outs:
@@ -189,8 +198,22 @@ def test_elastic_gemm_tile_shapes_agree(B):
     y = outs[4].cpu().numpy()
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
     errs = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s.cpu().numpy().astype(np.float64)))
-    print("rel-L2 max", errs.max())
-    assert errs.max() <= BOUND[("f16", "f16")]
+    print(dtype, "rel-L2 max", errs.max())
+    assert errs.max() <= BOUND[(dtype, dtype)]
+
+
+def test_tuning_round_trip():
+    # what s2w_get_tuning returns, given back to s2w_set_tuning, keeps every setting
+    cfg = synth.SynthConfig(nsub=20, ngrid=64, nobs=4, nt=32, seed=1, slip_seed=2, op_kind="dense", slip_mode="dense")
+    op = make_operator(cfg, max_batch=8, g_dtype="bf16", f_dtype="bf16")
+    for kw in ({"gemm_cfg": 4, "fgemm_lds": -1}, {"gemm_cfg": 18, "fgemm_lds": 3}, {"gemm_cfg": -1, "fgemm_lds": 1}):
+        op.set_tuning(**kw)
+        t = op.get_tuning()
+        for k, v in kw.items():
+            assert t[k] == v, (k, t[k], v)
+        op.set_tuning(**{"gemm_cfg": 12, "fgemm_lds": 2})
+        op.set_tuning(**t)
+        assert op.get_tuning() == t
 
 
 @pytest.mark.parametrize("B,nobs", [(40, 20), (130, 20), (40, 120), (130, 120), (257, 50)])

@@ -8,15 +8,16 @@ import torch
 
 import oracle
 import synth
-from gpu_util import log_case, make_operator, to_dev
+from gpu_util import BF16_CEILING, HALF_BOUND, log_case, make_operator, to_dev
 
 pytestmark = pytest.mark.gpu
 
 PATHS = {
     "single": (dict(layout="single"), 1e-5),
     "batched32": (dict(layout="batched"), 1e-5),
-    "f16": (dict(g_dtype="f16", f_dtype="f16"), 2e-3),
-    "bf16": (dict(g_dtype="bf16", f_dtype="bf16"), 1e-2),
+    "f16": (dict(g_dtype="f16", f_dtype="f16"), HALF_BOUND),
+    # bf16 stores do not meet the 2e-3 bound on dense iid operators: a regression ceiling
+    "bf16": (dict(g_dtype="bf16", f_dtype="bf16"), BF16_CEILING),
 }
 
 
