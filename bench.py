@@ -49,7 +49,6 @@ KERNEL_SOURCES = {
     "k_fused_forward": ["s2w_fft_kernels.hip", "s2w_device.h"],
     "k_mid_batch256": ["s2w_fft_kernels.hip", "s2w_device.h"],
     "k_gemm_g": ["s2w_mfma_kernels.hip", "s2w_half.h"],
-    "k_gemm_g2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
     "k_gemm_g4": ["s2w_mfma_kernels.hip", "s2w_half.h"],
     "k_gemm_f2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
     "k_gemm_t2": ["s2w_mfma_adj_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
@@ -86,13 +85,7 @@ def traffic_for(kernel: str):
 
 def elastic_kernel(cfg: int) -> str:
     """Kernel of the batched half-precision elastic GEMM for tile setting `cfg` (-1 automatic)."""
-    if cfg in (-1, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20):
-        return "k_gemm_g4"
-    if cfg in (7, 8, 9):
-        return "k_gemm_g3"
-    if cfg in (5, 6):
-        return "k_gemm_g2"
-    return "k_gemm_g"
+    return "k_gemm_g" if cfg == 4 else "k_gemm_g4"
 
 
 def headline_reference(bcfg, B: int, s_batch):
@@ -529,7 +522,7 @@ def main():
         result["adj"] = adj_path(args.batch_adj, "f32", "fp32 batched", "k_cgemm32 (transposed elastic)",
                                  MFMA_PEAK["f32"], layout="batched")
     if "hadj" in paths:
-        result["hadj"] = adj_path(args.batch, "bf16", "bf16 batched", "k_gemm_t (transposed elastic)",
+        result["hadj"] = adj_path(args.batch, "bf16", "bf16 batched", "k_gemm_t2 (transposed elastic)",
                                   MFMA_PEAK["bf16"])
 
     # ---------------- elastic operator alone (seafloor displacement of the share) ----------------

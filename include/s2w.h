@@ -195,14 +195,21 @@ typedef struct s2w_tuning {
   int32_t adj_cols;          /* grid-row contractions (adjoint elastic stage): columns per thread (8 or 16) */
   int32_t adj_splits;        /* single-rupture adjoint: grid splits of the transposed elastic stage */
   int32_t batch_path_min_b;  /* reserved: ignored (the layout, fixed at plan creation, picks the path) */
-  int32_t gemm_cfg;          /* batched elastic GEMM tile: -1 automatic, 1..3, 5..18 fixed shapes, 4 = narrow */
+  int32_t gemm_cfg;          /* batched elastic GEMM tile, 256 grid rows tall, persistent workgroups:
+                                -1 automatic (12 for B <= 64, else 18); 4 = 16 columns (four waves,
+                                register operands); 10 = 256 columns (eight waves, three-stage LDS copy
+                                pipeline); 12 = 128 columns (eight waves, four stages); 16 = 128 columns
+                                (four waves, two stages, two workgroups per compute unit); 17, 18 = 256
+                                columns on real-column activation fragments (eight waves, four and three
+                                stages).  A rupture takes two columns (real and imaginary part).  All
+                                tiles give the same results bit for bit. */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
-  int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (eight-wave kernel on real-column
-                                activation fragments for f16 and for bf16 with B > 64, else the
-                                LDS-staged kernel), 2 eight-wave kernel on full fragments, 3 eight-wave
+  int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (LDS-staged kernel for bf16 with
+                                B <= 64 where its tile fits, else the eight-wave kernel on real-column
+                                activation fragments), 2 eight-wave kernel on full fragments, 3 eight-wave
                                 kernel on real-column fragments (2 and 3 give the same results bit for
-                                bit), 4 LDS-staged kernel on packed bf16 activations (f16: as 3),
-                                -1 register kernel */
+                                bit), 4 LDS-staged kernel on packed bf16 activations where its tile fits
+                                (else, and for f16, as 3) */
   int32_t gemm32_cfg;        /* batched float32 GEMMs over grid rows (forward elastic, adjoint acoustic): tile,
                                 -1 automatic, 1..4 = rows x ruptures 64 x 128, 128 x 32, 256 x 8, 64 x 64 */
   int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint
@@ -210,11 +217,10 @@ typedef struct s2w_tuning {
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
   int32_t adj32_splits;      /* batched adjoint (float32 and half stores), transposed elastic GEMM: grid-row
                                 splits (1..8; half stores may clamp to what the partial region holds) */
-  int32_t hadj_tile_f;       /* half-precision adjoint, transposed acoustic GEMM tile: -1 automatic, 1..8 =
-                                rows x columns 64 x 256, 256 x 64 (four waves), 256 x 64, 256 x 128,
-                                256 x 256 (eight waves, both operands through LDS), then 6..8 = tiles
-                                3..5 holding only real-column activation fragments in LDS (same
-                                results bit for bit) */
+  int32_t hadj_tile_f;       /* half-precision adjoint, transposed acoustic GEMM tile (eight waves, both
+                                operands through LDS): -1 automatic, 3 = 256 x 64 rows x columns, 4 =
+                                256 x 128, then 6..8 = 256 x 64, 256 x 128, 256 x 256 holding only
+                                real-column activation fragments in LDS (same results bit for bit) */
   int32_t hadj_tile_g;       /* half-precision adjoint, transposed elastic GEMM tile: same values */
   int32_t mid_rupts;         /* batched mid-chain (Nt = 256): ruptures per work unit, 16 or 32 */
 } s2w_tuning;

@@ -33,15 +33,12 @@ def candidates(op, adjoint: bool = False) -> list[dict]:
         return [{}]  # the direct layout has no tile controls
     if adjoint:
         if op.g_dtype != "f32":
-            return [{"hadj_tile_f": a, "hadj_tile_g": b} for a in (1, 3, 4, 5, 6, 7, 8)
-                    for b in (3, 4, 5, 6, 7, 8)]
+            return [{"hadj_tile_f": a, "hadj_tile_g": b} for a, b in itertools.product((3, 4, 6, 7, 8), repeat=2)]
         if op.plan_layout() == "batched":
             return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
         return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]
     if op.g_dtype != "f32":
-        return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18,
-                                                           19, 20)
-                for f in (3, 4, 2, -1)]
+        return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 10, 12, 16, 17, 18) for f in (3, 4, 2)]
     if op.plan_layout() == "batched":
         return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
     return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]

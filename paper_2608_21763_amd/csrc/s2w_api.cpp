@@ -513,12 +513,14 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.adj_splits = t->adj_splits;
   }
   if (t->gemm_cfg) {
-    if (t->gemm_cfg < -1 || t->gemm_cfg > 20) return fail(p, S2W_EINVAL, "tuning: gemm_cfg");
+    const int c = t->gemm_cfg;
+    if (!(c == -1 || c == 4 || c == 10 || c == 12 || (c >= 16 && c <= 18)))
+      return fail(p, S2W_EINVAL, "tuning: gemm_cfg must be -1, 4, 10, 12, 16, 17 or 18");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) {
-    if (t->fgemm_lds > 4) return fail(p, S2W_EINVAL, "tuning: fgemm_lds");
-    n.fgemm_lds = t->fgemm_lds > 0 ? t->fgemm_lds : 0;
+    if (t->fgemm_lds < 1 || t->fgemm_lds > 4) return fail(p, S2W_EINVAL, "tuning: fgemm_lds must be 1..4");
+    n.fgemm_lds = t->fgemm_lds;
   }
   if (t->gemm32_cfg) {
     if (t->gemm32_cfg < -1 || t->gemm32_cfg > 4) return fail(p, S2W_EINVAL, "tuning: gemm32_cfg");
@@ -541,7 +543,9 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.fgemm_splits = t->fgemm_splits;
   }
   if (t->hadj_tile_f) {
-    if (t->hadj_tile_f < -1 || t->hadj_tile_f > 8) return fail(p, S2W_EINVAL, "tuning: hadj_tile_f");
+    const int c = t->hadj_tile_f;
+    if (!(c == -1 || c == 3 || c == 4 || (c >= 6 && c <= 8)))
+      return fail(p, S2W_EINVAL, "tuning: hadj_tile_f must be -1, 3, 4, 6, 7 or 8");
     n.hadj_tile_f = t->hadj_tile_f < 0 ? -1 : t->hadj_tile_f - 1;
   }
   if (t->mid_rupts) {
@@ -549,7 +553,9 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
     n.mid_rupts = t->mid_rupts;
   }
   if (t->hadj_tile_g) {
-    if (t->hadj_tile_g < -1 || t->hadj_tile_g > 8) return fail(p, S2W_EINVAL, "tuning: hadj_tile_g");
+    const int c = t->hadj_tile_g;
+    if (!(c == -1 || c == 3 || c == 4 || (c >= 6 && c <= 8)))
+      return fail(p, S2W_EINVAL, "tuning: hadj_tile_g must be -1, 3, 4, 6, 7 or 8");
     n.hadj_tile_g = t->hadj_tile_g < 0 ? -1 : t->hadj_tile_g - 1;
   }
   p->tune = n;
@@ -561,7 +567,6 @@ s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   *t = p->tune;
   // internal codes back to the public ones, so that get -> set round-trips
   t->gemm_cfg = p->tune.gemm_cfg == 0 ? 4 : p->tune.gemm_cfg;
-  t->fgemm_lds = p->tune.fgemm_lds == 0 ? -1 : p->tune.fgemm_lds;
   t->batch_path_min_b = 0;
   t->gemm32_cfg = p->tune.gemm32_cfg < 0 ? -1 : p->tune.gemm32_cfg + 1;
   t->gemm32_cfg_k = p->tune.gemm32_cfg_k < 0 ? -1 : p->tune.gemm32_cfg_k + 1;
@@ -730,29 +735,21 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   if (cfg < 0) cfg = B <= 64 ? 12 : 18;
   // acoustic GEMM: fgemm_lds 2 takes the eight-wave kernel on full activation fragments, 3 the
   // eight-wave kernel on real-column fragments (with either the mid-chain leaves complex64),
-  // 4 the LDS-staged kernel for packed bfloat16 activations (when its tile fits; float16: as
-  // 3), 0 the register kernel, and 1 chooses: the real-column eight-wave kernel for float16
-  // and for bfloat16 batches that give each wave two column blocks (B > 64; Cascadia-sized
-  // share, bf16: 26.9 against 30.4 ms per call at B = 128, 51.3 against 52.5 ms at B = 256),
-  // the LDS-staged kernel for smaller bfloat16 batches
+  // 4 the LDS-staged kernel for packed bfloat16 activations where its tile fits (else, and for
+  // float16, as 3), and 1 chooses: the LDS-staged kernel for bfloat16 batches of at most 64
+  // where it fits, the real-column eight-wave kernel otherwise (Cascadia-sized share, bf16:
+  // 26.9 against 30.4 ms per call at B = 128, 51.3 against 52.5 ms at B = 256)
   const int fl = p->tune.fgemm_lds;
   const bool bf16_act = h.ht_f == 1 && h.hterms_f == 2;
-  const bool wide = fl == 2 || fl == 3 || ((fl == 1 || fl == 4) && !bf16_act) || (fl == 1 && B > 64);
-  const bool wide_re = wide && fl != 2;
-  const bool packed = bf16_act && !wide;
-  const bool fstaged = packed && (fl == 1 || fl == 4) && gemm_f2_supported(h.noq, B);
-  const int zt = wide ? ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B, wide_re)
-                      : fstaged ? gemm_f2_col_tiles(B)
-                                : ((ncb > 8 && h.noq <= 64) ? (ncb + 31) / 32 : (ncb + 7) / 8);  // column tiles
+  const bool fstaged = bf16_act && gemm_f2_supported(h.noq, B) && (fl == 4 || (fl == 1 && B <= 64));
+  const bool wide_re = fl != 2;
+  const int zt = fstaged ? gemm_f2_col_tiles(B) : ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B, wide_re);
   int splits = p->tune.fgemm_splits;
   if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
   splits = std::min(splits, h.splits_max);
   hipError_t e = launch_rfft_rows(s, B, g.nsub, h.nsq, S, 1, bp, (int64_t)h.nsq * bp, g, 1.0f, st);
-  const bool compact = cfg >= 7 && cfg <= 9;
   if (e == hipSuccess) {
-    if (compact)
-      e = launch_prep_act_compact(h.ht_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (uint2*)Bop, st);
-    else if (cfg >= 17 && cfg <= 20)
+    if (cfg == 17 || cfg == 18)
       e = launch_prep_act_re(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (B + 15) / 16,
                              Bop, st);
     else
@@ -762,12 +759,8 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   e = mark(p->ev_begin, st);
   if (e == hipSuccess) {
     const int nwg = p->ncu * p->tune.fused_wg_per_cu;
-    if (compact)
-      e = launch_gemm_g3(h.ht_g, h.hterms_g, cfg, Gq, sG, (const uint2*)Bop, sig_down, (float*)U, nwg, g.ngrid, g.M,
-                         h.nks, B, bp, st);
-    else
-      e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, ncb, B,
-                        bp, st);
+    e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, ncb, B, bp,
+                      st);
   }
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
@@ -775,7 +768,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   // float16 acoustic operands: the column scales come from maxima the mid-chain keeps as it
   // writes (M = 256), else from a pass over U
   int groups = 0;
-  e = launch_mid_batch(U, sF, B, bp, false, packed, g, st, p->tune.mid_rupts, fscale ? part : nullptr,
+  e = launch_mid_batch(U, sF, B, bp, false, fstaged, g, st, p->tune.mid_rupts, fscale ? part : nullptr,
                        part_floats(p), &groups, disp);
   if (e != hipSuccess) return hip_fail(p, e, "forward: mid-chain");
   if (fscale) {
@@ -783,15 +776,13 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
                    : launch_col_scale(U, g.ngrid, g.M, B, bp, tau_up, tau_down, part, part_floats(p), st);
     if (e != hipSuccess) return hip_fail(p, e, "forward: activation scale");
   }
-  if (wide) {
+  if (fstaged) {
+    e = launch_gemm_f2(Fq, (const uint2*)U, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, splits, st);
+  } else {
     splits = std::min(splits, h.ngq / 16);
     e = launch_gemm_fw(h.ht_f, h.hterms_f, (const uint32_t*)Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq,
                        g.M, h.noq, g.nobs, B, bp, splits, wide_re, st);
-  } else if (fstaged)
-    e = launch_gemm_f2(Fq, (const uint2*)U, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, splits, st);
-  else
-    e = launch_gemm_f(h.ht_f, h.hterms_f, packed, Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq, g.M, h.noq,
-                      B, bp, ncb, splits, st);
+  }
   if (e == hipSuccess)
     e = launch_sum_f(part, splits, g.M, h.noq, g.nobs, B, bp, fscale ? tau_down : nullptr, yh, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");
@@ -949,8 +940,8 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   const int shape3 =
       p->tune.hadj_tile_g >= 0 ? p->tune.hadj_tile_g : (B <= 32 ? 5 : (sg16 && B > 128) ? 7 : 6);
   const int sh3 = shape3 >= 5 ? shape3 - 3 : shape3;
-  const int cols3 = sh3 == 0 ? 256 : sh3 == 1 ? 64 : sh3 == 2 ? 64 : (sh3 == 3 ? 128 : 256);
-  const int rows3 = shape3 == 0 ? 64 : 256;
+  const int cols3 = sh3 == 2 ? 64 : (sh3 == 3 ? 128 : 256);
+  const int rows3 = 256;
   const int tiles = g.M * ((g.nsub + rows3 - 1) / rows3) * ((2 * B + cols3 - 1) / cols3);
   const int fit = std::max(1, std::max(h.splits_max * h.noq, h.nsq) / h.nsq);
   int sa = p->tune.adj32_splits > 0 ? p->tune.adj32_splits : std::max(1, 2048 / std::max(1, tiles));

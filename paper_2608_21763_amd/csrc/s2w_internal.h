@@ -92,11 +92,6 @@ hipError_t launch_prep_act_re(int ht, int hterms, const float2* S, float* sig_up
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
                          hipStream_t st);
-hipError_t launch_prep_act_compact(int ht, const float2* S, float* sig_up, float* sig_down, int M, int nsub, int nsq,
-                                   int B, int bp, int nks, uint2* Sc, hipStream_t st);
-hipError_t launch_gemm_g3(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint2* Sc,
-                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int B, int bp,
-                          hipStream_t st);
 // LDS-staged acoustic GEMM (packed bfloat16 activation): supported observer paddings and the
 // number of rupture tiles it launches for a batch of B.
 inline bool gemm_f2_supported(int noq, int B) {
@@ -134,9 +129,6 @@ hipError_t launch_col_scale_final(const float* part, int splits, int M, int B, i
                                   hipStream_t st);
 hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, float* tau_up, float* tau_down,
                             float* part, int64_t part_floats, hipStream_t st);
-hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,
-                         float* part, int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits,
-                         hipStream_t st);
 hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs, int B, int bp, const float* tau_down,
                         float2* yh, hipStream_t st);
 hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st);

@@ -42,150 +42,8 @@ __device__ __forceinline__ int64_t a_off(const TArgs& p, int k, int row) {
   return (int64_t)(k >> 4) * p.a_k16 + (int64_t)(k & 15) * p.a_k + (int64_t)(row >> 4) * p.a_r16 + (row & 15);
 }
 
-template <int RT, int PER_T>
-__device__ __forceinline__ void gt_load(const TArgs& p, const uint32_t* Al, int ks, int row0, int tid, uint4* st) {
-  constexpr int A_U4 = 16 * RT / 4;
-#pragma unroll
-  for (int it = 0; it < PER_T; ++it) {
-    const int i = tid + 256 * it;
-    if (i < A_U4) {
-      const int kk = i / (RT / 4), rg = i % (RT / 4);
-      const int k = 16 * ks + kk;
-      const int row = min(row0 + 4 * rg, p.rows_alloc - 4);
-      uint4 v = *reinterpret_cast<const uint4*>(Al + a_off(p, min(k, p.kvalid - 1), row));
-      if (k >= p.kvalid) v = make_uint4(0u, 0u, 0u, 0u);
-      st[it] = v;
-    }
-  }
-}
-
-template <int RT, int LDA, int PER_T>
-__device__ __forceinline__ void gt_put(uint32_t* buf, int tid, const uint4* st) {
-  constexpr int A_U4 = 16 * RT / 4;
-#pragma unroll
-  for (int it = 0; it < PER_T; ++it) {
-    const int i = tid + 256 * it;
-    if (i < A_U4) {
-      const int kk = i / (RT / 4), rg = i % (RT / 4);
-      *reinterpret_cast<uint4*>(buf + kk * LDA + 4 * rg) = st[it];
-    }
-  }
-}
-
-template <int HT, int H, int MF, int NF, int WR, int WC>
-__global__ __launch_bounds__(256) void k_gemm_t(const TArgs p) {
-  static_assert(WR * WC == 4, "four waves");
-  constexpr int RT = 16 * MF * WR;        // rows per tile
-  constexpr int LDA = RT + 4;             // padded LDS row (words)
-  constexpr int PER_T = (16 * RT / 4 + 255) / 256;
-  __shared__ uint32_t lds[2][16 * LDA];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave / WC, wc = wave % WC;
-  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per_slot = p.nrt * p.nct * p.splits;
-  const int l = x + 8 * (q / per_slot);
-  int rem = q % per_slot;
-  const int split = rem % p.splits;
-  rem /= p.splits;
-  const int ct = rem % p.nct, rt = rem / p.nct;
-  const bool dc = (l == 0);
-  const uint32_t cmask = dc ? 0u : 0x80000000u;
-  const int ks0 = (int)((int64_t)p.nks * split / p.splits), ks1 = (int)((int64_t)p.nks * (split + 1) / p.splits);
-  const int row0 = rt * RT;
-  const int cb0 = (ct * WC + wc) * NF;
-  const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
-  const float2* Xl = p.X + (int64_t)l * p.x_slot;
-  int rup[NF], cim[NF];
-  float upv[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    const int n = 16 * (cb0 + f) + (lane & 15);
-    rup[f] = min(n >> 1, p.bp - 1);
-    cim[f] = n & 1;
-    upv[f] = p.up ? p.up[(int64_t)l * p.bp + rup[f]] : 1.f;
-  }
-  f32x4 acc[MF][NF];
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (ks0 < ks1) {
-    uint4 st[PER_T];
-    gt_load<RT, PER_T>(p, Al, ks0, row0, tid, st);
-    gt_put<RT, LDA, PER_T>(lds[0], tid, st);
-    __syncthreads();
-    for (int ks = ks0; ks < ks1; ++ks) {
-      const int cur = (ks - ks0) & 1;
-      const bool more = ks + 1 < ks1;
-      if (more) gt_load<RT, PER_T>(p, Al, ks + 1, row0, tid, st);
-      uint4 av[MF];
-#pragma unroll
-      for (int a = 0; a < MF; ++a) {
-        const int r = 16 * (MF * wr + a) + (lane & 15);
-        const uint32_t* la = &lds[cur][(4 * (lane >> 4)) * LDA + r];
-        av[a] = make_uint4(la[0] ^ cmask, la[LDA] ^ cmask, la[2 * LDA] ^ cmask, la[3 * LDA] ^ cmask);
-      }
-      const int kb = 16 * ks + 4 * (lane >> 4);
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        uint32_t hi[4], lo[4];
-#pragma unroll
-        for (int e2 = 0; e2 < 4; ++e2) {
-          const int k = kb + e2;
-          float2 v = Xl[(int64_t)min(k, p.xk_alloc - 1) * p.x_k + rup[f]];
-          if (k >= p.kvalid) v = make_float2(0.f, 0.f);
-          v.x *= upv[f];
-          v.y *= upv[f];
-          float v0, v1;
-          if (dc) {
-            v0 = cim[f] == 0 ? v.x : 0.f;
-            v1 = cim[f] == 0 ? 0.f : v.y;
-          } else {
-            v0 = cim[f] == 0 ? v.x : v.y;
-            v1 = cim[f] == 0 ? -v.y : v.x;
-          }
-          const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
-          hi[e2] = h0 | (h1 << 16);
-          if (H == 2)
-            lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) |
-                     (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
-        }
-        const uint4 bh = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-#pragma unroll
-        for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
-        if (H == 2) {
-          const uint4 bl = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-#pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bl, acc[a][f]);
-        }
-      }
-      if (more) gt_put<RT, LDA, PER_T>(lds[cur ^ 1], tid, st);
-      __syncthreads();
-    }
-  }
-  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
-      if (row < p.nrows) {
-        const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          const int n = 16 * (cb0 + f) + (lane & 15);
-          const int b = n >> 1;
-          if (b < p.B) {
-            const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
-            ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
-          }
-        }
-      }
-    }
-}
-
-// Eight-wave variant for the long-K product: a 256-row x 32*NF-column tile per workgroup (waves
-// 4 x 2, each 64 rows x 16*NF columns).  Per K step of 16 both operands pass through LDS, double
+// Eight waves per workgroup, a 256-row x 32*NF-column tile (waves 4 x 2, each 64 rows x 16*NF
+// columns).  Per K step of 16 both operands pass through LDS, double
 // buffered with one barrier per step: the operator tile as [k][row] words, the activation
 // converted once per workgroup into MFMA B fragments (H terms) by threads that each own four
 // consecutive k of one rupture.  The next step's global loads are issued before the current
@@ -366,23 +224,21 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
     }
 }
 
-// shape 0: 64 rows x 256 columns per workgroup (many rows, short K);
-// shape 1: 256 rows x 64 columns (few rows, long K);
-// shapes 2, 3, 4: eight waves, 256 rows x 64, 128 or 256 columns, both operands staged in LDS
+// shapes 2, 3: eight waves, 256 rows x 64 or 128 columns, both operands staged in LDS;
+// shapes 5, 6, 7: the same with 64, 128 or 256 columns on real-column activation fragments
 hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int64_t a_slot, int64_t a_k16, int64_t a_k,
                          int64_t a_r16, int nrows,
                          int rows_alloc, int kvalid, int kpad, const float2* X, int64_t x_slot, int64_t x_k,
                          int xk_alloc, const float* up, const float* down, const float* rowscale, int64_t rs_row,
                          int64_t rs_l, float* out, int64_t o_split, int64_t o_slot, int64_t o_row, int B, int bp,
                          int M, int splits, hipStream_t st) {
-  constexpr int MF = 4, NF = 4;
   if ((M & 7) || kpad % 16 || kpad < kvalid || kvalid < 1 || rows_alloc % 4 || rows_alloc < nrows || nrows < 1 ||
-      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || shape < 0 || shape > 7 || (o_row & 1) ||
-      (o_slot & 1) || (o_split & 1))
+      splits < 1 || xk_alloc < kvalid || B < 1 || B > bp || !(shape == 2 || shape == 3 || (shape >= 5 && shape <= 7)) ||
+      (o_row & 1) || (o_slot & 1) || (o_split & 1))
     return hipErrorInvalidValue;
-  const int rt = shape == 0 ? 64 : 256;
+  const int rt = 256;
   const int sh = shape >= 5 ? shape - 3 : shape;  // shapes 5, 6, 7: shapes 2, 3, 4 on real-column fragments
-  const int ctc = sh == 0 ? 256 : sh == 1 ? 64 : sh == 2 ? 64 : sh == 3 ? 128 : 256;
+  const int ctc = sh == 2 ? 64 : sh == 3 ? 128 : 256;
   TArgs a;
   a.Aq = Aq;
   a.a_slot = a_slot;
@@ -414,37 +270,20 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
   const int64_t blocks = (int64_t)M * a.nrt * a.nct * a.splits;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
-#define S2W_GT(HT_, H_, WR_, WC_) hipLaunchKernelGGL((k_gemm_t<HT_, H_, MF, NF, WR_, WC_>), grid, dim3(256), 0, st, a)
 #define S2W_GT2(HT_, H_, NF_, RE_) hipLaunchKernelGGL((k_gemm_t2<HT_, H_, NF_, RE_>), grid, dim3(512), 0, st, a)
 #define S2W_GT2_NF(HT_, H_) \
   do {                                                                        \
     if (shape == 2) S2W_GT2(HT_, H_, 2, false);                               \
     else if (shape == 3) S2W_GT2(HT_, H_, 4, false);                          \
-    else if (shape == 4) S2W_GT2(HT_, H_, 8, false);                          \
     else if (shape == 5) S2W_GT2(HT_, H_, 2, true);                           \
     else if (shape == 6) S2W_GT2(HT_, H_, 4, true);                           \
     else S2W_GT2(HT_, H_, 8, true);                                           \
   } while (0)
-  if (shape >= 2) {
-    if (ht == 1) {
-      if (hterms == 2) S2W_GT2_NF(1, 2); else S2W_GT2_NF(1, 1);
-    } else {
-      if (hterms == 2) S2W_GT2_NF(2, 2); else S2W_GT2_NF(2, 1);
-    }
-  } else if (shape == 0) {
-    if (ht == 1) {
-      if (hterms == 2) S2W_GT(1, 2, 1, 4); else S2W_GT(1, 1, 1, 4);
-    } else {
-      if (hterms == 2) S2W_GT(2, 2, 1, 4); else S2W_GT(2, 1, 1, 4);
-    }
+  if (ht == 1) {
+    if (hterms == 2) S2W_GT2_NF(1, 2); else S2W_GT2_NF(1, 1);
   } else {
-    if (ht == 1) {
-      if (hterms == 2) S2W_GT(1, 2, 4, 1); else S2W_GT(1, 1, 4, 1);
-    } else {
-      if (hterms == 2) S2W_GT(2, 2, 4, 1); else S2W_GT(2, 1, 4, 1);
-    }
+    if (hterms == 2) S2W_GT2_NF(2, 2); else S2W_GT2_NF(2, 1);
   }
-#undef S2W_GT
 #undef S2W_GT2
 #undef S2W_GT2_NF
   return hipGetLastError();

@@ -340,309 +340,8 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
 // eight distinct 16-byte bank groups.
 __device__ __forceinline__ int swz(int r, int c) { return r * 4 + (c ^ ((r >> 1) & 3)); }
 
-// Compact activation of the elastic GEMM: Sc[l][ks][jl][b] (b < bp), one uint2 per complex
-// activation value s (scaled by sig_up[l][b]): word x = bf16/f16 bits of (Re s_hi, Im s_hi) in
-// (low, high) halves, word y = the same for the low term s - s_hi.  The 2x2 real embedding is
-// formed in registers from these words (sign flip of the high half for the real output
-// column, half swap for the imaginary column, masks for the packed real slot).
-template <int HT>
-__global__ __launch_bounds__(256) void k_prep_act_compact(const float2* __restrict__ S, const float* __restrict__ sig_up,
-                                                          int M, int nsub, int nsq, int B, int bp, int nks,
-                                                          uint2* __restrict__ Sc) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = (int64_t)M * nks * 16 * bp;
-  if (i >= total) return;
-  const int b = (int)(i % bp);
-  int64_t q = i / bp;
-  const int jl = (int)(q % 16);
-  q /= 16;
-  const int ks = (int)(q % nks);
-  const int l = (int)(q / nks);
-  const int j = 16 * ks + jl;
-  float2 s = make_float2(0.f, 0.f);
-  if (b < B && j < nsub) {
-    s = S[((int64_t)l * nsq + j) * bp + b];
-    const float u = sig_up[(int64_t)l * bp + b];
-    s.x *= u;
-    s.y *= u;
-  }
-  const uint32_t hr = to_half_bits<HT>(s.x), hi = to_half_bits<HT>(s.y);
-  const uint32_t lr = to_half_bits<HT>(s.x - from_half_bits<HT>(hr));
-  const uint32_t li = to_half_bits<HT>(s.y - from_half_bits<HT>(hi));
-  Sc[i] = make_uint2(hr | (hi << 16), lr | (li << 16));
-}
-
-hipError_t launch_prep_act_compact(int ht, const float2* S, float* sig_up, float* sig_down, int M, int nsub, int nsq,
-                                   int B, int bp, int nks, uint2* Sc, hipStream_t st) {
-  const int64_t ns = (int64_t)M * bp;
-  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp, sig_up,
-                     sig_down);
-  const int64_t total = (int64_t)M * nks * 16 * bp;
-  dim3 grid((unsigned)((total + 255) / 256));
-  if (ht == 1)
-    hipLaunchKernelGGL(k_prep_act_compact<1>, grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, Sc);
-  else
-    hipLaunchKernelGGL(k_prep_act_compact<2>, grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, Sc);
-  return hipGetLastError();
-}
-
-// Fragment word of the 2x2 embedding for output column parity c (0 real, 1 imaginary) from a
-// packed (re | im << 16) word; dc selects the packed real slot.
-__device__ __forceinline__ uint32_t embed_word(uint32_t w, int c, bool dc) {
-  if (dc) return c == 0 ? (w & 0xffffu) : (w & 0xffff0000u);
-  return c == 0 ? (w ^ 0x80000000u) : ((w >> 16) | (w << 16));
-}
-
-// Elastic GEMM with compact activations, LDS-staged: eight waves (2 row groups x 4 column
-// groups), tile 2*MW grid rows x 4*NW output columns (2*NW ruptures).  Per K step the operator
-// tile (2*MW rows x 64 bytes, chunk-swizzled) and the compact activation tile (16 subfaults x
-// 2*NW ruptures x 8 bytes, rows padded by 64 bytes) are double-buffered in LDS.
-template <int HT, int MW, int NW, int WR, int H = 2>
-__global__ __launch_bounds__(256 * WR, WR == 1 ? 2 : 1) void k_gemm_g3(const uint4* __restrict__ Gq, const float* __restrict__ sG,
-                                                    const uint2* __restrict__ Sc, const float* __restrict__ sig_down,
-                                                    float* __restrict__ U, int ngrid, int M, int nks, int B, int bp,
-                                                    int nrb, int nct) {
-  constexpr int MF = MW / 16, NF = NW / 16;
-  constexpr int NTH = 256 * WR;              // threads
-  constexpr int RT = WR * MW;                // rows per tile
-  constexpr int NR = 2 * NW;                 // ruptures per tile (4 waves x NW columns / 2)
-  constexpr int LDB = NR + 8;                // padded LDS row of the activation tile (uint2)
-  constexpr int A_U4 = RT * 4;               // uint4 of the operator tile
-  constexpr int B_U4 = 16 * NR / 2;          // uint4 of the activation tile (two uint2 each)
-  constexpr int T_U4 = A_U4 + B_U4;
-  constexpr int PER_T = (T_U4 + NTH - 1) / NTH;
-  constexpr int LDS_A = A_U4;                // uint4
-  constexpr int LDS_B = 16 * LDB / 2;        // uint4
-  __shared__ uint4 lds[2][LDS_A + LDS_B];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 2, wc = wave & 3;
-  const int c = lane & 1;
-  const int nwg = gridDim.x, w = blockIdx.x;
-  const int nx = 8 < M ? 8 : M;
-  const int x = w % nx, wi = w / nx, nwx = (nwg - x + nx - 1) / nx;
-  const int slots_x = (M - x + nx - 1) / nx;
-  const int64_t per_slot = (int64_t)nrb * nct;
-  const int64_t items = (int64_t)slots_x * per_slot;
-  const int ng16 = (ngrid + 15) >> 4;
-  for (int64_t it = wi; it < items; it += nwx) {
-    const int l = x + nx * (int)(it / per_slot);
-    const bool dc = (l == 0);
-    const int64_t rem = it % per_slot;
-    const int rb = (int)(rem / nct), ct = (int)(rem % nct);
-    const int g0 = rb * RT;
-    const int b0 = ct * NR;
-    const uint4* src[PER_T];
-    int64_t sstep[PER_T];
-    bool valid[PER_T];
-    int dst[PER_T];
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k) {
-      const int i = tid + NTH * k;
-      valid[k] = i < T_U4;
-      if (i < A_U4) {
-        const int r = i >> 2, cc = i & 3;
-        const int g = min(g0 + r, ngrid - 1);
-        src[k] = gq_row(Gq, g, l, ng16, nks) + cc;
-        sstep[k] = kGqStepU4;
-        dst[k] = swz(r, cc);
-      } else {
-        const int j = min(i - A_U4, B_U4 - 1);
-        const int jl = j / (NR / 2), q = j % (NR / 2);  // row jl, uint4 q (ruptures 2q, 2q+1)
-        const int bb = min(b0 + 2 * q, bp - 2);
-        src[k] = reinterpret_cast<const uint4*>(Sc + (((int64_t)l * nks) * 16 + jl) * bp + bb);
-        sstep[k] = (int64_t)16 * bp / 2;
-        dst[k] = LDS_A + (jl * LDB) / 2 + q;
-      }
-    }
-    f32x4 acc[MF][NF];
-#pragma unroll
-    for (int a = 0; a < MF; ++a)
-#pragma unroll
-      for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    uint4 stage[PER_T];
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k)
-      if (valid[k]) stage[k] = ntload(src[k]);
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k)
-      if (valid[k]) lds[0][dst[k]] = stage[k];
-    __syncthreads();
-    for (int ks = 0; ks < nks; ++ks) {
-      const int cur = ks & 1;
-      const bool more = ks + 1 < nks;
-      if (more) {
-#pragma unroll
-        for (int k = 0; k < PER_T; ++k)
-          if (valid[k]) stage[k] = ntload(src[k] + (int64_t)(ks + 1) * sstep[k]);
-      }
-      const uint4* la = &lds[cur][0];
-      const uint2* lb = reinterpret_cast<const uint2*>(&lds[cur][LDS_A]);
-      uint4 av[MF];
-#pragma unroll
-      for (int a = 0; a < MF; ++a) av[a] = la[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
-#pragma unroll
-      for (int b = 0; b < NF; ++b) {
-        const int rl = wc * (NW / 2) + b * 8 + ((lane & 15) >> 1);  // rupture within the tile
-        uint32_t hw[4], lw[4];
-#pragma unroll
-        for (int e2 = 0; e2 < 4; ++e2) {
-          const uint2 wv = lb[(4 * (lane >> 4) + e2) * LDB + rl];
-          hw[e2] = embed_word(wv.x, c, dc);
-          lw[e2] = embed_word(wv.y, c, dc);
-        }
-        const uint4 bh = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-        const uint4 bl = make_uint4(lw[0], lw[1], lw[2], lw[3]);
-#pragma unroll
-        for (int a = 0; a < MF; ++a) {
-          acc[a][b] = mfma16<HT>(av[a], bh, acc[a][b]);
-          if (H == 2) acc[a][b] = mfma16<HT>(av[a], bl, acc[a][b]);
-        }
-      }
-      if (more) {
-#pragma unroll
-        for (int k = 0; k < PER_T; ++k)
-          if (valid[k]) lds[cur ^ 1][dst[k]] = stage[k];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < MF; ++a)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int g = g0 + wr * MW + 16 * a + 4 * (lane >> 4) + r;
-        if (g >= ngrid) continue;
-        const float sg = sG[(int64_t)g * M + l];
-#pragma unroll
-        for (int b = 0; b < NF; ++b) {
-          const int rup = b0 + wc * (NW / 2) + b * 8 + ((lane & 15) >> 1);
-          if (rup < B)
-            U[(((int64_t)g * M + l) * bp + rup) * 2 + c] = acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
-        }
-      }
-  }
-}
-
-// Elastic GEMM, LDS-staged variant for wide batches.  Eight waves (2 row groups x 4 column
-// groups); workgroup tile 2*MW grid rows x 4*NW output columns.  Per K step (16 subfaults)
-// the workgroup copies the operator tile (2*MW rows x 64 bytes) and the activation tile
-// (4*NW/16 column blocks x H fragments) from global memory into one of two LDS buffers
-// while the matrix cores consume the other; each operator and activation fragment is read
-// from HBM/L2 once per workgroup and shared by four (resp. two) waves through LDS.
-template <int HT, int H, int MW, int NW>
-__global__ __launch_bounds__(512, 1) void k_gemm_g2(const uint4* __restrict__ Gq, const float* __restrict__ sG,
-                                                    const uint4* __restrict__ Bop, const float* __restrict__ sig_down,
-                                                    float* __restrict__ U, int ngrid, int M, int nks, int ncb, int B,
-                                                    int bp, int nrb, int nct) {
-  constexpr int MF = MW / 16, NF = NW / 16;
-  constexpr int RT = 2 * MW;                 // rows per tile
-  constexpr int CBT = 4 * NF;                // column blocks per tile
-  constexpr int A_U4 = RT * 4;               // uint4 of the operator tile per K step
-  constexpr int B_U4 = CBT * H * 64;         // uint4 of the activation tile per K step
-  constexpr int T_U4 = A_U4 + B_U4;
-  constexpr int PER_T = (T_U4 + 511) / 512;  // uint4 each thread copies per K step
-  __shared__ uint4 lds[2][T_U4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 2, wc = wave & 3;
-  const int nwg = gridDim.x, w = blockIdx.x;
-  const int nx = 8 < M ? 8 : M;
-  const int x = w % nx, wi = w / nx, nwx = (nwg - x + nx - 1) / nx;
-  const int slots_x = (M - x + nx - 1) / nx;
-  const int64_t per_slot = (int64_t)nrb * nct;
-  const int64_t items = (int64_t)slots_x * per_slot;
-  const int ng16 = (ngrid + 15) >> 4;
-  for (int64_t it = wi; it < items; it += nwx) {
-    const int l = x + nx * (int)(it / per_slot);
-    const int64_t rem = it % per_slot;
-    const int rb = (int)(rem / nct), ct = (int)(rem % nct);
-    const int g0 = rb * RT;
-    const int cbt0 = ct * CBT;
-    // global sources of this thread's copy slots: operator rows (clamped) or activation blocks
-    const uint4* src[PER_T];
-    int64_t sstep[PER_T];
-    bool valid[PER_T];
-    int dst[PER_T];
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k) {
-      const int i = tid + 512 * k;
-      valid[k] = i < T_U4;
-      dst[k] = i;
-      if (i < A_U4) {
-        const int r = i >> 2, c = i & 3;
-        const int g = min(g0 + r, ngrid - 1);
-        src[k] = gq_row(Gq, g, l, ng16, nks) + c;
-        sstep[k] = kGqStepU4;
-        dst[k] = swz(r, c);
-      } else {
-        const int j = min(i - A_U4, B_U4 - 1);
-        const int cbl = j / (H * 64), rest = j % (H * 64);
-        const int cb = min(cbt0 + cbl, ncb - 1);
-        src[k] = Bop + ((int64_t)l * nks * ncb + cb) * H * 64 + rest;
-        sstep[k] = (int64_t)ncb * H * 64;
-      }
-    }
-    f32x4 acc[MF][NF];
-#pragma unroll
-    for (int a = 0; a < MF; ++a)
-#pragma unroll
-      for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    uint4 stage[PER_T];
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k)
-      if (valid[k]) stage[k] = ntload(src[k]);
-#pragma unroll
-    for (int k = 0; k < PER_T; ++k)
-      if (valid[k]) lds[0][dst[k]] = stage[k];
-    __syncthreads();
-    for (int ks = 0; ks < nks; ++ks) {
-      const int cur = ks & 1;
-      const bool more = ks + 1 < nks;
-      if (more) {
-#pragma unroll
-        for (int k = 0; k < PER_T; ++k)
-          if (valid[k]) stage[k] = ntload(src[k] + (int64_t)(ks + 1) * sstep[k]);
-      }
-      const uint4* la = &lds[cur][0];
-      const uint4* lb = &lds[cur][A_U4];
-      uint4 av[MF];
-#pragma unroll
-      for (int a = 0; a < MF; ++a) av[a] = la[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
-#pragma unroll
-      for (int b = 0; b < NF; ++b)
-#pragma unroll
-        for (int h = 0; h < H; ++h) {
-          const uint4 bv = lb[((wc * NF + b) * H + h) * 64 + lane];
-#pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bv, acc[a][b]);
-        }
-      if (more) {
-#pragma unroll
-        for (int k = 0; k < PER_T; ++k)
-          if (valid[k]) lds[cur ^ 1][dst[k]] = stage[k];
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int a = 0; a < MF; ++a)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int g = g0 + wr * MW + 16 * a + 4 * (lane >> 4) + r;
-        if (g >= ngrid) continue;
-        const float sg = sG[(int64_t)g * M + l];
-#pragma unroll
-        for (int b = 0; b < NF; ++b) {
-          const int cb = cbt0 + wc * NF + b;
-          const int n = 16 * cb + (lane & 15);
-          const int rup = n >> 1;
-          if (cb < ncb && rup < B)
-            U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
-                acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
-        }
-      }
-  }
-}
-
 // Elastic GEMM fed by direct global-to-LDS copies (global_load_lds_dwordx4): the same tile
-// and wave arrangement as k_gemm_g2, but the operator and activation tiles of a K step
+// and wave arrangement as the register-staged tiles, but the operator and activation tiles of a K step
 // travel from global memory to LDS without passing through registers, so NS stages can be in
 // flight at once (NS - 1 K steps ahead of the matrix cores).  A copy instruction moves 1 KB
 // per wave, lane p landing at byte 16*p of the wave's LDS target; for the operator tile the
@@ -850,36 +549,19 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
 template <int HT, int H>
 static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint4* Bop, const float* sig_down,
                            float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp, hipStream_t st) {
-#define S2W_GG(MW_, NW_, WR_, WC_)                                                                                 \
-  do {                                                                                                              \
-    const int nrb = (ngrid + MW_ * WR_ - 1) / (MW_ * WR_);                                                          \
-    const int nct = (ncb + (NW_ / 16) * WC_ - 1) / ((NW_ / 16) * WC_);                                              \
-    hipLaunchKernelGGL((k_gemm_g<HT, H, MW_, NW_, WR_, WC_>), dim3(nwg), dim3(64 * WR_ * WC_), 0, st, Gq, sG, Bop, \
-                       sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);                                           \
-  } while (0)
   switch (cfg) {
-    case 0: S2W_GG(64, 16, 4, 1); break;   // narrow batches (B <= 8)
-    case 1: S2W_GG(64, 64, 2, 2); break;   // 128 x 128
-    case 2: S2W_GG(32, 128, 1, 4); break;  // 32 x 512
-    case 3: S2W_GG(64, 128, 1, 4); break;  // 64 x 512
-    case 5:
-    case 6: {
-      // LDS-staged eight-wave tiles: 5 = 256 rows x 256 columns, 6 = 128 rows x 512 columns
-      const int MW = cfg == 5 ? 128 : 64, NW = cfg == 5 ? 64 : 128;
-      const int nrb = (ngrid + 2 * MW - 1) / (2 * MW);
-      const int nct = (ncb + 4 * (NW / 16) - 1) / (4 * (NW / 16));
-      if (cfg == 5)
-        hipLaunchKernelGGL((k_gemm_g2<HT, H, 128, 64>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
-                           nks, ncb, B, bp, nrb, nct);
-      else
-        hipLaunchKernelGGL((k_gemm_g2<HT, H, 64, 128>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
-                           nks, ncb, B, bp, nrb, nct);
+    case 0: {
+      // narrow batches: register tile of 64 rows x 16 columns per wave, four waves down
+      const int nrb = (ngrid + 255) / 256;
+      const int nct = ncb;
+      hipLaunchKernelGGL((k_gemm_g<HT, H, 64, 16, 4, 1>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop, sig_down, U, ngrid, M,
+                         nks, ncb, B, bp, nrb, nct);
       break;
     }
     case 17:
     case 18: {
-      // tile 10 on real-column activation fragments (k_prep_act_re): 17 with four stages of
-      // 32 KB, 18 with three
+      // 256 x 256 tiles on real-column activation fragments (k_prep_act_re): 17 with four
+      // stages of 32 KB, 18 with three
       const int nrcb = (B + 15) / 16;
       const int nrb = (ngrid + 255) / 256;
       const int nct = (nrcb + 7) / 8;
@@ -891,99 +573,30 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
                            sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
       break;
     }
-    case 19:
-    case 20: {
-      // one wave per SIMD with 128 x 128 wave tiles on real-column activation fragments, three
-      // stages: 19 = 256 rows x 256 columns (2 x 2 waves), 20 = 128 rows x 512 columns (1 x 4
-      // waves: 256 ruptures in one column tile, so the operator is read once per slot)
-      const int nrcb = (B + 15) / 16;
-      const int WR = cfg == 19 ? 2 : 1, WC = cfg == 19 ? 2 : 4;
-      const int nrb = (ngrid + 128 * WR - 1) / (128 * WR);
-      const int nct = (nrcb + 4 * WC - 1) / (4 * WC);
-      if (cfg == 19)
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 3, 2, 2, 1, true>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop,
-                           sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
-      else
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 3, 1, 4, 1, true>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop,
-                           sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
-      break;
-    }
     case 10:
-    case 11:
     case 12: {
-      // direct-to-LDS copies: 10 = 256 x 256 (three stages), 11 = 128 x 512 (two stages),
-      // 12 = 256 x 128 (four stages)
-      const int MW = cfg == 11 ? 64 : 128, NW = cfg == 11 ? 128 : (cfg == 12 ? 32 : 64);
-      const int nrb = (ngrid + 2 * MW - 1) / (2 * MW);
+      // direct-to-LDS copies, eight waves: 10 = 256 x 256 (three stages), 12 = 256 x 128 (four stages)
+      const int NW = cfg == 12 ? 32 : 64;
+      const int nrb = (ngrid + 255) / 256;
       const int nct = (ncb + 4 * (NW / 16) - 1) / (4 * (NW / 16));
       if (cfg == 10)
         hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 3, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
-                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
-      else if (cfg == 11)
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 64, 128, 2, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
                            U, ngrid, M, nks, ncb, B, bp, nrb, nct);
       else
         hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 32, 4, 2, 4>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down,
                            U, ngrid, M, nks, ncb, B, bp, nrb, nct);
       break;
     }
-    case 15:
     case 16: {
-      // direct-to-LDS copies, four waves, two stages, two workgroups per compute unit:
-      // 15 = 128 x 256, 16 = 256 x 128
-      const int MW = cfg == 15 ? 64 : 128, NW = cfg == 15 ? 128 : 64;
-      const int nrb = (ngrid + 2 * MW - 1) / (2 * MW);
-      const int nct = (ncb + 2 * (NW / 16) - 1) / (2 * (NW / 16));
-      if (cfg == 15)
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 64, 128, 2, 2, 2, 2>), dim3(2 * nwg), dim3(256), 0, st, Gq, sG, Bop,
-                           sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);
-      else
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 2, 2, 2, 2>), dim3(2 * nwg), dim3(256), 0, st, Gq, sG, Bop,
-                           sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);
-      break;
-    }
-    case 13:
-    case 14: {
-      // direct-to-LDS copies, one wave per SIMD with 128 x 128 wave tiles (accumulators in the
-      // extended register file): 13 = 256 x 256 (three stages), 14 = 128 x 512 (two stages)
-      const int WR = cfg == 13 ? 2 : 1, WC = cfg == 13 ? 2 : 4;
-      const int nrb = (ngrid + 128 * WR - 1) / (128 * WR);
-      const int nct = (ncb + 8 * WC - 1) / (8 * WC);
-      if (cfg == 13)
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 3, 2, 2>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop, sig_down,
-                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
-      else
-        hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 128, 2, 1, 4>), dim3(nwg), dim3(256), 0, st, Gq, sG, Bop, sig_down,
-                           U, ngrid, M, nks, ncb, B, bp, nrb, nct);
+      // direct-to-LDS copies, four waves of 128 x 64, two stages, two workgroups per compute unit
+      const int nrb = (ngrid + 255) / 256;
+      const int nct = (ncb + 7) / 8;
+      hipLaunchKernelGGL((k_gemm_g4<HT, H, 128, 64, 2, 2, 2, 2>), dim3(2 * nwg), dim3(256), 0, st, Gq, sG, Bop,
+                         sig_down, U, ngrid, M, nks, ncb, B, bp, nrb, nct);
       break;
     }
     default: return hipErrorInvalidValue;
   }
-#undef S2W_GG
-  return hipGetLastError();
-}
-
-hipError_t launch_gemm_g3(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint2* Sc,
-                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int B, int bp,
-                          hipStream_t st) {
-  // 7: 256 rows x 128 ruptures (eight waves); 8: 128 rows x 256 ruptures (eight waves);
-  // 9: 128 rows x 128 ruptures (four waves, two workgroups per compute unit)
-  const int WR = cfg == 9 ? 1 : 2;
-  const int MW = cfg == 8 ? 64 : 128, NW = cfg == 8 ? 128 : 64;
-  const int nrb = (ngrid + WR * MW - 1) / (WR * MW);
-  const int nct = (B + 2 * NW - 1) / (2 * NW);
-  const int grid = cfg == 9 ? 2 * nwg : nwg;
-#define S2W_G3(HT_, MW_, NW_, WR_, H_)                                                                            \
-  hipLaunchKernelGGL((k_gemm_g3<HT_, MW_, NW_, WR_, H_>), dim3(grid), dim3(256 * WR_), 0, st, Gq, sG, Sc, sig_down, \
-                     U, ngrid, M, nks, B, bp, nrb, nct)
-  if (ht == 1) {
-    if (cfg == 8) S2W_G3(1, 64, 128, 2, 2); else if (cfg == 9) S2W_G3(1, 128, 64, 1, 2); else S2W_G3(1, 128, 64, 2, 2);
-  } else if (hterms == 2) {
-    if (cfg == 8) S2W_G3(2, 64, 128, 2, 2); else if (cfg == 9) S2W_G3(2, 128, 64, 1, 2); else S2W_G3(2, 128, 64, 2, 2);
-  } else {
-    if (cfg == 8) S2W_G3(2, 64, 128, 2, 1); else if (cfg == 9) S2W_G3(2, 128, 64, 1, 1); else S2W_G3(2, 128, 64, 2, 1);
-  }
-#undef S2W_G3
   return hipGetLastError();
 }
 
@@ -998,112 +611,11 @@ hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const flo
 }
 
 // ---------------------------------------------------------------------------------------------
-// Acoustic GEMM per bin (eq. 2, Alg. 2 step 3, batched), split over grid rows:
-//   part[split][l][o][n] = sum_{g in split} Fq[l][o][g] (x) V[g][l][b]   (n = 2b + re/im)
-// V holds the mid-chain output (already multiplied by sF[g][l]), either as complex64, which is
-// scaled by tau_up[l][b] and split into H half-precision terms in registers, or (PACKED) as
-// bfloat16 high/low terms of the real and imaginary parts, from which the fragment entries
-// follow by sign flips and half swaps.  Workgroup (l, split, column tile): rows = all
-// observers (MF fragments of 16), NF column blocks per wave, four waves side by side.
-template <int HT, int H, int NF, int MF, bool PACKED>
-__global__ __launch_bounds__(256) void k_gemm_f(const uint4* __restrict__ Fq, const float2* __restrict__ V,
-                                                const float* __restrict__ tau_up, float* __restrict__ part, int ngrid,
-                                                int ngq, int M, int noq, int B, int bp, int ncb) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l = blockIdx.x;
-  const int split = blockIdx.y, splits = gridDim.y;
-  const int cb0 = (blockIdx.z * 4 + wave) * NF;
-  const int kst0 = (int)((int64_t)(ngq / 16) * split / splits), kst1 = (int)((int64_t)(ngq / 16) * (split + 1) / splits);
-  const bool dc = (l == 0);
-  f32x4 acc[MF][NF];
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int b = 0; b < NF; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int rup[NF], cim[NF];
-  float tu[NF];
-#pragma unroll
-  for (int b = 0; b < NF; ++b) {
-    const int n = 16 * (cb0 + b) + (lane & 15);
-    rup[b] = min(n >> 1, bp - 1);
-    cim[b] = n & 1;
-    tu[b] = tau_up ? tau_up[(int64_t)l * bp + rup[b]] : 1.f;
-  }
-  const int64_t frow = (int64_t)ngq / 4;  // uint4 per (l, o) row of Fq
-  const uint4* fa = Fq + (int64_t)l * noq * frow + (lane >> 4);
-  const int64_t vrow = (int64_t)M * bp;   // complex values per grid row of V
-  const float2* vb = V + (int64_t)l * bp;
-  for (int ks = kst0; ks < kst1; ++ks) {
-    uint4 av[MF];
-#pragma unroll
-    for (int a = 0; a < MF; ++a) av[a] = ntload(fa + (int64_t)(16 * a + (lane & 15)) * frow + 4 * ks);
-    const int gb = 16 * ks + 4 * (lane >> 4);
-#pragma unroll
-    for (int b = 0; b < NF; ++b) {
-      uint32_t hi[4], lo[4];
-#pragma unroll
-      for (int e2 = 0; e2 < 4; ++e2) {
-        const int g = min(gb + e2, ngrid - 1);
-        const bool gok = gb + e2 < ngrid;
-        if (PACKED) {
-          // words: (re_hi | im_hi << 16), (re_lo | im_lo << 16); column re: (re, -im), column im: (im, re)
-          uint2 w = reinterpret_cast<const uint2*>(vb)[(int64_t)g * vrow + rup[b]];
-          if (!gok) w = make_uint2(0u, 0u);
-          uint32_t wh = w.x, wl = w.y;
-          if (dc) {
-            wh = cim[b] == 0 ? (wh & 0xffffu) : (wh & 0xffff0000u);
-            wl = cim[b] == 0 ? (wl & 0xffffu) : (wl & 0xffff0000u);
-          } else if (cim[b] == 0) {
-            wh ^= 0x80000000u;
-            wl ^= 0x80000000u;
-          } else {
-            wh = (wh >> 16) | (wh << 16);
-            wl = (wl >> 16) | (wl << 16);
-          }
-          hi[e2] = wh;
-          lo[e2] = wl;
-        } else {
-          float2 v = gok ? vb[(int64_t)g * vrow + rup[b]] : make_float2(0.f, 0.f);
-          v.x *= tu[b];
-          v.y *= tu[b];
-          float v0, v1;
-          if (dc) {
-            v0 = cim[b] == 0 ? v.x : 0.f;
-            v1 = cim[b] == 0 ? 0.f : v.y;
-          } else {
-            v0 = cim[b] == 0 ? v.x : v.y;
-            v1 = cim[b] == 0 ? -v.y : v.x;
-          }
-          const uint32_t h0 = to_half_bits<HT>(v0), h1 = to_half_bits<HT>(v1);
-          hi[e2] = h0 | (h1 << 16);
-          if (H == 2)
-            lo[e2] = to_half_bits<HT>(v0 - from_half_bits<HT>(h0)) |
-                     (to_half_bits<HT>(v1 - from_half_bits<HT>(h1)) << 16);
-        }
-      }
-      const uint4 bh = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-#pragma unroll
-      for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bh, acc[a][b]);
-      if (H == 2) {
-        const uint4 bl = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-#pragma unroll
-        for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bl, acc[a][b]);
-      }
-    }
-  }
-  // part[split][l][o][n], n < 2*bp
-  float* pw = part + ((int64_t)split * M + l) * noq * (2 * bp);
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int o = 16 * a + 4 * (lane >> 4) + r;
-#pragma unroll
-      for (int b = 0; b < NF; ++b) {
-        const int n = 16 * (cb0 + b) + (lane & 15);
-        if (cb0 + b < ncb && n < 2 * bp) pw[(int64_t)o * (2 * bp) + n] = acc[a][b][r];
-      }
-    }
+// Fragment word of the 2x2 embedding for output column parity c (0 real, 1 imaginary) from a
+// packed (re | im << 16) word; dc selects the packed real slot.
+__device__ __forceinline__ uint32_t embed_word(uint32_t w, int c, bool dc) {
+  if (dc) return c == 0 ? (w & 0xffffu) : (w & 0xffff0000u);
+  return c == 0 ? (w ^ 0x80000000u) : ((w >> 16) | (w << 16));
 }
 
 // Acoustic GEMM, LDS-staged, for the packed bfloat16 activation: workgroup (l, split, column
@@ -1257,46 +769,6 @@ hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngri
   }
 #undef S2W_F2
   return hipGetLastError();
-}
-
-template <int HT, int H, int NF, bool PK>
-static hipError_t gemm_f_nf(const uint4* Fq, const float2* V, const float* tau_up, float* part, int ngrid, int ngq,
-                            int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st) {
-  dim3 grid(M, splits, (ncb + 4 * NF - 1) / (4 * NF));
-  const int mf = noq / 16;
-#define S2W_GF(MF_)                                                                                               \
-  hipLaunchKernelGGL((k_gemm_f<HT, H, NF, MF_, PK>), grid, dim3(256), 0, st, Fq, V, tau_up, part, ngrid, ngq, M, noq, \
-                     B, bp, ncb)
-  if (mf == 1) S2W_GF(1);
-  else if (mf == 2) S2W_GF(2);
-  else if (mf == 4) S2W_GF(4);
-  else if (mf == 8 && NF <= 2) S2W_GF(8);
-  else if (mf == 16 && NF <= 2) S2W_GF(16);
-  else return hipErrorInvalidValue;
-#undef S2W_GF
-  return hipGetLastError();
-}
-
-template <int HT, int H, bool PK>
-static hipError_t gemm_f_h(const uint4* Fq, const float2* V, const float* tau_up, float* part, int ngrid, int ngq,
-                           int M, int noq, int B, int bp, int ncb, int splits, hipStream_t st) {
-  // wide batches: each wave covers eight column blocks so one workgroup spans 512 columns
-  if (ncb > 8 && noq <= 64) return gemm_f_nf<HT, H, 8, PK>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
-  return gemm_f_nf<HT, H, 2, PK>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
-}
-
-hipError_t launch_gemm_f(int ht, int hterms, bool packed, const uint4* Fq, const float2* V, const float* tau_up,
-                         float* part, int ngrid, int ngq, int M, int noq, int B, int bp, int ncb, int splits,
-                         hipStream_t st) {
-  if (packed) {
-    if (ht != 1 || hterms != 2) return hipErrorInvalidValue;
-    return gemm_f_h<1, 2, true>(Fq, V, nullptr, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
-  }
-  if (ht == 1)
-    return hterms == 2 ? gemm_f_h<1, 2, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st)
-                       : gemm_f_h<1, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
-  return hterms == 2 ? gemm_f_h<2, 2, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st)
-                     : gemm_f_h<2, 1, false>(Fq, V, tau_up, part, ngrid, ngq, M, noq, B, bp, ncb, splits, st);
 }
 
 hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int bp, float* sig_up, float* sig_down,

@@ -14,6 +14,7 @@ import torch
 import oracle
 import synth
 from gpu_util import half_limit, log_case, make_operator, report_half, to_dev
+from paper_2608_21763_amd import S2WError
 
 pytestmark = pytest.mark.gpu
 
@@ -135,7 +136,8 @@ def test_half_adjoint_split_counts_agree():
 def test_half_adjoint_tile_shapes_agree(B, dtype):
     # every tile of the two transposed products accumulates each output over the same K steps
     # in the same order (tiles 6..8 only re-form the imaginary-column fragments in registers):
-    # with the split count fixed, all tiles give bit-identical gradients
+    # with the split count fixed, all tiles give bit-identical gradients; the pruned tile ids
+    # are rejected
     cfg = synth.SynthConfig(nsub=300, ngrid=333, nobs=20, nt=48, seed=103, slip_seed=104, op_kind="dense",
                             slip_mode="dense")
     log_case("half_adjoint_tiles", B=B, dtype=dtype)
@@ -143,11 +145,17 @@ def test_half_adjoint_tile_shapes_agree(B, dtype):
     r = synth.normals(cfg.seed, "r", 0, (B, cfg.nobs, cfg.nt))
     rd = to_dev(r)
     outs = {}
-    for tf in range(1, 9):
-        for tg in range(1, 9):
+    tiles = (3, 4, 6, 7, 8)
+    for tf in tiles:
+        for tg in tiles:
             op.set_tuning(hadj_tile_f=tf, hadj_tile_g=tg, adj32_splits=2)
             outs[(tf, tg)] = op.adjoint(rd).clone()
-    ref = outs[(1, 5)]
+    for bad in (1, 2, 5, 9):
+        with pytest.raises(S2WError):
+            op.set_tuning(hadj_tile_f=bad)
+        with pytest.raises(S2WError):
+            op.set_tuning(hadj_tile_g=bad)
+    ref = outs[(3, 6)]
     for k, v in outs.items():
         assert torch.equal(v, ref), f"tiles {k} differ"
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
@@ -190,9 +198,12 @@ def test_elastic_gemm_tile_shapes_agree(B, dtype):
     op = make_operator(cfg, max_batch=B, g_dtype=dtype, f_dtype=dtype)
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
     outs = {}
-    for c in (4, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20):
+    for c in (4, 10, 12, 16, 17, 18):
         op.set_tuning(gemm_cfg=c)
         outs[c] = op.forward(s).clone()
+    for bad in (1, 2, 3, 5, 11, 19, 20):
+        with pytest.raises(S2WError):
+            op.set_tuning(gemm_cfg=bad)
     for c in outs:
         assert torch.equal(outs[c], outs[4]), f"tile shape {c} differs"
     y = outs[4].cpu().numpy()
@@ -206,7 +217,8 @@ def test_tuning_round_trip():
     # what s2w_get_tuning returns, given back to s2w_set_tuning, keeps every setting
     cfg = synth.SynthConfig(nsub=20, ngrid=64, nobs=4, nt=32, seed=1, slip_seed=2, op_kind="dense", slip_mode="dense")
     op = make_operator(cfg, max_batch=8, g_dtype="bf16", f_dtype="bf16")
-    for kw in ({"gemm_cfg": 4, "fgemm_lds": -1}, {"gemm_cfg": 18, "fgemm_lds": 3}, {"gemm_cfg": -1, "fgemm_lds": 1}):
+    for kw in ({"gemm_cfg": 4, "fgemm_lds": 4}, {"gemm_cfg": 18, "fgemm_lds": 3}, {"gemm_cfg": -1, "fgemm_lds": 1},
+               {"hadj_tile_f": 3, "hadj_tile_g": 8}, {"hadj_tile_f": -1, "hadj_tile_g": -1}):
         op.set_tuning(**kw)
         t = op.get_tuning()
         for k, v in kw.items():
@@ -216,11 +228,12 @@ def test_tuning_round_trip():
         assert op.get_tuning() == t
 
 
-@pytest.mark.parametrize("B,nobs", [(40, 20), (130, 20), (40, 120), (130, 120), (257, 50)])
-def test_acoustic_gemm_kernels_agree(B, nobs):
-    # the LDS-staged and the register acoustic kernels take the same K steps in the same order;
-    # with 120 observers and B > 64 the staged tile does not fit and both settings take the
-    # register kernel
+@pytest.mark.parametrize("B,nobs,fits", [(40, 20, True), (130, 20, True), (40, 120, True), (130, 120, False),
+                                         (257, 50, True)])
+def test_acoustic_gemm_kernels_agree(B, nobs, fits):
+    # the LDS-staged kernel (fgemm_lds 4) and the real-column eight-wave kernel (3) against the
+    # oracle; with 120 observers and B > 64 the staged tile does not fit and 4 takes the
+    # eight-wave kernel, bit for bit
     cfg = synth.SynthConfig(nsub=40, ngrid=333, nobs=nobs, nt=48, seed=95, slip_seed=96, op_kind="dense",
                             slip_mode="dense")
     log_case("half_acoustic", B=B, nobs=nobs)
@@ -228,19 +241,25 @@ def test_acoustic_gemm_kernels_agree(B, nobs):
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
     op.set_tuning(fgemm_lds=4)
     y1 = op.forward(s).clone()
-    op.set_tuning(fgemm_lds=-1)
+    op.set_tuning(fgemm_lds=3)
     y2 = op.forward(s).clone()
-    assert torch.equal(y1, y2)
+    if not fits:
+        assert torch.equal(y1, y2)
+    for bad in (-1, 5):
+        with pytest.raises(S2WError):
+            op.set_tuning(fgemm_lds=bad)
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
-    errs = oracle.rel_l2_per_rupture(y1.cpu().numpy(), oracle.forward(G, F, s.cpu().numpy().astype(np.float64)))
-    print("rel-L2 max", errs.max())
-    assert errs.max() <= BOUND[("bf16", "bf16")]
+    yref = oracle.forward(G, F, s.cpu().numpy().astype(np.float64))
+    for y in (y1, y2):
+        errs = oracle.rel_l2_per_rupture(y.cpu().numpy(), yref)
+        print("rel-L2 max", errs.max())
+        assert errs.max() <= BOUND[("bf16", "bf16")]
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 @pytest.mark.parametrize("B,nobs", [(1, 5), (40, 20), (100, 70), (200, 20), (257, 50)])
 def test_acoustic_kernel_choices(dtype, B, nobs):
-    # the three acoustic GEMMs (LDS-staged, eight-wave, register) against the oracle; the
+    # the two acoustic GEMMs (LDS-staged, eight-wave) against the oracle; the
     # eight-wave kernel covers one to four column tiles and observers beyond one 64-row tile,
     # and gives the same bits on full (2) and real-column (3) activation fragments once the
     # grid-row splits are fixed (the real-column form may take wider tiles, hence other splits)
@@ -253,7 +272,7 @@ def test_acoustic_kernel_choices(dtype, B, nobs):
     G, F = synth.gen_G(cfg).astype(np.float64), synth.gen_F(cfg).astype(np.float64)
     ref = oracle.forward(G, F, s)
     ys = {}
-    for sel in (1, 2, 3, 4, -1):
+    for sel in (1, 2, 3, 4):
         op.set_tuning(fgemm_lds=sel)
         y = op.forward(to_dev(s)).cpu().numpy()
         ys[sel] = y
