@@ -185,8 +185,9 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,direct,fp32b,half,half16,halfmix,adj,hadj,bltt,strong,weak",
+    ap.add_argument("--paths", default="fp32,direct,fp32b,half,halfh,half16,halfmix,adj,hadj,bltt,strong,weak",
                     help="fp32 (single rupture), fp32b (batched float32), half (batched half precision, --half-dtype), "
+                         "halfh (bfloat16 stores with bfloat16 products on high and low activation terms), "
                          "half16 (batched float16 stores), halfmix (bfloat16 elastic and float16 acoustic stores), "
                          "adj (batched float32 adjoint), hadj (batched bfloat16 adjoint, "
                          "--batch residuals), "
@@ -415,14 +416,16 @@ def main():
         torch.cuda.empty_cache()
 
     # ---------------- batched half-precision paths ----------------
-    def half_path(gdt, fdt, B):
+    def half_path(gdt, fdt, B, products="auto"):
         import oracle
         op = S2WOperator(bcfg.nsub, bcfg.ngrid, bcfg.nobs, bcfg.nt, max_batch=B, dt=bcfg.dt, device=0,
-                         g_dtype=gdt, f_dtype=fdt)
+                         g_dtype=gdt, f_dtype=fdt, products=products)
+        bf16_products = products == "bf16" and gdt == "bf16"
+        label = f"{gdt}/{fdt}" + (" bf16 products" if bf16_products else "")
         t = time.perf_counter()
         op.load_operators(*host_generators(bcfg), chunk_rows=1024)
         setup_s = time.perf_counter() - t
-        log(f"{gdt}/{fdt} operators set in {setup_s:.1f} s")
+        log(f"{label} operators set in {setup_s:.1f} s")
         nb = 2
         s_host = synth.gen_slip_batch(bcfg, 0, nb * B)
         s_dev = torch.tensor(s_host, device=dev).reshape(nb, B, bcfg.nsub, bcfg.nt)
@@ -431,19 +434,21 @@ def main():
         ms_step = total_ms / args.steps
         kmean = float(np.mean(kern_ms))
         flops_g = 8.0 * bcfg.ngrid * bcfg.nsub * (bcfg.nt) * B      # complex MACs of the elastic stage per call
-        terms = 1 if gdt == "f16" else 2                              # activation terms the matrix cores multiply
+        terms = 2 if bf16_products else 1                             # activation terms the matrix cores multiply
         hbytes = algorithmic_bytes(bcfg.nsub, bcfg.nobs, bcfg.ngrid, bcfg.nt, 2)
         res = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{fdt}",
+               "products": "bf16 (high and low activation terms)" if bf16_products else
+               ("f16 (bf16 operator words converted exactly in registers)" if "bf16" in (gdt, fdt) else "f16"),
                "tuning": tuning, "kernel": elastic_kernel(op.get_tuning()["gemm_cfg"]), "kernel_ms": kmean,
                "kernel_ms_min": float(np.min(kern_ms)),
                "algorithmic_flops": flops_g, "achieved_TFLOPs": flops_g / (kmean * 1e9),
                "activation_terms": terms, "issued_TFLOPs": terms * flops_g / (kmean * 1e9), "algorithmic_bytes": hbytes,
                "setup_s": setup_s}
-        log(f"half {gdt}/{fdt} B={B}: {ms_step:.3f} ms/call, {res['ruptures_per_s']:.0f} ruptures/s, "
+        log(f"half {label} B={B}: {ms_step:.3f} ms/call, {res['ruptures_per_s']:.0f} ruptures/s, "
             f"elastic GEMM {kmean:.3f} ms = {res['achieved_TFLOPs']:.0f} TFLOP/s algorithmic")
         if not args.no_graph:
             res["graph_ms_per_step"] = time_graph(op, s_dev, args.steps, B)
-            log(f"half {gdt}/{fdt} B={B}: {res['graph_ms_per_step']:.3f} ms per captured-graph replay")
+            log(f"half {label} B={B}: {res['graph_ms_per_step']:.3f} ms per captured-graph replay")
         golden = headline_reference(bcfg, B, s_host[:B])
         if golden is not None:
             # stored FP64 oracle waveforms of 34 ruptures of this very batch (every eighth, the
@@ -457,7 +462,7 @@ def main():
                                    "median": float(np.median(rel)), "min_k_rupture": float(rel[np.argmin(act)]),
                                    "max_k_rupture": float(rel[np.argmax(act)]), "elementwise_max": float(mab.max()),
                                    "meets_2e-3": bool(rel.max() <= 2e-3)}
-            log(f"half {gdt}/{fdt} rel-L2 over {len(idx)} ruptures: max {rel.max():.2e}, p95 "
+            log(f"half {label} rel-L2 over {len(idx)} ruptures: max {rel.max():.2e}, p95 "
                 f"{np.percentile(rel, 95):.2e}, median {np.median(rel):.2e}, element-wise max {mab.max():.2e}")
         elif not args.no_cpu_baseline:
             y = op.forward(s_dev[0]).cpu().numpy().astype(np.float64)
@@ -466,7 +471,7 @@ def main():
             errs = [oracle.rel_l2(y[b], r) for b, r in zip(pick, batch_oracle(s_host, pick))]
             res["rel_l2_sampled"] = {str(b): e for b, e in zip(pick, errs)}
             res["rel_l2"] = max(errs)
-            log(f"half {gdt}/{fdt} rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
+            log(f"half {label} rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
         del op
         torch.cuda.empty_cache()
         return res
@@ -474,6 +479,8 @@ def main():
     if "half" in paths:
         gdt, fdt = args.half_dtype.split("/") if "/" in args.half_dtype else (args.half_dtype, args.half_dtype)
         result["half"] = half_path(gdt, fdt, args.batch)
+    if "halfh" in paths:
+        result["halfh"] = half_path("bf16", "bf16", args.batch, products="bf16")
     if "half16" in paths:
         result["half16"] = half_path("f16", "f16", args.batch)
     if "halfmix" in paths:

@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define S2W_ABI_VERSION 4
+#define S2W_ABI_VERSION 5
 
 typedef struct s2w_plan s2w_plan;
 
@@ -63,6 +63,22 @@ typedef enum s2w_dtype {
 } s2w_dtype;
 
 typedef enum s2w_diff { S2W_DIFF_NONE = 0, S2W_DIFF_BACKWARD = 1 } s2w_diff;
+
+/* Matrix-core products of the bfloat16 stores (float16 stores always take float16 products;
+ * products accumulate in float32 always).
+ *  AUTO  as F16.
+ *  BF16  bfloat16 products; each float32 activation value enters as a high and a low
+ *        bfloat16 term (two products, about 16 significant bits).
+ *  F16   float16 products: bfloat16 operator words are converted to float16 in registers,
+ *        exactly for every word within 2^31 of its row's largest (the power-of-two row scales
+ *        keep that largest in [2^14, 2^15]); each activation value enters as one float16 term
+ *        (11 significant bits) under a power-of-two scale per (bin, rupture).  Half the
+ *        products and activation bytes of BF16. */
+typedef enum s2w_products {
+  S2W_PRODUCTS_AUTO = 0,
+  S2W_PRODUCTS_BF16 = 1,
+  S2W_PRODUCTS_F16 = 2
+} s2w_products;
 
 /* Storage of the spectra and the kernels that go with it.
  *  SINGLE   float32 only: each (grid row, column) spectrum contiguous over the bins; forward
@@ -100,7 +116,7 @@ typedef struct s2w_desc {
   int32_t f_dtype;    /* s2w_dtype of the stored acoustic-gravity spectra */
   double dt;          /* time step in seconds (> 0); enters only through D_t */
   int32_t layout;     /* s2w_layout */
-  int32_t reserved;   /* must be 0 */
+  int32_t products;   /* s2w_products; must be 0 for float32 stores */
 } s2w_desc;
 
 /* Create a plan for `desc` on HIP device `device`.  Host-side only: no device
@@ -196,7 +212,8 @@ typedef struct s2w_tuning {
   int32_t adj_splits;        /* single-rupture adjoint: grid splits of the transposed elastic stage */
   int32_t batch_path_min_b;  /* reserved: ignored (the layout, fixed at plan creation, picks the path) */
   int32_t gemm_cfg;          /* batched elastic GEMM tile, 256 grid rows tall, persistent workgroups:
-                                -1 automatic (12 for B <= 64, else 18); 4 = 16 columns (four waves,
+                                -1 automatic (12 for B <= 64, else 18; with float16 products on
+                                bfloat16 words 16 and 10); 4 = 16 columns (four waves,
                                 register operands); 10 = 256 columns (eight waves, three-stage LDS copy
                                 pipeline); 12 = 128 columns (eight waves, four stages); 16 = 128 columns
                                 (four waves, two stages, two workgroups per compute unit); 17, 18 = 256
@@ -204,12 +221,12 @@ typedef struct s2w_tuning {
                                 stages).  A rupture takes two columns (real and imaginary part).  All
                                 tiles give the same results bit for bit. */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
-  int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (LDS-staged kernel for bf16 with
-                                B <= 64 where its tile fits, else the eight-wave kernel on real-column
-                                activation fragments), 2 eight-wave kernel on full fragments, 3 eight-wave
-                                kernel on real-column fragments (2 and 3 give the same results bit for
-                                bit), 4 LDS-staged kernel on packed bf16 activations where its tile fits
-                                (else, and for f16, as 3) */
+  int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (LDS-staged kernel for bfloat16 products
+                                with B <= 64 where its tile fits, else the eight-wave kernel on
+                                real-column activation fragments), 2 eight-wave kernel on full
+                                fragments, 3 eight-wave kernel on real-column fragments (2 and 3 give the
+                                same results bit for bit), 4 LDS-staged kernel on packed bfloat16
+                                activations where its tile fits (else, and for float16 products, as 3) */
   int32_t gemm32_cfg;        /* batched float32 GEMMs over grid rows (forward elastic, adjoint acoustic): tile,
                                 -1 automatic, 1..4 = rows x ruptures 64 x 128, 128 x 32, 256 x 8, 64 x 64 */
   int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint

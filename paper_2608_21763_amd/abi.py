@@ -15,6 +15,7 @@ DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 DIFF_NONE = 0
 DIFF_BACKWARD = 1
 LAYOUTS = {"auto": 0, "single": 1, "batched": 2, "direct": 3}
+PRODUCTS = {"auto": 0, "bf16": 1, "f16": 2}
 
 STATUS = {0: "S2W_OK", 1: "S2W_EINVAL", 2: "S2W_ENOMEM", 3: "S2W_ESTATE", 4: "S2W_EUNSUPPORTED", 5: "S2W_EHIP"}
 
@@ -30,7 +31,7 @@ class Desc(ctypes.Structure):
     _fields_ = [("nsub", ctypes.c_int32), ("ngrid", ctypes.c_int32), ("nobs", ctypes.c_int32),
                 ("nt", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("diff", ctypes.c_int32),
                 ("g_dtype", ctypes.c_int32), ("f_dtype", ctypes.c_int32), ("dt", ctypes.c_double),
-                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("products", ctypes.c_int32)]
 
 
 class BlttDesc(ctypes.Structure):
@@ -108,10 +109,10 @@ class Plan:
 
     def __init__(self, nsub: int, ngrid: int, nobs: int, nt: int, max_batch: int = 1, dt: float = 1.0,
                  diff: int = DIFF_BACKWARD, g_dtype: str = "f32", f_dtype: str = "f32", device: int = 0,
-                 layout: str = "auto"):
+                 layout: str = "auto", products: str = "auto"):
         self.lib = load_library()
         self.desc = Desc(nsub, ngrid, nobs, nt, max_batch, diff, DTYPES[g_dtype], DTYPES[f_dtype], dt,
-                         LAYOUTS[layout], 0)
+                         LAYOUTS[layout], PRODUCTS[products])
         self.handle = ctypes.c_void_p()
         st = self.lib.s2w_plan_create(ctypes.byref(self.desc), device, ctypes.byref(self.handle))
         if st != 0:

@@ -88,10 +88,14 @@ struct BatchGeo32 {
   int splits_a_max = 8;       // transposed elastic GEMM grid-row splits
 };
 
+// Type of the activation terms for product type kt (bf16 words converted to f16 meet f16 terms).
+static inline int act_type(int kt) { return kt == 3 ? 2 : kt; }
+
 // Extra geometry of the batched half-precision path.
 struct HalfGeo {
   bool on = false;
-  int ht_g = 1, ht_f = 1;     // 1 = bf16, 2 = f16
+  int ht_g = 1, ht_f = 1;     // stored words: 1 = bf16, 2 = f16
+  int kt_g = 1, kt_f = 1;     // products: 1 = bf16, 2 = f16, 3 = bf16 words converted to f16
   int hterms_g = 2, hterms_f = 2;
   int nsq, noq, ngq, nks;     // padded subfaults (x16), observers (16 * 2^k), grid rows (x16); K steps
   int bp;                     // max_batch padded to a multiple of 8
@@ -338,7 +342,9 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   if (d.g_dtype < S2W_F32 || d.g_dtype > S2W_F16 || d.f_dtype < S2W_F32 || d.f_dtype > S2W_F16) return S2W_EINVAL;
   const bool half = d.g_dtype != S2W_F32 || d.f_dtype != S2W_F32;
   if (half && (d.g_dtype == S2W_F32 || d.f_dtype == S2W_F32)) return S2W_EUNSUPPORTED;
-  if (d.layout < S2W_LAYOUT_AUTO || d.layout > S2W_LAYOUT_DIRECT || d.reserved != 0) return S2W_EINVAL;
+  if (d.layout < S2W_LAYOUT_AUTO || d.layout > S2W_LAYOUT_DIRECT) return S2W_EINVAL;
+  if (d.products < S2W_PRODUCTS_AUTO || d.products > S2W_PRODUCTS_F16 || (!half && d.products != S2W_PRODUCTS_AUTO))
+    return S2W_EINVAL;
   if (half && (d.layout == S2W_LAYOUT_SINGLE || d.layout == S2W_LAYOUT_DIRECT)) return S2W_EUNSUPPORTED;
   const bool batched32 =
       !half && (d.layout == S2W_LAYOUT_BATCHED || (d.layout == S2W_LAYOUT_AUTO && d.max_batch >= 8));
@@ -372,10 +378,14 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
     h.on = true;
     h.ht_g = d.g_dtype == S2W_BF16 ? 1 : 2;
     h.ht_f = d.f_dtype == S2W_BF16 ? 1 : 2;
-    // activations: a high and a low bf16 term each for bfloat16 operators; one scaled f16
-    // term for float16 operators (its rounding is then of the operator's own order)
-    h.hterms_g = d.g_dtype == S2W_F16 ? 1 : 2;
-    h.hterms_f = d.f_dtype == S2W_F16 ? 1 : 2;
+    // products: bfloat16 words either meet bfloat16 activations split into a high and a low
+    // term (two products each), or are converted to float16 in registers and meet one scaled
+    // f16 term, as float16 words always do (its rounding is then of the operator's own order)
+    const bool f16_products = d.products != S2W_PRODUCTS_BF16;
+    h.kt_g = h.ht_g == 2 ? 2 : (f16_products ? 3 : 1);
+    h.kt_f = h.ht_f == 2 ? 2 : (f16_products ? 3 : 1);
+    h.hterms_g = h.kt_g == 1 ? 2 : 1;
+    h.hterms_f = h.kt_f == 1 ? 2 : 1;
     h.nsq = (d.nsub + 15) / 16 * 16;
     h.noq = 16 * next_pow2((d.nobs + 15) / 16);
     h.ngq = (d.ngrid + 15) / 16 * 16;
@@ -732,7 +742,9 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   const int bp = h.bp;
   const int ncb = (2 * B + 15) / 16;
   int cfg = p->tune.gemm_cfg;
-  if (cfg < 0) cfg = B <= 64 ? 12 : 18;
+  // default tiles from sweeps on the Cascadia-sized share: with converted bfloat16 words the
+  // real-column tiles lose their edge (the conversions already load the vector ALUs)
+  if (cfg < 0) cfg = h.kt_g == 3 ? (B <= 64 ? 16 : 10) : (B <= 64 ? 12 : 18);
   // acoustic GEMM: fgemm_lds 2 takes the eight-wave kernel on full activation fragments, 3 the
   // eight-wave kernel on real-column fragments (with either the mid-chain leaves complex64),
   // 4 the LDS-staged kernel for packed bfloat16 activations where its tile fits (else, and for
@@ -740,7 +752,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   // where it fits, the real-column eight-wave kernel otherwise (Cascadia-sized share, bf16:
   // 26.9 against 30.4 ms per call at B = 128, 51.3 against 52.5 ms at B = 256)
   const int fl = p->tune.fgemm_lds;
-  const bool bf16_act = h.ht_f == 1 && h.hterms_f == 2;
+  const bool bf16_act = h.kt_f == 1;
   const bool fstaged = bf16_act && gemm_f2_supported(h.noq, B) && (fl == 4 || (fl == 1 && B <= 64));
   const bool wide_re = fl != 2;
   const int zt = fstaged ? gemm_f2_col_tiles(B) : ((g.nobs + 63) / 64) * gemm_fw_col_tiles(h.hterms_f, B, wide_re);
@@ -750,21 +762,22 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   hipError_t e = launch_rfft_rows(s, B, g.nsub, h.nsq, S, 1, bp, (int64_t)h.nsq * bp, g, 1.0f, st);
   if (e == hipSuccess) {
     if (cfg == 17 || cfg == 18)
-      e = launch_prep_act_re(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, (B + 15) / 16,
-                             Bop, st);
+      e = launch_prep_act_re(act_type(h.kt_g), h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks,
+                             (B + 15) / 16, Bop, st);
     else
-      e = launch_prep_act(h.ht_g, h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, ncb, Bop, st);
+      e = launch_prep_act(act_type(h.kt_g), h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks, ncb,
+                          Bop, st);
   }
   if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
   e = mark(p->ev_begin, st);
   if (e == hipSuccess) {
     const int nwg = p->ncu * p->tune.fused_wg_per_cu;
-    e = launch_gemm_g(h.ht_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, ncb, B, bp,
+    e = launch_gemm_g(h.kt_g, h.hterms_g, cfg, Gq, sG, Bop, sig_down, (float*)U, nwg, g.ngrid, g.M, h.nks, ncb, B, bp,
                       st);
   }
   if (e == hipSuccess) e = mark(p->ev_end, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: elastic matrix-core stage");
-  const bool fscale = h.ht_f == 2;
+  const bool fscale = h.kt_f != 1;
   // float16 acoustic operands: the column scales come from maxima the mid-chain keeps as it
   // writes (M = 256), else from a pass over U
   int groups = 0;
@@ -780,7 +793,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
     e = launch_gemm_f2(Fq, (const uint2*)U, part, g.ngrid, h.ngq, g.M, h.noq, B, bp, splits, st);
   } else {
     splits = std::min(splits, h.ngq / 16);
-    e = launch_gemm_fw(h.ht_f, h.hterms_f, (const uint32_t*)Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq,
+    e = launch_gemm_fw(h.kt_f, h.hterms_f, (const uint32_t*)Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq,
                        g.M, h.noq, g.nobs, B, bp, splits, wide_re, st);
   }
   if (e == hipSuccess)
@@ -914,7 +927,7 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   const uint32_t* Fq = (const uint32_t*)(p->op + L.fq);
   const float* sF = (const float*)(p->op + L.sf);
   const int bp = h.bp;
-  const bool sf16 = h.ht_f == 2, sg16 = h.ht_g == 2;
+  const bool sf16 = h.kt_f != 1, sg16 = h.kt_g != 1;  // f16 activation terms with column scales
   hipError_t e = launch_rfft_rows(r, B, g.nobs, g.nobs, R, 1, bp, (int64_t)g.nobs * bp, g, 1.0f, st);
   if (e == hipSuccess && sf16) e = launch_act_scale(R, g.M, g.nobs, g.nobs, B, bp, sig_up, sig_down, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
@@ -922,7 +935,7 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   // default tiles (sweep on the Cascadia-sized share): eight waves on real-column activation
   // fragments, 256 rows x 128 columns, and 256 x 64 for batches of at most 32
   const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 5 : 6);
-  e = launch_gemm_t(h.ht_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, 16 * (int64_t)h.ngq, h.ngq, 16, g.ngrid,
+  e = launch_gemm_t(h.kt_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, 16 * (int64_t)h.ngq, h.ngq, 16, g.ngrid,
                     h.ngq, g.nobs, h.noq, R,
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,
                     (float*)W, 0, 2 * (int64_t)bp, 2 * (int64_t)g.M * bp, B, bp, g.M, 1, st);
@@ -948,7 +961,7 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   sa = std::min(std::min(std::min(sa, fit), 8), (g.ngrid + 15) / 16);
   e = mark(p->ev_begin, st);
   if (e == hipSuccess)
-    e = launch_gemm_t(h.ht_g, h.hterms_g, shape3, Gq, (int64_t)(h.ngq / 16) * h.nks * 256, (int64_t)h.nks * 256, 16,
+    e = launch_gemm_t(h.kt_g, h.hterms_g, shape3, Gq, (int64_t)(h.ngq / 16) * h.nks * 256, (int64_t)h.nks * 256, 16,
                       256, g.nsub, h.nsq, g.ngrid,
                       (g.ngrid + 15) / 16 * 16, W, bp, (int64_t)g.M * bp, g.ngrid, sg16 ? tau_up : nullptr,
                       sg16 ? tau_down : nullptr, nullptr, 0, 0, part, (int64_t)g.M * h.nsq * prow,

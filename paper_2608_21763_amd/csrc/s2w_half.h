@@ -73,6 +73,32 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
                                                   0, 0);
 }
 
+// Product types.  HT names the operator words and the products: 1 bfloat16 words, bfloat16
+// products; 2 float16 words and products; 3 bfloat16 words converted to float16 in registers
+// (op_word), float16 products.  kActT<HT> is the type of the activation terms and of the
+// matrix-core instruction.
+template <int HT>
+constexpr int kActT = HT == 3 ? 2 : HT;
+
+// bfloat16 pair -> float16 pair, low half first.  The stores' power-of-two row scales put every
+// row maximum in [2^14, 2^15], inside float16's range; bfloat16's 8 significant bits fit
+// float16's grid down to 2^-17 (normals from 2^-14, subnormal steps of 2^-24), so every word
+// within 2^31 of its row maximum converts exactly, and smaller ones (below 2^-17) are cut
+// toward zero by at most 2^-24 absolute.
+__device__ __forceinline__ uint32_t bf16x2_to_f16x2(uint32_t w) {
+  const float lo = __uint_as_float(w << 16), hi = __uint_as_float(w & 0xffff0000u);
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(lo, hi));
+}
+
+// Operator fragment (8 half words) in the instruction's type.
+template <int HT>
+__device__ __forceinline__ uint4 op_word(uint4 a) {
+  if constexpr (HT == 3)
+    return make_uint4(bf16x2_to_f16x2(a.x), bf16x2_to_f16x2(a.y), bf16x2_to_f16x2(a.z), bf16x2_to_f16x2(a.w));
+  else
+    return a;
+}
+
 // power-of-two scale that maps a row maximum mx into [2^14, 2^15); returns the multiplier
 // applied before rounding (`up`) and its inverse (`down`)
 __device__ __forceinline__ void pow2_scale(float mx, float& up, float& down) {

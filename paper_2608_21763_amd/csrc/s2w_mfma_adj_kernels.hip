@@ -128,15 +128,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
     for (int it = 0; it < 2; ++it) {
       const int i = tid + 512 * it;
       const int kk = i >> 6, rg = i & 63;
-      *reinterpret_cast<uint4*>(&la_s[buf][kk * LDA + 4 * rg]) = ast[it];
+      *reinterpret_cast<uint4*>(&la_s[buf][kk * LDA + 4 * rg]) = op_word<HT>(ast[it]);
     }
 #pragma unroll
     for (int rp = 0; rp < XREP; ++rp) {
       const int s = tid + 512 * rp;
       if (s < XSLOTS) {
         uint4* dst = &lb_s[buf][(s >> 6) * H * 64 + (s & 63)];
-        if (RE) t2_convert_re<HT, H>(xv[rp], upx[rp], dc, dst);
-        else t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, dst);
+        if (RE) t2_convert_re<kActT<HT>, H>(xv[rp], upx[rp], dc, dst);
+        else t2_convert<kActT<HT>, H>(xv[rp], upx[rp], dc, s & 1, dst);
       }
     }
   };
@@ -168,9 +168,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
             const uint4 bi = make_uint4(t2_im_word(w.x, dc), t2_im_word(w.y, dc), t2_im_word(w.z, dc),
                                         t2_im_word(w.w, dc));
 #pragma unroll
-            for (int a = 0; a < MF; ++a) acc[a][2 * fr] = mfma16<HT>(av[a], br, acc[a][2 * fr]);
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr] = mfma16<kActT<HT>>(av[a], br, acc[a][2 * fr]);
 #pragma unroll
-            for (int a = 0; a < MF; ++a) acc[a][2 * fr + 1] = mfma16<HT>(av[a], bi, acc[a][2 * fr + 1]);
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr + 1] = mfma16<kActT<HT>>(av[a], bi, acc[a][2 * fr + 1]);
           }
         }
       } else {
@@ -179,11 +179,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
           const int cb = NF * wc + f;
           const uint4 bh = lb_s[cur][cb * H * 64 + lane];
 #pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
+          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<kActT<HT>>(av[a], bh, acc[a][f]);
           if (H == 2) {
             const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
 #pragma unroll
-            for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+            for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<kActT<HT>>(av[a], bo, acc[a][f]);
           }
         }
       }
@@ -279,11 +279,11 @@ hipError_t launch_gemm_t(int ht, int hterms, int shape, const uint32_t* Aq, int6
     else if (shape == 6) S2W_GT2(HT_, H_, 4, true);                           \
     else S2W_GT2(HT_, H_, 8, true);                                           \
   } while (0)
-  if (ht == 1) {
-    if (hterms == 2) S2W_GT2_NF(1, 2); else S2W_GT2_NF(1, 1);
-  } else {
-    if (hterms == 2) S2W_GT2_NF(2, 2); else S2W_GT2_NF(2, 1);
-  }
+  // operand pairs of the plans (as in the forward kernels)
+  if (ht == 1 && hterms == 2) S2W_GT2_NF(1, 2);
+  else if (ht == 2 && hterms == 1) S2W_GT2_NF(2, 1);
+  else if (ht == 3 && hterms == 1) S2W_GT2_NF(3, 1);
+  else return hipErrorInvalidValue;
 #undef S2W_GT2
 #undef S2W_GT2_NF
   return hipGetLastError();

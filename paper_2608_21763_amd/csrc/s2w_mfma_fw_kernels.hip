@@ -85,14 +85,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RE ? 4 : 1)
       }
   };
   auto stage = [&](int buf) {
-    if (aown) la_s[buf][tid] = ast;
+    if (aown) la_s[buf][tid] = op_word<HT>(ast);
 #pragma unroll
     for (int rp = 0; rp < XREP; ++rp) {
       const int s = tid + 512 * rp;
       if (s < XSLOTS) {
         uint4* dst = &lb_s[buf][(s >> 6) * H * 64 + (s & 63)];
-        if (RE) t2_convert_re<HT, H>(xv[rp], upx[rp], dc, dst);
-        else t2_convert<HT, H>(xv[rp], upx[rp], dc, s & 1, dst);
+        if (RE) t2_convert_re<kActT<HT>, H>(xv[rp], upx[rp], dc, dst);
+        else t2_convert<kActT<HT>, H>(xv[rp], upx[rp], dc, s & 1, dst);
       }
     }
   };
@@ -119,9 +119,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RE ? 4 : 1)
             const uint4 bi = make_uint4(t2_im_word(w.x, dc), t2_im_word(w.y, dc), t2_im_word(w.z, dc),
                                         t2_im_word(w.w, dc));
 #pragma unroll
-            for (int a = 0; a < MF; ++a) acc[a][2 * fr] = mfma16<HT>(av[a], br, acc[a][2 * fr]);
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr] = mfma16<kActT<HT>>(av[a], br, acc[a][2 * fr]);
 #pragma unroll
-            for (int a = 0; a < MF; ++a) acc[a][2 * fr + 1] = mfma16<HT>(av[a], bi, acc[a][2 * fr + 1]);
+            for (int a = 0; a < MF; ++a) acc[a][2 * fr + 1] = mfma16<kActT<HT>>(av[a], bi, acc[a][2 * fr + 1]);
           }
         }
       } else {
@@ -130,11 +130,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(RE ? 4 : 1)
           const int cb = NF * wave + f;
           const uint4 bh = lb_s[cur][cb * H * 64 + lane];
 #pragma unroll
-          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bh, acc[a][f]);
+          for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<kActT<HT>>(av[a], bh, acc[a][f]);
           if (H == 2) {
             const uint4 bo = lb_s[cur][cb * H * 64 + 64 + lane];
 #pragma unroll
-            for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<HT>(av[a], bo, acc[a][f]);
+            for (int a = 0; a < MF; ++a) acc[a][f] = mfma16<kActT<HT>>(av[a], bo, acc[a][f]);
           }
         }
       }
@@ -208,18 +208,16 @@ hipError_t launch_gemm_fw(int ht, int hterms, const uint32_t* Fq, const float2* 
     else                                 \
       S2W_FW1(HT_, H_, NF_, false);      \
   } while (0)
-  if (ht == 1) {
-    if (hterms == 2) {
-      if (nf == 1) S2W_FW(1, 2, 1); else if (nf == 2) S2W_FW(1, 2, 2); else S2W_FW1(1, 2, 4, true);
-    } else {
-      if (nf == 1) S2W_FW(1, 1, 1); else if (nf == 2) S2W_FW(1, 1, 2); else S2W_FW(1, 1, 4);
-    }
+  // operand pairs of the plans: bf16 words with two bf16 activation terms, f16 words with one
+  // f16 term, bf16 words converted to f16 with one f16 term
+  if (ht == 1 && hterms == 2) {
+    if (nf == 1) S2W_FW(1, 2, 1); else if (nf == 2) S2W_FW(1, 2, 2); else S2W_FW1(1, 2, 4, true);
+  } else if (ht == 2 && hterms == 1) {
+    if (nf == 1) S2W_FW(2, 1, 1); else if (nf == 2) S2W_FW(2, 1, 2); else S2W_FW(2, 1, 4);
+  } else if (ht == 3 && hterms == 1) {
+    if (nf == 1) S2W_FW(3, 1, 1); else if (nf == 2) S2W_FW(3, 1, 2); else S2W_FW(3, 1, 4);
   } else {
-    if (hterms == 2) {
-      if (nf == 1) S2W_FW(2, 2, 1); else if (nf == 2) S2W_FW(2, 2, 2); else S2W_FW1(2, 2, 4, true);
-    } else {
-      if (nf == 1) S2W_FW(2, 1, 1); else if (nf == 2) S2W_FW(2, 1, 2); else S2W_FW(2, 1, 4);
-    }
+    return hipErrorInvalidValue;
   }
 #undef S2W_FW
 #undef S2W_FW1

@@ -179,11 +179,9 @@ hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, f
   dim3 grid((unsigned)((total + 255) / 256));
 #define S2W_PREP(HT_, H_) \
   hipLaunchKernelGGL((k_prep_act<HT_, H_>), grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, ncb, Bop)
-  if (ht == 1) {
-    if (hterms == 2) S2W_PREP(1, 2); else S2W_PREP(1, 1);
-  } else {
-    if (hterms == 2) S2W_PREP(2, 2); else S2W_PREP(2, 1);
-  }
+  if (ht == 1 && hterms == 2) S2W_PREP(1, 2);
+  else if (ht == 2 && hterms == 1) S2W_PREP(2, 1);
+  else return hipErrorInvalidValue;
 #undef S2W_PREP
   return hipGetLastError();
 }
@@ -245,11 +243,9 @@ hipError_t launch_prep_act_re(int ht, int hterms, const float2* S, float* sig_up
   dim3 grid((unsigned)((total + 255) / 256));
 #define S2W_PREPR(HT_, H_) \
   hipLaunchKernelGGL((k_prep_act_re<HT_, H_>), grid, dim3(256), 0, st, S, sig_up, M, nsub, nsq, B, bp, nks, nrcb, Bre)
-  if (ht == 1) {
-    if (hterms == 2) S2W_PREPR(1, 2); else S2W_PREPR(1, 1);
-  } else {
-    if (hterms == 2) S2W_PREPR(2, 2); else S2W_PREPR(2, 1);
-  }
+  if (ht == 1 && hterms == 2) S2W_PREPR(1, 2);
+  else if (ht == 2 && hterms == 1) S2W_PREPR(2, 1);
+  else return hipErrorInvalidValue;
 #undef S2W_PREPR
   return hipGetLastError();
 }
@@ -300,7 +296,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
     for (int ks = 0; ks < nks; ++ks) {
       uint4 av[MF], bv[NF][H];
 #pragma unroll
-      for (int a = 0; a < MF; ++a) av[a] = ntload(arow[a] + kGqStepU4 * ks);
+      for (int a = 0; a < MF; ++a) av[a] = op_word<HT>(ntload(arow[a] + kGqStepU4 * ks));
 #pragma unroll
       for (int b = 0; b < NF; ++b)
 #pragma unroll
@@ -313,7 +309,7 @@ __global__ __launch_bounds__(64 * WR * WC, 1) void k_gemm_g(const uint4* __restr
 #pragma unroll
         for (int b = 0; b < NF; ++b)
 #pragma unroll
-          for (int h = 0; h < H; ++h) acc[a][b] = mfma16<HT>(av[a], bv[b][h], acc[a][b]);
+          for (int h = 0; h < H; ++h) acc[a][b] = mfma16<kActT<HT>>(av[a], bv[b][h], acc[a][b]);
     }
     if (!colok) continue;
 #pragma unroll
@@ -376,14 +372,14 @@ __device__ __forceinline__ void g4_compute(const uint4* cur, f32x4 (&acc)[MF][NF
   const uint4* lb = cur + A_BLK * 64;
   uint4 av[MF];
 #pragma unroll
-  for (int a = 0; a < MF; ++a) av[a] = cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+  for (int a = 0; a < MF; ++a) av[a] = op_word<HT>(cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)]);
 #pragma unroll
   for (int b = 0; b < NF; ++b)
 #pragma unroll
     for (int h = 0; h < H; ++h) {
       const uint4 bv = lb[((wc * NF + b) * H + h) * 64 + lane];
 #pragma unroll
-      for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<HT>(av[a], bv, acc[a][b]);
+      for (int a = 0; a < MF; ++a) acc[a][b] = mfma16<kActT<HT>>(av[a], bv, acc[a][b]);
     }
   (void)WC;
 }
@@ -403,7 +399,7 @@ __device__ __forceinline__ void g4_compute_re(const uint4* cur, f32x4 (&acc)[MF]
   const uint4* lb = cur + A_BLK * 64;
   uint4 av[MF];
 #pragma unroll
-  for (int a = 0; a < MF; ++a) av[a] = cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+  for (int a = 0; a < MF; ++a) av[a] = op_word<HT>(cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)]);
 #pragma unroll
   for (int q = 0; q < NF / 2; ++q)
 #pragma unroll
@@ -412,9 +408,9 @@ __device__ __forceinline__ void g4_compute_re(const uint4* cur, f32x4 (&acc)[MF]
       const uint4 re = dc ? make_uint4(w.x & 0xffffu, w.y & 0xffffu, w.z & 0xffffu, w.w & 0xffffu) : w;
       const uint4 im = make_uint4(im_word(w.x, dc), im_word(w.y, dc), im_word(w.z, dc), im_word(w.w, dc));
 #pragma unroll
-      for (int a = 0; a < MF; ++a) acc[a][2 * q] = mfma16<HT>(av[a], re, acc[a][2 * q]);
+      for (int a = 0; a < MF; ++a) acc[a][2 * q] = mfma16<kActT<HT>>(av[a], re, acc[a][2 * q]);
 #pragma unroll
-      for (int a = 0; a < MF; ++a) acc[a][2 * q + 1] = mfma16<HT>(av[a], im, acc[a][2 * q + 1]);
+      for (int a = 0; a < MF; ++a) acc[a][2 * q + 1] = mfma16<kActT<HT>>(av[a], im, acc[a][2 * q + 1]);
     }
   (void)WC;
 }
@@ -603,11 +599,12 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
 hipError_t launch_gemm_g(int ht, int hterms, int cfg, const uint4* Gq, const float* sG, const uint4* Bop,
                          const float* sig_down, float* U, int nwg, int ngrid, int M, int nks, int ncb, int B, int bp,
                          hipStream_t st) {
-  if (ht == 1)
-    return hterms == 2 ? gemm_g_h<1, 2>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st)
-                       : gemm_g_h<1, 1>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
-  return hterms == 2 ? gemm_g_h<2, 2>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st)
-                     : gemm_g_h<2, 1>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
+  // operand pairs of the plans: bf16 words with two bf16 activation terms, f16 words with one
+  // f16 term, bf16 words converted to f16 with one f16 term
+  if (ht == 1 && hterms == 2) return gemm_g_h<1, 2>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
+  if (ht == 2 && hterms == 1) return gemm_g_h<2, 1>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
+  if (ht == 3 && hterms == 1) return gemm_g_h<3, 1>(cfg, Gq, sG, Bop, sig_down, U, nwg, ngrid, M, nks, ncb, B, bp, st);
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -44,13 +44,13 @@ class S2WOperator:
 
     def __init__(self, nsub: int, ngrid: int, nobs: int, nt: int, max_batch: int = 1, dt: float = 1.0,
                  diff: int = DIFF_BACKWARD, g_dtype: str = "f32", f_dtype: str = "f32", device: int | str = 0,
-                 layout: str = "auto"):
+                 layout: str = "auto", products: str = "auto"):
         self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
         idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
         self.nsub, self.ngrid, self.nobs, self.nt, self.max_batch = nsub, ngrid, nobs, nt, max_batch
         self.dt, self.diff, self.g_dtype, self.f_dtype = dt, diff, g_dtype, f_dtype
-        self.layout = layout
-        self.plan = Plan(nsub, ngrid, nobs, nt, max_batch, dt, diff, g_dtype, f_dtype, idx, layout)
+        self.layout, self.products = layout, products
+        self.plan = Plan(nsub, ngrid, nobs, nt, max_batch, dt, diff, g_dtype, f_dtype, idx, layout, products)
         op_bytes, ws_bytes = self.plan.query_sizes()
         self.op_store = torch.empty(max(op_bytes, 1), dtype=torch.uint8, device=self.device)
         self.workspace = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=self.device)

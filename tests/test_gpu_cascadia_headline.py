@@ -33,10 +33,11 @@ def headline_reference():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("dtypes", [("bf16", "bf16"), ("f16", "f16"), ("bf16", "f16")])
+@pytest.mark.parametrize("dtypes", [("bf16", "bf16", "auto"), ("bf16", "bf16", "bf16"), ("f16", "f16", "auto"),
+                                    ("bf16", "f16", "auto")])
 def test_headline_batch256(dtypes):
-    gdt, fdt = dtypes
-    dtype = f"{gdt}/{fdt}"
+    gdt, fdt, products = dtypes
+    dtype = f"{gdt}/{fdt}" + (" bf16 products" if products == "bf16" else "")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     cfg = synth.workload("cascadia_batch")
@@ -47,7 +48,7 @@ def test_headline_batch256(dtypes):
     act_now = np.array([np.count_nonzero(np.any(s[b] != 0, axis=1)) for b in idx])
     assert np.array_equal(act_now, act), "the stored reference is for another batch"
     assert act.min() == min(np.count_nonzero(np.any(sb != 0, axis=1)) for sb in s)
-    op = make_operator(cfg, max_batch=B, chunk_rows=1024, g_dtype=gdt, f_dtype=fdt)
+    op = make_operator(cfg, max_batch=B, chunk_rows=1024, g_dtype=gdt, f_dtype=fdt, products=products)
     y = op.forward(to_dev(s)).cpu().numpy()
     assert np.all(np.isfinite(y))
     rel = np.array([oracle.rel_l2(y[b], ref[i]) for i, b in enumerate(idx)])

@@ -18,6 +18,7 @@ KINDS = {
     "single": dict(layout="single"),
     "batched32": dict(layout="batched"),
     "half": dict(g_dtype="bf16", f_dtype="bf16"),
+    "half_bf16_products": dict(g_dtype="bf16", f_dtype="bf16", products="bf16"),
     "half16": dict(g_dtype="f16", f_dtype="f16"),
 }
 

@@ -18,6 +18,7 @@ PATHS = {
     "f16": (dict(g_dtype="f16", f_dtype="f16"), HALF_BOUND),
     # bf16 stores do not meet the 2e-3 bound on dense iid operators: a regression ceiling
     "bf16": (dict(g_dtype="bf16", f_dtype="bf16"), BF16_CEILING),
+    "bf16h": (dict(g_dtype="bf16", f_dtype="bf16", products="bf16"), BF16_CEILING),
 }
 
 
@@ -47,7 +48,7 @@ def test_all_maxima(path):
     assert eg.max() <= tol
 
 
-@pytest.mark.parametrize("path", ["batched32", "f16", "bf16"])
+@pytest.mark.parametrize("path", ["batched32", "f16", "bf16", "bf16h"])
 def test_largest_batch(path):
     kw, tol = PATHS[path]
     cfg = synth.SynthConfig(nsub=8, ngrid=64, nobs=4, nt=16, seed=93, slip_seed=94, op_kind="dense",
