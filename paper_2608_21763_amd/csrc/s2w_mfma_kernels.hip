@@ -370,6 +370,31 @@ __device__ __forceinline__ void g4_sync() {
 template <int HT, int H, int MF, int NF, int MW, int A_BLK, int WC>
 __device__ __forceinline__ void g4_compute(const uint4* cur, f32x4 (&acc)[MF][NF], int wr, int wc, int lane) {
   const uint4* lb = cur + A_BLK * 64;
+  if constexpr (HT == 3 && H == 1) {
+    // converted bfloat16 words: fragment a + 1 is converted (12 vector ALU instructions) under
+    // the NF products of fragment a, instead of all conversions ahead of all products; each
+    // output still takes its products in the same order
+    uint4 raw[MF], bv[NF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a) raw[a] = cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+    for (int b = 0; b < NF; ++b) bv[b] = lb[(wc * NF + b) * 64 + lane];
+    uint4 av = op_word<3>(raw[0]);
+    __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+#pragma unroll
+    for (int a = 0; a < MF; ++a) {
+      const uint4 nxt = op_word<3>(raw[a + 1 < MF ? a + 1 : a]);
+#pragma unroll
+      for (int b = 0; b < NF; ++b) acc[a][b] = mfma16<2>(av, bv[b], acc[a][b]);
+      av = nxt;
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (a + 1 < MF) __builtin_amdgcn_sched_group_barrier(0x002, 12 / NF, 0);
+      }
+    }
+    return;
+  }
   uint4 av[MF];
 #pragma unroll
   for (int a = 0; a < MF; ++a) av[a] = op_word<HT>(cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)]);
@@ -397,6 +422,37 @@ template <int HT, int H, int MF, int NF, int MW, int A_BLK, int WC>
 __device__ __forceinline__ void g4_compute_re(const uint4* cur, f32x4 (&acc)[MF][NF], int wr, int wc, int lane,
                                               bool dc) {
   const uint4* lb = cur + A_BLK * 64;
+  if constexpr (HT == 3 && H == 1) {
+    // converted bfloat16 words, as in g4_compute: the real- and imaginary-column fragments
+    // first, then fragment a + 1 converted under the products of fragment a
+    uint4 raw[MF], re[NF / 2], im[NF / 2];
+#pragma unroll
+    for (int a = 0; a < MF; ++a) raw[a] = cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)];
+#pragma unroll
+    for (int q = 0; q < NF / 2; ++q) {
+      const uint4 w = lb[(wc * (NF / 2) + q) * 64 + lane];
+      re[q] = dc ? make_uint4(w.x & 0xffffu, w.y & 0xffffu, w.z & 0xffffu, w.w & 0xffffu) : w;
+      im[q] = make_uint4(im_word(w.x, dc), im_word(w.y, dc), im_word(w.z, dc), im_word(w.w, dc));
+    }
+    uint4 av = op_word<3>(raw[0]);
+    __builtin_amdgcn_sched_group_barrier(0x002, 12 + 20 * (NF / 2), 0);
+#pragma unroll
+    for (int a = 0; a < MF; ++a) {
+      const uint4 nxt = op_word<3>(raw[a + 1 < MF ? a + 1 : a]);
+#pragma unroll
+      for (int q = 0; q < NF / 2; ++q) {
+        acc[a][2 * q] = mfma16<2>(av, re[q], acc[a][2 * q]);
+        acc[a][2 * q + 1] = mfma16<2>(av, im[q], acc[a][2 * q + 1]);
+      }
+      av = nxt;
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if (a + 1 < MF) __builtin_amdgcn_sched_group_barrier(0x002, 12 / NF, 0);
+      }
+    }
+    return;
+  }
   uint4 av[MF];
 #pragma unroll
   for (int a = 0; a < MF; ++a) av[a] = op_word<HT>(cur[swz(wr * MW + 16 * a + (lane & 15), lane >> 4)]);
