@@ -326,10 +326,12 @@ __device__ __forceinline__ void fft256_passA(float2 (&v)[16], int c, const float
 // spectra and is overwritten; T (LDS, at least R*16*17 values) receives the packed output
 // spectra with row stride ldt (256 <= ldt <= 272).
 // Same arithmetic as lds_midchain2 (inverse real FFT, truncate to nt, D_t, zero-pad, forward
-// real FFT), with the complex transforms done as two 16-point passes in registers.
-__device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int mode, float scale,
-                                       const Twiddles& tw, int ldx = 256, int ldt = 256,
-                                       const DispRows* disp = nullptr, const short* dtab = nullptr) {
+// real FFT), with the complex transforms done as two 16-point passes in registers.  MODE is the
+// MidMode, fixed at compile time so that the time step has no branches.
+template <int MODE>
+__device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, float scale, const Twiddles& tw,
+                                       int ldx = 256, int ldt = 256, const DispRows* disp = nullptr,
+                                       const short* dtab = nullptr) {
   constexpr int M = 256;
   const int tid = threadIdx.x;
   const int r = tid >> 4, c = tid & 15;
@@ -364,12 +366,15 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, int 
       if (m0 < nt) disp_put(disp, dtab, r, m0, z.x);
       if (m1 < nt) disp_put(disp, dtab, r, m1, z.y);
       float a = 0.f, b = 0.f;
-      if (mode == MID_BACKWARD) {
-        const float xm1 = n > 0 ? Xr[n - 1].y : 0.f;
+      // neighbours are read unconditionally (clamped index) and selected, so no lane branches
+      if constexpr (MODE == MID_BACKWARD) {
+        const float2 zp = Xr[n > 0 ? n - 1 : 0];
+        const float xm1 = n > 0 ? zp.y : 0.f;
         a = m0 < nt ? z.x - xm1 : 0.f;
         b = m1 < nt ? z.y - z.x : 0.f;
-      } else if (mode == MID_BACKWARD_T) {
-        const float xp2 = (n + 1 < M && m1 + 1 < nt) ? Xr[n + 1].x : 0.f;
+      } else if constexpr (MODE == MID_BACKWARD_T) {
+        const float2 zn = Xr[n + 1 < M ? n + 1 : M - 1];
+        const float xp2 = (n + 1 < M && m1 + 1 < nt) ? zn.x : 0.f;
         a = m0 < nt ? z.x - (m1 < nt ? z.y : 0.f) : 0.f;
         b = m1 < nt ? z.y - xp2 : 0.f;
       } else {

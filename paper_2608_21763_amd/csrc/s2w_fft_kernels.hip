@@ -574,9 +574,9 @@ __global__ __launch_bounds__(256) void k_mid_batch(float2* __restrict__ U, const
 // With cmax, the grid is a multiple of the rupture blocks per row (nbb), so a workgroup always
 // works on the same block of ruptures; it keeps the largest |Re|, |Im| of every (slot, rupture)
 // it writes and leaves them in cmax[blockIdx / nbb][l][b] (b < bp; zero for b >= B).
-template <int PACK, int R, bool DISP>
+template <int PACK, int R, bool DISP, int MODE>
 __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U, const float* __restrict__ sF,
-                                                         int ngrid, int B, int bp, int nt, int mode, float mscale,
+                                                         int ngrid, int B, int bp, int nt, float mscale,
                                                          float* __restrict__ cmax, DispOut disp) {
   constexpr int M = 256, LD = 257;
   __shared__ float2 X[R * LD];
@@ -588,39 +588,42 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
   const int tid = threadIdx.x;
   const int r = tid % R, lq = tid / R;  // gather/scatter: rupture r, slots lq + 16 k
   const int nbb = (B + R - 1) / R;
-  const int64_t units = (int64_t)ngrid * nbb;
+  const int units = ngrid * nbb;  // the launcher checks that this fits an int
   float2 pre[16];
   float fs[16];
   float cmx[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) cmx[k] = 0.f;
-  auto fetch = [&](int64_t u) {
-    const int g = (int)(u / nbb);
-    const int b = (int)(u % nbb) * R + r;
-    const float2* src = U + (int64_t)g * M * bp + b;
+  // loads are unconditional (ruptures past B read rupture B - 1 and are zeroed), so that the
+  // gather has no lane branches
+  auto fetch = [&](int u) {
+    const int g = u / nbb;
+    const int b = (u % nbb) * R + r;
+    const float2* src = U + (int64_t)g * M * bp + (b < B ? b : B - 1);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int l = lq + 16 * k;
-      pre[k] = b < B ? src[(int64_t)l * bp] : make_float2(0.f, 0.f);
+      const float2 v = src[(int64_t)l * bp];
+      pre[k] = b < B ? v : make_float2(0.f, 0.f);
       fs[k] = sF ? sF[(int64_t)g * M + l] : 1.f;
     }
   };
-  int64_t u = blockIdx.x;
+  int u = blockIdx.x;
   if (u < units) fetch(u);
   for (; u < units; u += gridDim.x) {
-    const int g = (int)(u / nbb);
-    const int b = (int)(u % nbb) * R + r;
+    const int g = u / nbb;
+    const int b = (u % nbb) * R + r;
 #pragma unroll
     for (int k = 0; k < 16; ++k) X[r * LD + lq + 16 * k] = pre[k];
     float f[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) f[k] = fs[k];
     __syncthreads();
-    if (u + gridDim.x < units) fetch(u + gridDim.x);
-    const int b0 = (int)(u % nbb) * R;
+    if (u + (int)gridDim.x < units) fetch(u + gridDim.x);
+    const int b0 = (u % nbb) * R;
     const DispRows dr{disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride, disp.row_stride,
                       B - b0, disp.scale};
-    mid256(X, T, R, nt, mode, mscale, tw, LD, LD, DISP ? &dr : nullptr, dtab);
+    mid256<MODE>(X, T, R, nt, mscale, tw, LD, LD, DISP ? &dr : nullptr, dtab);
     float2* dst = U + (int64_t)g * M * bp + b;
     if (b < B) {
 #pragma unroll
@@ -668,21 +671,30 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
       nb256 = groups * nbb;
       if (cmax_groups) *cmax_groups = (int)groups;
     }
+    if (B < 1 || units256 > 0x7fffffff) return hipErrorInvalidValue;
+#define S2W_MID256K(P_, R_, D_, M_)                                                                              \
+  hipLaunchKernelGGL((k_mid_batch256<P_, R_, D_, M_>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF, g.ngrid, B, \
+                     bp, g.nt, mscale, cmax, dd)
+    // forward: packed or plain output, with or without displacement capture; adjoint: plain
 #define S2W_MID256(P_, R_)                                                                                       \
   do {                                                                                                            \
-    if (dd.base)                                                                                                  \
-      hipLaunchKernelGGL((k_mid_batch256<P_, R_, true>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF,        \
-                         g.ngrid, B, bp, g.nt, mode, mscale, cmax, dd);                                            \
-    else                                                                                                          \
-      hipLaunchKernelGGL((k_mid_batch256<P_, R_, false>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF,       \
-                         g.ngrid, B, bp, g.nt, mode, mscale, cmax, dd);                                            \
+    if (adjoint) {                                                                                                \
+      if (mode == MID_BACKWARD_T) S2W_MID256K(0, R_, false, MID_BACKWARD_T);                                      \
+      else S2W_MID256K(0, R_, false, MID_NONE);                                                                   \
+    } else if (mode == MID_BACKWARD) {                                                                            \
+      if (dd.base) S2W_MID256K(P_, R_, true, MID_BACKWARD); else S2W_MID256K(P_, R_, false, MID_BACKWARD);        \
+    } else {                                                                                                      \
+      if (dd.base) S2W_MID256K(P_, R_, true, MID_NONE); else S2W_MID256K(P_, R_, false, MID_NONE);                \
+    }                                                                                                             \
   } while (0)
+    if (adjoint && (pack_bf16 || dd.base)) return hipErrorInvalidValue;
     if (ru == 32) {
       if (pack_bf16) S2W_MID256(1, 32); else S2W_MID256(0, 32);
     } else {
       if (pack_bf16) S2W_MID256(1, 16); else S2W_MID256(0, 16);
     }
 #undef S2W_MID256
+#undef S2W_MID256K
     return hipGetLastError();
   }
   const size_t lds = (2 * (size_t)g.M * (R + 1) + 2 * (size_t)g.M) * sizeof(float2);
