@@ -70,9 +70,10 @@ def kernel_source_hash(kernel: str | None = None) -> str:
     return h.hexdigest()[:12]
 
 
-def traffic_for(kernel: str):
+def traffic_for(kernel: str, gemm_cfg: int | None = None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter figures
-    (profiles/traffic_<kernel>.json), or None when its sources changed since they were taken."""
+    (profiles/traffic_<kernel>.json), or None when its sources changed since they were taken
+    or they were taken on another tile than `gemm_cfg`."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
     if not os.path.exists(path):
         return None
@@ -80,7 +81,19 @@ def traffic_for(kernel: str):
         d = json.load(fh)
     if d.get("source_hash") != kernel_source_hash(kernel):
         return None
+    if gemm_cfg is not None and d.get("gemm_cfg", gemm_cfg) != gemm_cfg:
+        return None
     return d.get("bytes_per_launch")
+
+
+def effective_tile(cfg: int, B: int, converted: bool) -> int:
+    """Elastic GEMM tile a call runs with: `cfg` (from s2w_get_tuning), or for -1 the library's
+    default for B (forward_half in s2w_api.cpp); `converted`: bfloat16 words with float16 products."""
+    if cfg != -1:
+        return cfg
+    if converted:
+        return 16 if B <= 64 else 10
+    return 12 if B <= 64 else 18
 
 
 def elastic_kernel(cfg: int) -> str:
@@ -439,7 +452,9 @@ def main():
         res = {"ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "dtypes": f"{gdt}/{fdt}",
                "products": "bf16 (high and low activation terms)" if bf16_products else
                ("f16 (bf16 operator words converted exactly in registers)" if "bf16" in (gdt, fdt) else "f16"),
-               "tuning": tuning, "kernel": elastic_kernel(op.get_tuning()["gemm_cfg"]), "kernel_ms": kmean,
+               "tuning": tuning, "kernel": elastic_kernel(op.get_tuning()["gemm_cfg"]),
+               "gemm_cfg": effective_tile(op.get_tuning()["gemm_cfg"], B, gdt == "bf16" and not bf16_products),
+               "kernel_ms": kmean,
                "kernel_ms_min": float(np.min(kern_ms)),
                "algorithmic_flops": flops_g, "achieved_TFLOPs": flops_g / (kmean * 1e9),
                "activation_terms": terms, "issued_TFLOPs": terms * flops_g / (kmean * 1e9), "algorithmic_bytes": hbytes,
@@ -607,7 +622,7 @@ def main():
         roof = {"bound": "mfma", "achieved": half["achieved_TFLOPs"], "peak": MFMA_PEAK[half["dtypes"].split("/")[0]],
                 "unit": "TFLOP/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = traffic_for(half["kernel"])
+        roof["traffic"] = traffic_for(half["kernel"], half["gemm_cfg"])
         workload = (f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, batched {half['dtypes']} "
                     f"B={half['B']} (vs fp32 single rupture)")
     elif fp32:
