@@ -497,6 +497,8 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
   __shared__ uint4 st1[STAGE];
   __shared__ uint4 st2[NS > 2 ? STAGE : 1];
   __shared__ uint4 st3[NS > 3 ? STAGE : 1];
+  __shared__ float sg_s[RT];  // row scales of the tile for the epilogue
+  static_assert(RT <= 64 * NWAVE, "one thread per tile row loads its scale");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
   const int nwg = gridDim.x, w = blockIdx.x;
@@ -541,6 +543,8 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
     g4_issue<PER_W, NWAVE>(src, sstep, 0, nks, st0, wave);
     if (NS > 2) g4_issue<PER_W, NWAVE>(src, sstep, 1, nks, st1, wave);
     if (NS > 3) g4_issue<PER_W, NWAVE>(src, sstep, 2, nks, st2, wave);
+    // the tile's row scales, loaded under the K loop and passed through LDS to the epilogue
+    const float sgv = tid < RT ? sG[(int64_t)min(g0 + tid, ngrid - 1) * M + l] : 0.f;
     // step ks reads stage ks % NS and refills stage (ks - 1) % NS with step ks + NS - 1; every
     // step issues its copies so that the count in flight is the same on every path
 #define S2W_G4_STEP(K, CUR, NEXT)                                      \
@@ -568,28 +572,47 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
       }
     }
 #undef S2W_G4_STEP
+    // epilogue: U[g][l][rup][c] = acc * sG[g][l] * sig_down[l][rup].  Column scales, validity
+    // and offsets are per lane and column block, so each row takes one address computation and
+    // its stores use constant offsets from it; with RE the real and imaginary part of a rupture
+    // sit in one lane and go out as one 8-byte store.
+    float sdn[NF];
+    bool cok[NF];
+    // first output float of this lane's column block 0, relative to the row's start
+    const int rup0 = RE ? 16 * (cbt0 / 2 + wc * (NF / 2)) + (lane & 15) : (16 * (cbt0 + wc * NF) + (lane & 15)) >> 1;
+    const int c0 = RE ? 0 : (lane & 1);
+#pragma unroll
+    for (int b = 0; b < NF; ++b) {
+      const int blk = RE ? cbt0 / 2 + wc * (NF / 2) + (b >> 1) : cbt0 + wc * NF + b;
+      const int rup = RE ? rup0 + 16 * (b >> 1) : rup0 + 8 * b;
+      cok[b] = blk < ncb && rup < B;
+      sdn[b] = cok[b] ? sig_down[(int64_t)l * bp + rup] : 0.f;
+    }
+    float* colp = U + ((int64_t)l * bp + rup0) * 2 + c0;
+    const int64_t row_stride = (int64_t)M * bp * 2;
+    // every wave read sg_s of the previous tile before the barrier at this tile's start
+    if (tid < RT) sg_s[tid] = sgv;
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the scale is in LDS
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int a = 0; a < MF; ++a)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int g = g0 + wr * MW + 16 * a + 4 * (lane >> 4) + r;
+        const int gt = wr * MW + 16 * a + 4 * (lane >> 4) + r;  // row within the tile
+        const int g = g0 + gt;
         if (g >= ngrid) continue;
-        const float sg = sG[(int64_t)g * M + l];
+        const float sg = sg_s[gt];
+        float* p = colp + (int64_t)g * row_stride;
 #pragma unroll
         for (int b = 0; b < NF; ++b) {
           if (RE) {
-            const int rcb = cbt0 / 2 + wc * (NF / 2) + (b >> 1);
-            const int rup = 16 * rcb + (lane & 15);
-            if (rcb < ncb && rup < B)
-              U[(((int64_t)g * M + l) * bp + rup) * 2 + (b & 1)] =
-                  acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+            if ((b & 1) == 0 && cok[b])
+              *reinterpret_cast<float2*>(p + 32 * (b >> 1)) =
+                  make_float2(acc[a][b][r] * sg * sdn[b], acc[a][b + 1][r] * sg * sdn[b]);
           } else {
-            const int cb = cbt0 + wc * NF + b;
-            const int n = 16 * cb + (lane & 15);
-            const int rup = n >> 1;
-            if (cb < ncb && rup < B)
-              U[(((int64_t)g * M + l) * bp + rup) * 2 + (n & 1)] =
-                  acc[a][b][r] * sg * sig_down[(int64_t)l * bp + rup];
+            if (cok[b]) p[16 * b] = acc[a][b][r] * sg * sdn[b];
           }
         }
       }
