@@ -68,6 +68,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
   constexpr int NBS = RE ? NCB / 2 : NCB;  // fragment blocks held in LDS per step
   __shared__ uint32_t la_s[2][16 * LDA];
   __shared__ uint4 lb_s[2][NBS * H * 64];
+  __shared__ float rs_s[RT];  // row scales of the tile for the epilogue
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
   const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
@@ -81,6 +82,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
   const uint32_t cmask = dc ? 0u : 0x80000000u;
   const int ks0 = (int)((int64_t)p.nks * split / p.splits), ks1 = (int)((int64_t)p.nks * (split + 1) / p.splits);
   const int row0 = rt * RT;
+  if (tid < RT)
+    rs_s[tid] = p.rowscale ? p.rowscale[(int64_t)min(row0 + tid, p.nrows - 1) * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
+  __syncthreads();
   const uint32_t* Al = p.Aq + (int64_t)l * p.a_slot;
   const float2* Xl = p.X + (int64_t)l * p.x_slot;
   // activation ownership: granule slot s = tid + 512 * rep -> column block s / 64, lane s % 64
@@ -192,33 +196,36 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NF <= 4 ? 4
     }
   }
   float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
+  // per column block of this lane: rupture, validity and down scale, hoisted out of the rows;
+  // each row takes one address computation and its stores use constant offsets
+  constexpr int NC = RE ? NF / 2 : NF;
+  const int b0 = RE ? ct * RB + 16 * ((NF / 2) * wc) + (lane & 15) : (2 * ct * RB + 16 * NF * wc + (lane & 15)) >> 1;
+  float dn[NC];
+  bool ok[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const int b = RE ? b0 + 16 * c : b0 + 8 * c;
+    ok[c] = b < p.B;
+    dn[c] = (ok[c] && p.down) ? p.down[(int64_t)l * p.bp + b] : 1.f;
+  }
+  float* colp = ow + 2 * b0 + (RE ? 0 : (lane & 1));
 #pragma unroll
   for (int a = 0; a < MF; ++a)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 16 * (MF * wr + a) + 4 * (lane >> 4) + r;
+      const int rt_row = 16 * (MF * wr + a) + 4 * (lane >> 4) + r;  // row within the tile
+      const int row = row0 + rt_row;
       if (row < p.nrows) {
-        const float rs = p.rowscale ? p.rowscale[(int64_t)row * p.rs_row + (int64_t)l * p.rs_l] : 1.f;
-        if (RE) {
+        const float rs = rs_s[rt_row];
+        float* pr = colp + (int64_t)row * p.o_row;
 #pragma unroll
-          for (int fr = 0; fr < NF / 2; ++fr) {
-            const int b = ct * RB + 16 * ((NF / 2) * wc + fr) + (lane & 15);
-            if (b < p.B) {
-              const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
-              *reinterpret_cast<float2*>(&ow[(int64_t)row * p.o_row + 2 * b]) =
-                  make_float2(acc[a][2 * fr][r] * rs * dn, acc[a][2 * fr + 1][r] * rs * dn);
-            }
-          }
-        } else {
-#pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            const int n = 2 * ct * RB + 16 * (NF * wc + f) + (lane & 15);
-            const int b = n >> 1;
-            if (b < p.B) {
-              const float dn = p.down ? p.down[(int64_t)l * p.bp + b] : 1.f;
-              ow[(int64_t)row * p.o_row + n] = acc[a][f][r] * rs * dn;
-            }
-          }
+        for (int c = 0; c < NC; ++c) {
+          if (!ok[c]) continue;
+          if (RE)
+            *reinterpret_cast<float2*>(pr + 32 * c) =
+                make_float2(acc[a][2 * c][r] * rs * dn[c], acc[a][2 * c + 1][r] * rs * dn[c]);
+          else
+            pr[16 * c] = acc[a][c][r] * rs * dn[c];
         }
       }
     }
