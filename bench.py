@@ -92,7 +92,7 @@ def effective_tile(cfg: int, B: int, converted: bool) -> int:
     if cfg != -1:
         return cfg
     if converted:
-        return 16 if B <= 64 else 10
+        return 16 if B <= 64 else 24
     return 12 if B <= 64 else 18
 
 

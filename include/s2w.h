@@ -213,13 +213,14 @@ typedef struct s2w_tuning {
   int32_t batch_path_min_b;  /* reserved: ignored (the layout, fixed at plan creation, picks the path) */
   int32_t gemm_cfg;          /* batched elastic GEMM tile, 256 grid rows tall, persistent workgroups:
                                 -1 automatic (12 for B <= 64, else 18; with float16 products on
-                                bfloat16 words 16 and 10); 4 = 16 columns (four waves,
+                                bfloat16 words 16 and 24); 4 = 16 columns (four waves,
                                 register operands); 10 = 256 columns (eight waves, three-stage LDS copy
                                 pipeline); 12 = 128 columns (eight waves, four stages); 16 = 128 columns
                                 (four waves, two stages, two workgroups per compute unit); 17, 18 = 256
                                 columns on real-column activation fragments (eight waves, four and three
-                                stages).  A rupture takes two columns (real and imaginary part).  All
-                                tiles give the same results bit for bit. */
+                                stages); 24 = 256 columns (eight waves of 64 x 128, three stages).
+                                A rupture takes two columns (real and imaginary part).  All tiles
+                                give the same results bit for bit. */
   int32_t fgemm_splits;      /* batched acoustic GEMM: grid-row splits (1..16) */
   int32_t fgemm_lds;         /* batched acoustic GEMM: 1 automatic (LDS-staged kernel for bfloat16 products
                                 with B <= 64 where its tile fits, else the eight-wave kernel on

@@ -38,7 +38,7 @@ def candidates(op, adjoint: bool = False) -> list[dict]:
             return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
         return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]
     if op.g_dtype != "f32":
-        return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 10, 12, 16, 17, 18) for f in (3, 4, 2)]
+        return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 10, 12, 16, 17, 18, 24) for f in (3, 4, 2)]
     if op.plan_layout() == "batched":
         return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
     return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]

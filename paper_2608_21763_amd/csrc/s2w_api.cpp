@@ -524,8 +524,8 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
   }
   if (t->gemm_cfg) {
     const int c = t->gemm_cfg;
-    if (!(c == -1 || c == 4 || c == 10 || c == 12 || (c >= 16 && c <= 18)))
-      return fail(p, S2W_EINVAL, "tuning: gemm_cfg must be -1, 4, 10, 12, 16, 17 or 18");
+    if (!(c == -1 || c == 4 || c == 10 || c == 12 || (c >= 16 && c <= 18) || c == 24))
+      return fail(p, S2W_EINVAL, "tuning: gemm_cfg must be -1, 4, 10, 12, 16, 17, 18 or 24");
     n.gemm_cfg = t->gemm_cfg == 4 ? 0 : t->gemm_cfg;
   }
   if (t->fgemm_lds) {
@@ -744,7 +744,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   int cfg = p->tune.gemm_cfg;
   // default tiles from sweeps on the Cascadia-sized share: with converted bfloat16 words the
   // real-column tiles lose their edge (the conversions already load the vector ALUs)
-  if (cfg < 0) cfg = h.kt_g == 3 ? (B <= 64 ? 16 : 10) : (B <= 64 ? 12 : 18);
+  if (cfg < 0) cfg = h.kt_g == 3 ? (B <= 64 ? 16 : 24) : (B <= 64 ? 12 : 18);
   // acoustic GEMM: fgemm_lds 2 takes the eight-wave kernel on full activation fragments, 3 the
   // eight-wave kernel on real-column fragments (with either the mid-chain leaves complex64),
   // 4 the LDS-staged kernel for packed bfloat16 activations where its tile fits (else, and for
@@ -933,8 +933,8 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
   // W[g][l][b] = sF[g][l] * sum_o conj(Fq[l][o][g]) R[l][o][b]
   // default tiles (sweep on the Cascadia-sized share): eight waves on real-column activation
-  // fragments, 256 rows x 128 columns, and 256 x 64 for batches of at most 32
-  const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 5 : 6);
+  // fragments, 256 rows x 256 columns above B = 128, 256 x 128 down to B = 33, 256 x 64 below
+  const int shape1 = p->tune.hadj_tile_f >= 0 ? p->tune.hadj_tile_f : (B <= 32 ? 5 : (B > 128 ? 7 : 6));
   e = launch_gemm_t(h.kt_f, h.hterms_f, shape1, Fq, (int64_t)h.noq * h.ngq, 16 * (int64_t)h.ngq, h.ngq, 16, g.ngrid,
                     h.ngq, g.nobs, h.noq, R,
                     (int64_t)g.nobs * bp, bp, g.nobs, sf16 ? sig_up : nullptr, sf16 ? sig_down : nullptr, sF, g.M, 1,

@@ -648,6 +648,15 @@ static hipError_t gemm_g_h(int cfg, const uint4* Gq, const float* sG, const uint
                            sig_down, U, ngrid, M, nks, nrcb, B, bp, nrb, nct);
       break;
     }
+    case 24: {
+      // 256 x 256 tiles with wave tiles of 64 rows x 128 columns (waves 4 x 2): half the
+      // operator fragments per wave of tile 10, so half the conversions of bfloat16 words
+      const int nrb = (ngrid + 255) / 256;
+      const int nct = (ncb + 15) / 16;
+      hipLaunchKernelGGL((k_gemm_g4<HT, H, 64, 128, 3, 4, 2>), dim3(nwg), dim3(512), 0, st, Gq, sG, Bop, sig_down, U,
+                         ngrid, M, nks, ncb, B, bp, nrb, nct);
+      break;
+    }
     case 10:
     case 12: {
       // direct-to-LDS copies, eight waves: 10 = 256 x 256 (three stages), 12 = 256 x 128 (four stages)

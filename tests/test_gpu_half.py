@@ -216,10 +216,10 @@ def test_elastic_gemm_tile_shapes_agree(B, dtype):
     op = make_operator(cfg, max_batch=B, **store(dtype))
     s = to_dev(synth.gen_slip_batch(cfg, 0, B))
     outs = {}
-    for c in (4, 10, 12, 16, 17, 18):
+    for c in (4, 10, 12, 16, 17, 18, 24):
         op.set_tuning(gemm_cfg=c)
         outs[c] = op.forward(s).clone()
-    for bad in (1, 2, 3, 5, 11, 19, 20):
+    for bad in (1, 2, 3, 5, 11, 19, 20, 25):
         with pytest.raises(S2WError):
             op.set_tuning(gemm_cfg=bad)
     for c in outs:
