@@ -310,18 +310,26 @@ __device__ __forceinline__ void dft16(float2 (&v)[16]) {
 
 // Pass A of a 256-point transform for column n2 = c: v[n1] = x[16 n1 + c] in, out
 // v[k1] = W256^{DIR c k1} * sum_{n1} x[16 n1 + c] W16^{DIR n1 k1}.
+// The twiddles W256^{-c k1}, k1 = 1..15, are the thread's own (twA, in registers).
 template <int DIR>
-__device__ __forceinline__ void fft256_passA(float2 (&v)[16], int c, const float2* twc) {
+__device__ __forceinline__ void fft256_passA(float2 (&v)[16], const float2 (&twA)[15]) {
   dft16<DIR>(v);
 #pragma unroll
   for (int k1 = 1; k1 < 16; ++k1) {
-    float2 w = twc[c * k1];
+    float2 w = twA[k1 - 1];
     if (DIR > 0) w.y = -w.y;
     v[k1] = cmul(v[k1], w);
   }
 }
 
-// Mid-chain round trip for R rows with M = 256, 16 threads per row: thread tid handles row
+// Pass-A twiddles of column c: twc[c * k1] for k1 = 1..15 (forward sign).
+__device__ __forceinline__ void passA_twiddles(const float2* twc, int c, float2 (&twA)[15]) {
+#pragma unroll
+  for (int k1 = 1; k1 < 16; ++k1) twA[k1 - 1] = twc[c * k1];
+}
+
+// Mid-chain round trip for R rows with M = 256, 16 threads per row (twA: passA_twiddles of
+// column tid % 16): thread tid handles row
 // r = tid / 16 and column c = tid % 16.  X (row stride ldx >= 256) holds the packed input
 // spectra and is overwritten; T (LDS, at least R*16*17 values) receives the packed output
 // spectra with row stride ldt (256 <= ldt <= 272).
@@ -330,8 +338,8 @@ __device__ __forceinline__ void fft256_passA(float2 (&v)[16], int c, const float
 // MidMode, fixed at compile time so that the time step has no branches.
 template <int MODE>
 __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, float scale, const Twiddles& tw,
-                                       int ldx = 256, int ldt = 256, const DispRows* disp = nullptr,
-                                       const short* dtab = nullptr) {
+                                       const float2 (&twA)[15], int ldx = 256, int ldt = 256,
+                                       const DispRows* disp = nullptr, const short* dtab = nullptr) {
   constexpr int M = 256;
   const int tid = threadIdx.x;
   const int r = tid >> 4, c = tid & 15;
@@ -343,7 +351,7 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, floa
   if (act) {
 #pragma unroll
     for (int n1 = 0; n1 < 16; ++n1) v[n1] = irfft_pre(Xr, 16 * n1 + c, M, tw.r);
-    fft256_passA<+1>(v, c, tw.c);
+    fft256_passA<+1>(v, twA);
 #pragma unroll
     for (int k1 = 0; k1 < 16; ++k1) Tr[k1 * 17 + c] = v[k1];
   }
@@ -383,7 +391,7 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, floa
       }
       v[n1] = make_float2(a * scale, b * scale);
     }
-    fft256_passA<-1>(v, c, tw.c);
+    fft256_passA<-1>(v, twA);
   }
   __syncthreads();  // all reads of X done before pass B below overwrites it
   if (act) {
