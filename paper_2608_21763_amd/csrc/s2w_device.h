@@ -335,7 +335,10 @@ __device__ __forceinline__ void passA_twiddles(const float2* twc, int c, float2 
 // spectra with row stride ldt (256 <= ldt <= 272).
 // Same arithmetic as lds_midchain2 (inverse real FFT, truncate to nt, D_t, zero-pad, forward
 // real FFT), with the complex transforms done as two 16-point passes in registers.  MODE is the
-// MidMode, fixed at compile time so that the time step has no branches.
+// MidMode, fixed at compile time so that the time step has no branches.  M = 256 means
+// nt <= 256, so the packed series z[n] = x[2n] + i x[2n+1] is kept only for n < 128: the inverse
+// transform's pass B writes only those outputs, and the forward transform's pass A takes zeros
+// for n >= 128 (products with them are not formed).
 template <int MODE>
 __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, float scale, const Twiddles& tw,
                                        const float2 (&twA)[15], int ldx = 256, int ldt = 256,
@@ -361,13 +364,17 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, floa
     for (int n2 = 0; n2 < 16; ++n2) v[n2] = Tr[c * 17 + n2];
     dft16<+1>(v);
 #pragma unroll
-    for (int k2 = 0; k2 < 16; ++k2) Xr[c + 16 * k2] = v[k2];  // z[n] = L (x[2n] + i x[2n+1])
+    for (int k2 = 0; k2 < 8; ++k2) Xr[c + 16 * k2] = v[k2];  // z[n] = L (x[2n] + i x[2n+1]), n < 128
   }
   __syncthreads();
   // time step (truncate, D_t, scale) fused into pass A of the forward FFT
   if (act) {
 #pragma unroll
     for (int n1 = 0; n1 < 16; ++n1) {
+      if (n1 >= 8) {  // n >= 128: samples 2n >= 256 >= nt are truncated
+        v[n1] = make_float2(0.f, 0.f);
+        continue;
+      }
       const int n = 16 * n1 + c;
       const float2 z = Xr[n];
       const int m0 = 2 * n, m1 = m0 + 1;

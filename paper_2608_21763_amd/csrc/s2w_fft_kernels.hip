@@ -673,7 +673,7 @@ hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjo
       nb256 = groups * nbb;
       if (cmax_groups) *cmax_groups = (int)groups;
     }
-    if (B < 1 || units256 > 0x7fffffff) return hipErrorInvalidValue;
+    if (B < 1 || g.nt > 256 || units256 > 0x7fffffff) return hipErrorInvalidValue;  // M = 256 implies nt <= 256
 #define S2W_MID256K(P_, R_, D_, M_)                                                                              \
   hipLaunchKernelGGL((k_mid_batch256<P_, R_, D_, M_>), dim3((unsigned)nb256), dim3(16 * R_), 0, st, U, sF, g.ngrid, B, \
                      bp, g.nt, mscale, cmax, dd)
