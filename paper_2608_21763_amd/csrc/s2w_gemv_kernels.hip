@@ -104,6 +104,60 @@ __global__ __launch_bounds__(256) void k_bltt_gemv_lds(const float4* __restrict_
   }
 }
 
+// As k_bltt_gemv_lds for rows of at most 512 float4 (ncol <= 1024): the row's loads
+// (8 x 64 x 16 bytes) are issued together, and the next row's go out before the current row is
+// reduced, so that a wavefront always has a row in flight.
+template <int NB>
+__global__ __launch_bounds__(256) void k_bltt_gemv_row(const float4* __restrict__ K, const float4* __restrict__ X,
+                                                       float2* __restrict__ yh, int nrow, int M, int nc4, int B,
+                                                       int nsplit) {
+  constexpr int NI = 8;           // float4 per lane and row: nc4 <= 512
+  extern __shared__ float4 xs[];  // [b][i], b < B, i < nc4
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l = blockIdx.x % M, split = blockIdx.x / M;
+  const bool dc = (l == 0);
+  for (int j = threadIdx.x; j < B * nc4; j += 256) {
+    const int b = j / nc4, i = j - b * nc4;
+    xs[j] = X[((int64_t)b * M + l) * nc4 + i];
+  }
+  __syncthreads();
+  const int r0 = (int)((int64_t)nrow * split / nsplit), r1 = (int)((int64_t)nrow * (split + 1) / nsplit);
+  auto load_row = [&](int r, float4 (&kv)[NI]) {
+    const float4* a = K + ((int64_t)r * M + l) * nc4;
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int i = lane + 64 * t;
+      if (i < nc4) {
+        const gv_f4 v = __builtin_nontemporal_load(reinterpret_cast<const gv_f4*>(a + i));  // streamed once
+        kv[t] = make_float4(v.x, v.y, v.z, v.w);
+      } else {
+        kv[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  };
+  float4 cur[NI], nxt[NI];
+  int r = r0 + wave;
+  if (r < r1) load_row(r, cur);
+  for (; r < r1; r += 4) {
+    if (r + 4 < r1) load_row(r + 4, nxt);
+    float re[NB], im[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) re[b] = im[b] = 0.f;
+#pragma unroll
+    for (int t = 0; t < NI; ++t) {
+      const int i = lane + 64 * t;
+      if (i < nc4) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (b < B) gv_mac(cur[t], xs[b * nc4 + i], dc, re[b], im[b]);
+      }
+    }
+    gv_store<NB>(re, im, lane, B, yh, nrow, r, M, l);
+#pragma unroll
+    for (int t = 0; t < NI; ++t) cur[t] = nxt[t];
+  }
+}
+
 hipError_t launch_bltt_gemv(const float2* K, const float2* X, float2* yh, int nrow, int M, int ncp, int B, int ncu,
                             hipStream_t st) {
   if (B < 1 || B > 4 || (ncp & 1) || nrow < 1 || M < 1) return hipErrorInvalidValue;
@@ -115,8 +169,12 @@ hipError_t launch_bltt_gemv(const float2* K, const float2* X, float2* yh, int nr
     // inputs of a slot in LDS; enough row ranges per slot for about 16 workgroups per CU
     const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ncu * 16 / M, (nrow + 3) / 4));
     const dim3 grid((unsigned)((int64_t)M * nsplit));
-#define S2W_GV2(NB_) hipLaunchKernelGGL((k_bltt_gemv_lds<NB_>), grid, dim3(256), lds, st, k4, x4, yh, nrow, M, nc4, B, nsplit)
-    if (B == 1) S2W_GV2(1); else if (B == 2) S2W_GV2(2); else S2W_GV2(4);
+#define S2W_GV2(K_, NB_) hipLaunchKernelGGL((K_<NB_>), grid, dim3(256), lds, st, k4, x4, yh, nrow, M, nc4, B, nsplit)
+    if (nc4 <= 512) {  // rows of at most 8 float4 per lane: whole rows in flight
+      if (B == 1) S2W_GV2(k_bltt_gemv_row, 1); else if (B == 2) S2W_GV2(k_bltt_gemv_row, 2); else S2W_GV2(k_bltt_gemv_row, 4);
+    } else {
+      if (B == 1) S2W_GV2(k_bltt_gemv_lds, 1); else if (B == 2) S2W_GV2(k_bltt_gemv_lds, 2); else S2W_GV2(k_bltt_gemv_lds, 4);
+    }
 #undef S2W_GV2
     return hipGetLastError();
   }
