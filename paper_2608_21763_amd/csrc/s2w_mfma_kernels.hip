@@ -88,21 +88,32 @@ hipError_t launch_quant_rows(int ht, const float2* staging, int64_t nrows, int M
 // ---------------------------------------------------------------------------------------------
 // Activation scales: sig[l][b] = power of two mapping max_j |S[l][j][b]| (re, im) into
 // [2^14, 2^15) (the inverse is applied to the GEMM result).  S is [l][nsq][bp] complex.
+// Workgroup of 16 columns (l, b..b+15) x 16 row groups: thread (jg, c) takes rows j = jg, jg +
+// 16, ... of column c (consecutive threads read consecutive columns), then the 16 partial maxima
+// of a column are combined in LDS.  Columns b >= B get unit scales.
 __global__ __launch_bounds__(256) void k_act_scale(const float2* __restrict__ S, int M, int nsub, int nsq, int B,
                                                    int bp, float* __restrict__ sig_up, float* __restrict__ sig_down) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)M * bp) return;
-  const int l = (int)(i / bp), b = (int)(i - (int64_t)l * bp);
+  __shared__ float part[16][17];
+  const int c = threadIdx.x & 15, jg = threadIdx.x >> 4;
+  const int64_t col = (int64_t)blockIdx.x * 16 + c;  // l * bp + b
+  const bool inb = col < (int64_t)M * bp;
+  const int l = inb ? (int)(col / bp) : 0, b = inb ? (int)(col - (int64_t)l * bp) : 0;
   float mx = 0.f;
-  if (b < B)
-    for (int j = 0; j < nsub; ++j) {
+  if (inb && b < B)
+    for (int j = jg; j < nsub; j += 16) {
       const float2 v = S[((int64_t)l * nsq + j) * bp + b];
       mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
-  float up, down;
-  pow2_scale(mx, up, down);
-  sig_up[i] = up;
-  sig_down[i] = down;
+  part[jg][c] = mx;
+  __syncthreads();
+  if (jg == 0 && inb) {
+#pragma unroll
+    for (int k = 1; k < 16; ++k) mx = fmaxf(mx, part[k][c]);
+    float up, down;
+    pow2_scale(mx, up, down);
+    sig_up[col] = up;
+    sig_down[col] = down;
+  }
 }
 
 // B operand of the elastic GEMM in fragment order: Bop[l][ks][cb][h][lane] (16 bytes each).
@@ -173,7 +184,7 @@ hipError_t launch_prep_act(int ht, int hterms, const float2* S, float* sig_up, f
   if (ht == 1)
     hipLaunchKernelGGL(k_unit_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns, sig_up, sig_down);
   else
-    hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp,
+    hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 15) / 16)), dim3(256), 0, st, S, M, nsub, nsq, B, bp,
                        sig_up, sig_down);
   const int64_t total = (int64_t)M * nks * ncb * 64;
   dim3 grid((unsigned)((total + 255) / 256));
@@ -237,7 +248,7 @@ hipError_t launch_prep_act_re(int ht, int hterms, const float2* S, float* sig_up
   if (ht == 1)
     hipLaunchKernelGGL(k_unit_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, ns, sig_up, sig_down);
   else
-    hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nsub, nsq, B, bp,
+    hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 15) / 16)), dim3(256), 0, st, S, M, nsub, nsq, B, bp,
                        sig_up, sig_down);
   const int64_t total = (int64_t)M * nks * nrcb * 64;
   dim3 grid((unsigned)((total + 255) / 256));
@@ -859,7 +870,7 @@ hipError_t launch_gemm_f2(const uint4* Fq, const uint2* V, float* part, int ngri
 hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int bp, float* sig_up, float* sig_down,
                             hipStream_t st) {
   const int64_t ns = (int64_t)M * bp;
-  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, S, M, nk, nkp, B, bp, sig_up,
+  hipLaunchKernelGGL(k_act_scale, dim3((unsigned)((ns + 15) / 16)), dim3(256), 0, st, S, M, nk, nkp, B, bp, sig_up,
                      sig_down);
   return hipGetLastError();
 }
