@@ -814,7 +814,7 @@ static int b32_cfg(const s2w_plan* p, int B, bool few_rows) {
     return B <= 8 ? 2 : (B <= 64 ? 3 : 0);
   }
   if (p->tune.gemm32_cfg >= 0) return p->tune.gemm32_cfg;
-  return B <= 64 ? 2 : 1;
+  return B <= 8 ? 2 : 1;
 }
 
 static int b32_splits(int tuned, int maxs, int M, int nrows, int B, int cfg) {
