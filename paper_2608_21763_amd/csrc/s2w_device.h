@@ -118,7 +118,8 @@ __device__ __forceinline__ float2* lds_cfft(float2* a, float2* b, int R, int M, 
 
 // Pre-step of the inverse real FFT: packed spectrum X (M slots, real length L = 2M)
 // -> Z with z = IFFT_M(Z) giving L*x[2n] + i L*x[2n+1].  tr = Twiddles::r.
-__device__ __forceinline__ float2 irfft_pre(const float2* X, int k, int M, const float2* tr) {
+// w: the twiddle tr[k] (unused for k = 0)
+__device__ __forceinline__ float2 irfft_pre_w(const float2* X, int k, int M, float2 w) {
   if (k == 0) {
     const float2 x0 = X[0];
     return make_float2(x0.x + x0.y, x0.x - x0.y);
@@ -126,12 +127,16 @@ __device__ __forceinline__ float2 irfft_pre(const float2* X, int k, int M, const
   const float2 xk = X[k];
   const float2 xc = cconj(X[M - k]);
   const float2 e = cadd(xk, xc);
-  const float2 o = cmul(csub(xk, xc), cconj(tr[k]));
+  const float2 o = cmul(csub(xk, xc), cconj(w));
   return make_float2(e.x - o.y, e.y + o.x);  // e + i o
+}
+__device__ __forceinline__ float2 irfft_pre(const float2* X, int k, int M, const float2* tr) {
+  if (k == 0) return irfft_pre_w(X, 0, M, make_float2(1.f, 0.f));
+  return irfft_pre_w(X, k, M, tr[k]);
 }
 
 // Post-step of the forward real FFT: Z = FFT_M(x[2n] + i x[2n+1]) -> packed slot k.
-__device__ __forceinline__ float2 rfft_post(const float2* Z, int k, int M, const float2* tr) {
+__device__ __forceinline__ float2 rfft_post_w(const float2* Z, int k, int M, float2 w) {
   if (k == 0) {
     const float2 z0 = Z[0];
     return make_float2(z0.x + z0.y, z0.x - z0.y);
@@ -141,7 +146,11 @@ __device__ __forceinline__ float2 rfft_post(const float2* Z, int k, int M, const
   const float2 e = cscale(cadd(zk, zc), 0.5f);
   const float2 d = csub(zk, zc);
   const float2 o = make_float2(0.5f * d.y, -0.5f * d.x);  // d / (2i)
-  return cadd(e, cmul(tr[k], o));
+  return cadd(e, cmul(w, o));
+}
+__device__ __forceinline__ float2 rfft_post(const float2* Z, int k, int M, const float2* tr) {
+  if (k == 0) return rfft_post_w(Z, 0, M, make_float2(1.f, 0.f));
+  return rfft_post_w(Z, k, M, tr[k]);
 }
 
 // Real time sample m (0 <= m < L) from the inverse-FFT output z (pairs).
@@ -328,6 +337,12 @@ __device__ __forceinline__ void passA_twiddles(const float2* twc, int c, float2 
   for (int k1 = 1; k1 < 16; ++k1) twA[k1 - 1] = twc[c * k1];
 }
 
+// Real-transform twiddles of column c: twr[c + 16 j], j = 0..15.
+__device__ __forceinline__ void real_twiddles(const float2* twr, int c, float2 (&twR)[16]) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) twR[j] = twr[c + 16 * j];
+}
+
 // Mid-chain round trip for R rows with M = 256, 16 threads per row (twA: passA_twiddles of
 // column tid % 16): thread tid handles row
 // r = tid / 16 and column c = tid % 16.  X (row stride ldx >= 256) holds the packed input
@@ -341,8 +356,8 @@ __device__ __forceinline__ void passA_twiddles(const float2* twc, int c, float2 
 // for n >= 128 (products with them are not formed).
 template <int MODE>
 __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, float scale, const Twiddles& tw,
-                                       const float2 (&twA)[15], int ldx = 256, int ldt = 256,
-                                       const DispRows* disp = nullptr, const short* dtab = nullptr) {
+                                       const float2 (&twA)[15], const float2 (&twR)[16], int ldx = 256,
+                                       int ldt = 256, const DispRows* disp = nullptr, const short* dtab = nullptr) {
   constexpr int M = 256;
   const int tid = threadIdx.x;
   const int r = tid >> 4, c = tid & 15;
@@ -353,7 +368,7 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, floa
   // inverse real FFT: pre-step fused into pass A (element 16 n1 + c)
   if (act) {
 #pragma unroll
-    for (int n1 = 0; n1 < 16; ++n1) v[n1] = irfft_pre(Xr, 16 * n1 + c, M, tw.r);
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = irfft_pre_w(Xr, 16 * n1 + c, M, twR[n1]);
     fft256_passA<+1>(v, twA);
 #pragma unroll
     for (int k1 = 0; k1 < 16; ++k1) Tr[k1 * 17 + c] = v[k1];
@@ -419,7 +434,7 @@ __device__ __forceinline__ void mid256(float2* X, float2* T, int R, int nt, floa
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int k = c + 16 * j;
-      T[r * ldt + k] = rfft_post(Xr, k, M, tw.r);
+      T[r * ldt + k] = rfft_post_w(Xr, k, M, twR[j]);
     }
   }
   __syncthreads();

@@ -587,8 +587,9 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
   const Twiddles tw = lds_twiddles(twb, M);
   const int tid = threadIdx.x;
   const int r = tid % R, lq = tid / R;  // gather/scatter: rupture r, slots lq + 16 k
-  float2 twA[15];
+  float2 twA[15], twR[16];
   passA_twiddles(tw.c, tid & 15, twA);
+  real_twiddles(tw.r, tid & 15, twR);
   const int nbb = (B + R - 1) / R;
   const int units = ngrid * nbb;  // the launcher checks that this fits an int
   float2 pre[16];
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
     const int b0 = (u % nbb) * R;
     const DispRows dr{disp.base + (int64_t)g * disp.grid_stride + (int64_t)b0 * disp.row_stride, disp.row_stride,
                       B - b0, disp.scale};
-    mid256<MODE>(X, T, R, nt, mscale, tw, twA, LD, LD, DISP ? &dr : nullptr, dtab);
+    mid256<MODE>(X, T, R, nt, mscale, tw, twA, twR, LD, LD, DISP ? &dr : nullptr, dtab);
     float2* dst = U + (int64_t)g * M * bp + b;
     if (b < B) {
 #pragma unroll
