@@ -160,37 +160,50 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const CGemmArgs p) {
 #pragma unroll
     for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  if (c0 < c1) {
-    float4 st[PER_T];
-    load(c0, st);
-    put(0, st);
-    __syncthreads();
-    for (int c = c0; c < c1; ++c) {
-      const int cur = (c - c0) & 1;
-      const bool more = c + 1 < c1;
-      if (more) load(c + 1, st);
-      const float4* la = &lds[cur][0];
-      const float2* lx = reinterpret_cast<const float2*>(&lds[cur][A_F4]);
-      float4 av[MF];
+  // products of chunk c from LDS buffer cur
+  auto compute = [&](int cur) {
+    const float4* la = &lds[cur][0];
+    const float2* lx = reinterpret_cast<const float2*>(&lds[cur][A_F4]);
+    float4 av[MF];
 #pragma unroll
-      for (int a = 0; a < MF; ++a) av[a] = la[swz32(wr * MF * 16 + 16 * a + (lane & 15), kq)];
+    for (int a = 0; a < MF; ++a) av[a] = la[swz32(wr * MF * 16 + 16 * a + (lane & 15), kq)];
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const int rl = wc * NF * 8 + f * 8 + ((lane & 15) >> 1);
-        const float2 x0 = lx[(2 * kq) * LDX + rl];
-        const float2 x1 = lx[(2 * kq + 1) * LDX + rl];
-        float bv[4];
-        embed32<CONJ>(x0, ci, dc, bv[0], bv[1]);
-        embed32<CONJ>(x1, ci, dc, bv[2], bv[3]);
+    for (int f = 0; f < NF; ++f) {
+      const int rl = wc * NF * 8 + f * 8 + ((lane & 15) >> 1);
+      const float2 x0 = lx[(2 * kq) * LDX + rl];
+      const float2 x1 = lx[(2 * kq + 1) * LDX + rl];
+      float bv[4];
+      embed32<CONJ>(x0, ci, dc, bv[0], bv[1]);
+      embed32<CONJ>(x1, ci, dc, bv[2], bv[3]);
 #pragma unroll
-        for (int a = 0; a < MF; ++a) {
-          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[0], acc[a][f], 0, 0, 0);
-          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[1], acc[a][f], 0, 0, 0);
-          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z, bv[2], acc[a][f], 0, 0, 0);
-          acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].w, bv[3], acc[a][f], 0, 0, 0);
-        }
+      for (int a = 0; a < MF; ++a) {
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[0], acc[a][f], 0, 0, 0);
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[1], acc[a][f], 0, 0, 0);
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z, bv[2], acc[a][f], 0, 0, 0);
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].w, bv[3], acc[a][f], 0, 0, 0);
       }
-      if (more) put(cur ^ 1, st);
+    }
+  };
+  // two chunks in flight: chunk c + 2 is loaded into registers while chunk c is consumed from
+  // LDS and chunk c + 1 (loaded one step earlier) waits to be stored to the other buffer; the
+  // two register sets alternate, so the loop body is written for a pair of chunks
+  if (c0 < c1) {
+    float4 sa[PER_T], sb[PER_T];
+    load(c0, sa);
+    if (c0 + 1 < c1) load(c0 + 1, sb);
+    put(0, sa);
+    __syncthreads();
+    for (int c = c0; c < c1; c += 2) {
+      // chunk c (buffer 0) ready; sb holds chunk c + 1
+      if (c + 2 < c1) load(c + 2, sa);
+      compute(0);
+      if (c + 1 < c1) put(1, sb);
+      __syncthreads();
+      if (c + 1 >= c1) break;
+      // chunk c + 1 (buffer 1) ready; sa holds chunk c + 2
+      if (c + 3 < c1) load(c + 3, sb);
+      compute(1);
+      if (c + 2 < c1) put(0, sa);
       __syncthreads();
     }
   }
@@ -209,9 +222,191 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32(const CGemmArgs p) {
     }
 }
 
+// Copies of chunk c of the float32 forward products into one LDS stage (see k_cgemm32d).
+template <int NRT>
+__device__ __forceinline__ int c32d_xsw(int kk) {
+  return NRT >= 32 ? ((kk >> 1) & 3) * 4 : 0;
+}
+
+template <int NRT, int A_PER_W, int X_PER_W, int X_LANES>
+__device__ __forceinline__ void c32d_issue(const float2* const (&asrc)[A_PER_W], const float2* Xl,
+                                           const CGemmArgs& p, int b0, int c, float4* a_dst, float4* x_dst,
+                                           int wave, int lane) {
+#pragma unroll
+  for (int qq = 0; qq < A_PER_W; ++qq)
+    __builtin_amdgcn_global_load_lds(asrc[qq] + 8 * c, (__attribute__((address_space(3))) void*)(a_dst + 256 * qq),
+                                     16, 0, 0);
+  // all 64 lanes copy (no branch: a divergent copy makes the compiler drain every copy in
+  // flight at the loop head); lane j >= X_LANES writes the unit that belongs at its position,
+  // the same bytes as the wave that owns it, or past the block into padding
+#pragma unroll
+  for (int t = 0; t < X_PER_W; ++t) {
+    const int u = min((wave * X_PER_W + t) * X_LANES + lane, 4 * NRT - 1);
+    const int kk = u / (NRT / 2), pq = (u % (NRT / 2)) ^ c32d_xsw<NRT>(kk);
+    const int k = min(8 * c + kk, p.xk_alloc - 1);
+    const int b = min(b0 + 2 * pq, p.bp - 2);
+    float4* dst = x_dst + (wave * X_PER_W + t) * X_LANES;
+    __builtin_amdgcn_global_load_lds(Xl + (int64_t)k * p.x_k + b, (__attribute__((address_space(3))) void*)dst, 16, 0,
+                                     0);
+  }
+}
+
+// The same products for k-contiguous operators without conjugation (the forward products)
+// with the tiles copied straight from global memory into LDS (global_load_lds_dwordx4, no
+// register staging) in NS stages: register-staged copies cap a streaming kernel near half the
+// HBM bandwidth.  Each wave copies RT/64 operator blocks (16 rows x 64 bytes, the lanes
+// assigned so that the linear LDS placement is the swz32 layout) and a quarter of the
+// activation block (the 8 k x NRT ruptures of a chunk, NRT float2 per k row, NRT/16 KB) per
+// chunk; activation entries k >= kvalid are zeroed in registers.
+template <int MF, int NF, int WR, int WC, int NS>
+__global__ __launch_bounds__(256, 2) void k_cgemm32d(const CGemmArgs p) {
+  static_assert(WR * WC == 4, "four waves");
+  constexpr int RT = WR * MF * 16;
+  constexpr int NRT = WC * NF * 8;
+  constexpr int A_BLK = RT / 16;                        // 1 KB operator blocks per chunk
+  constexpr int A_PER_W = A_BLK / 4;
+  constexpr int X_U4 = 4 * NRT;                         // activation 16-byte units per chunk
+  constexpr int X_PER_W = X_U4 / 4 > 64 ? X_U4 / 256 : 1;  // activation copies per wave and chunk
+  constexpr int X_LANES = X_U4 / 4 > 64 ? 64 : X_U4 / 4;   // active lanes of an activation copy
+  constexpr int PER_W = A_PER_W + X_PER_W;
+  constexpr int STAGE = A_BLK * 64 + X_U4 + 64 - X_LANES;  // float4 per stage, with copy padding
+  constexpr int PENDING = (NS - 2) * PER_W;
+  static_assert(A_BLK % 4 == 0 && X_U4 % 4 == 0, "every wave issues the same copies");
+  static_assert(NS >= 2 && NS <= 4 && PENDING < 16, "stages and wait counts");
+  __shared__ float4 st0[STAGE];
+  __shared__ float4 st1[STAGE];
+  __shared__ float4 st2[NS > 2 ? STAGE : 1];
+  __shared__ float4 st3[NS > 3 ? STAGE : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WC, wc = wave % WC;
+  const int ci = lane & 1, kq = lane >> 4;
+  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
+  const int per_slot = p.nrt * p.nct * p.splits;
+  const int l = x + 8 * (q / per_slot);
+  int rem = q % per_slot;
+  const int split = rem % p.splits;
+  rem /= p.splits;
+  const int ct = rem % p.nct, rt = rem / p.nct;
+  const bool dc = (l == 0);
+  const int c0 = (int)((int64_t)p.nchunks * split / p.splits);
+  const int c1 = (int)((int64_t)p.nchunks * (split + 1) / p.splits);
+  const int row0 = rt * RT, b0 = ct * NRT;
+  const float2* Al = p.A + (int64_t)l * p.a_slot;
+  const float2* Xl = p.X + (int64_t)l * p.x_slot;
+  // operator copy slot q of this wave: 16 rows of block wave + 4 q; lane -> row rr = lane / 4,
+  // 16-byte unit cc such that the linear LDS slot is swz32(row, cc)
+  const int a_rr = lane >> 2;
+  const float2* asrc[A_PER_W];
+#pragma unroll
+  for (int qq = 0; qq < A_PER_W; ++qq) {
+    const int r = 16 * (wave + 4 * qq) + a_rr;
+    const int cc = (lane & 3) ^ ((r >> 1) & 3);
+    asrc[qq] = Al + (int64_t)min(row0 + r, p.rows_alloc - 1) * p.a_row + 2 * cc;
+  }
+  // activation copy: unit u = (wave * X_PER_W + t) * X_LANES + lane is slot s = u % (NRT / 2) of k
+  // row kk = u / (NRT / 2) and holds rupture pair s ^ c32d_xsw(kk): the XOR spreads the four k
+  // rows read together by a wave over distinct LDS banks.  Past the range, a copy of the last
+  // chunk is issued (never read), so that every step has the same number of copies in flight.
+  auto issue = [&](int c, float4* stage) {
+    c32d_issue<NRT, A_PER_W, X_PER_W, X_LANES>(asrc, Xl, p, b0, min(c, c1 - 1), stage + wave * 64,
+                                                stage + A_BLK * 64, wave, lane);
+  };
+
+  f32x4 acc[MF][NF];
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  auto compute = [&](int c, const float4* cur) {
+    const float2* lx = reinterpret_cast<const float2*>(cur + A_BLK * 64);
+    float4 av[MF];
+#pragma unroll
+    for (int a = 0; a < MF; ++a) av[a] = cur[swz32(wr * MF * 16 + 16 * a + (lane & 15), kq)];
+    // K entries of this lane: complex k = 8 c + 2 kq (+1); activation rows past kvalid are zero
+    const bool k0ok = 8 * c + 2 * kq < p.kvalid, k1ok = 8 * c + 2 * kq + 1 < p.kvalid;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int rl = wc * NF * 8 + f * 8 + ((lane & 15) >> 1);
+      const int xs = 2 * ((rl >> 1) ^ c32d_xsw<NRT>(2 * kq)) + (rl & 1);  // same XOR for rows 2 kq, 2 kq + 1
+      float2 x0 = lx[(2 * kq) * NRT + xs];
+      float2 x1 = lx[(2 * kq + 1) * NRT + xs];
+      if (!k0ok) x0 = make_float2(0.f, 0.f);
+      if (!k1ok) x1 = make_float2(0.f, 0.f);
+      float bv[4];
+      embed32<false>(x0, ci, dc, bv[0], bv[1]);
+      embed32<false>(x1, ci, dc, bv[2], bv[3]);
+#pragma unroll
+      for (int a = 0; a < MF; ++a) {
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[0], acc[a][f], 0, 0, 0);
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[1], acc[a][f], 0, 0, 0);
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z, bv[2], acc[a][f], 0, 0, 0);
+        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].w, bv[3], acc[a][f], 0, 0, 0);
+      }
+    }
+  };
+  // chunk c is read from stage (c - c0) % NS, which is then refilled with chunk c + NS - 1
+  // after the next barrier; every chunk issues its copies so that the count in flight is the
+  // same on every path (the wait counts below rely on it)
+  if (c0 < c1) {
+    issue(c0, st0);
+    if (NS > 2) issue(c0 + 1, st1);
+    if (NS > 3) issue(c0 + 2, st2);
+#define S2W_C32D_STEP(K, CUR, NEXT)                                     \
+  do {                                                                  \
+    __builtin_amdgcn_s_waitcnt(0x0F70 | PENDING);                       \
+    asm volatile("" ::: "memory");                                      \
+    __builtin_amdgcn_s_barrier();                                       \
+    asm volatile("" ::: "memory");                                      \
+    issue((K) + NS - 1, NEXT);                                          \
+    if ((K) < c1) compute((K), CUR);                                    \
+  } while (0)
+    for (int k0 = c0; k0 < c1; k0 += NS) {
+      if (NS == 2) {
+        S2W_C32D_STEP(k0, st0, st1);
+        S2W_C32D_STEP(k0 + 1, st1, st0);
+      } else if (NS == 3) {
+        S2W_C32D_STEP(k0, st0, st2);
+        S2W_C32D_STEP(k0 + 1, st1, st0);
+        S2W_C32D_STEP(k0 + 2, st2, st1);
+      } else {
+        S2W_C32D_STEP(k0, st0, st3);
+        S2W_C32D_STEP(k0 + 1, st1, st0);
+        S2W_C32D_STEP(k0 + 2, st2, st1);
+        S2W_C32D_STEP(k0 + 3, st3, st2);
+      }
+    }
+#undef S2W_C32D_STEP
+  }
+  // no copy into LDS may still be in flight when the workgroup ends
+  __builtin_amdgcn_s_waitcnt(0);
+  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
+#pragma unroll
+  for (int a = 0; a < MF; ++a)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + wr * MF * 16 + 16 * a + 4 * kq + r;
+      if (row >= p.nrows) continue;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const int n = 2 * b0 + wc * NF * 16 + 16 * f + (lane & 15);
+        if (n < p.ncols) ow[(int64_t)row * p.o_row + n] = acc[a][f][r];
+      }
+    }
+}
+
 // Tile shapes (rows x ruptures): 0: 64 x 128, 1: 128 x 32, 2: 256 x 8, 3: 64 x 64.
 int cgemm32_rows(int cfg) { return cfg == 0 ? 64 : cfg == 1 ? 128 : cfg == 2 ? 256 : 64; }
 int cgemm32_ruptures(int cfg) { return cfg == 0 ? 128 : cfg == 1 ? 32 : cfg == 2 ? 8 : 64; }
+
+static void cgemm32d_dispatch(int cfg, dim3 grid, hipStream_t st, const CGemmArgs& a) {
+  switch (cfg) {
+    case 0: hipLaunchKernelGGL((k_cgemm32d<2, 8, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_cgemm32d<4, 2, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_cgemm32d<4, 1, 4, 1, 3>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_cgemm32d<2, 4, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
+  }
+}
 
 template <bool RCONT, bool CONJ>
 static void cgemm32_dispatch(int cfg, dim3 grid, hipStream_t st, const CGemmArgs& a) {
@@ -255,7 +450,7 @@ hipError_t launch_cgemm32(int cfg, bool rcont, bool conj, const float2* A, int64
   const int64_t blocks = (int64_t)M * a.nrt * a.nct * splits;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
-  if (!rcont && !conj) cgemm32_dispatch<false, false>(cfg, grid, st, a);
+  if (!rcont && !conj) cgemm32d_dispatch(cfg, grid, st, a);
   else if (!rcont && conj) cgemm32_dispatch<false, true>(cfg, grid, st, a);
   else if (rcont && !conj) cgemm32_dispatch<true, false>(cfg, grid, st, a);
   else cgemm32_dispatch<true, true>(cfg, grid, st, a);
