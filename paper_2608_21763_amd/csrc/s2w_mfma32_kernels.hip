@@ -403,7 +403,7 @@ static void cgemm32d_dispatch(int cfg, dim3 grid, hipStream_t st, const CGemmArg
   switch (cfg) {
     case 0: hipLaunchKernelGGL((k_cgemm32d<2, 8, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
     case 1: hipLaunchKernelGGL((k_cgemm32d<4, 2, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_cgemm32d<4, 1, 4, 1, 3>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_cgemm32d<4, 1, 4, 1, 4>), grid, dim3(256), 0, st, a); break;
     default: hipLaunchKernelGGL((k_cgemm32d<2, 4, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
   }
 }
