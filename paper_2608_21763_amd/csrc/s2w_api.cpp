@@ -720,6 +720,18 @@ static int64_t part_floats(const s2w_plan* p) {
   return (int64_t)std::max(p->hg.splits_max * p->hg.noq, p->hg.nsq) * p->geo.M * 2 * p->hg.bp;
 }
 
+// Sum of the split partials part[s][l][o][2 bp] of a batched product (times tau[l][b] when given)
+// and the inverse real FFT into out[b][o][n]: one fused kernel for M = 256, else the sum into
+// the spectra rows yh[b][o][l] and a row transform.
+static hipError_t sum_and_irfft(const float* part, int splits, int noq, int nrows, int B, int bp, const float* tau,
+                                float2* yh, float* out, const Geometry& g, hipStream_t st) {
+  const float scale = 1.0f / (float)g.L;
+  if (g.M == 256) return launch_sum_irfft256(part, splits, noq, nrows, B, bp, tau, out, g.nt, scale, st);
+  hipError_t e = launch_sum_f(part, splits, g.M, noq, nrows, B, bp, tau, yh, st);
+  if (e == hipSuccess) e = launch_irfft_rows(yh, (int64_t)B * nrows, g.M, 1, out, g.nt, g, scale, st);
+  return e;
+}
+
 // Batched forward on the matrix cores (half-precision stores).
 static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y, hipStream_t st,
                                const DispOut* disp) {
@@ -796,10 +808,8 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
     e = launch_gemm_fw(h.kt_f, h.hterms_f, (const uint32_t*)Fq, U, fscale ? tau_up : nullptr, part, g.ngrid, h.ngq,
                        g.M, h.noq, g.nobs, B, bp, splits, wide_re, st);
   }
-  if (e == hipSuccess)
-    e = launch_sum_f(part, splits, g.M, h.noq, g.nobs, B, bp, fscale ? tau_down : nullptr, yh, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");
-  e = launch_irfft_rows(yh, (int64_t)B * g.nobs, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+  e = sum_and_irfft(part, splits, h.noq, g.nobs, B, bp, fscale ? tau_down : nullptr, yh, y, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: output transform");
   return S2W_OK;
 }
@@ -858,9 +868,8 @@ static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, 
   e = launch_cgemm32(cf, false, false, Fs, f.ngk, 1, (int64_t)f.nok * f.ngk, g.nobs, f.nok, f.ngk, f.ngk, U,
                      (int64_t)g.M * bp, bp, g.ngrid, B, bp, part, prow, (int64_t)f.nok * prow,
                      (int64_t)g.M * f.nok * prow, g.M, sf, st);
-  if (e == hipSuccess) e = launch_sum_f(part, sf, g.M, f.nok, g.nobs, B, bp, nullptr, yh, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: acoustic matrix-core stage");
-  e = launch_irfft_rows(yh, (int64_t)B * g.nobs, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+  e = sum_and_irfft(part, sf, f.nok, g.nobs, B, bp, nullptr, yh, y, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: output transform");
   return S2W_OK;
 }
@@ -899,9 +908,8 @@ static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs,
                        (g.ngrid + 7) / 8 * 8, W, (int64_t)g.M * bp, bp, g.ngrid, B, bp, part, prow,
                        (int64_t)f.nsk * prow, (int64_t)g.M * f.nsk * prow, g.M, sa, st);
   if (e == hipSuccess) e = mark(p->ev_end, st);
-  if (e == hipSuccess) e = launch_sum_f(part, sa, g.M, f.nsk, g.nsub, B, bp, nullptr, gh, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: elastic matrix-core stage");
-  e = launch_irfft_rows(gh, (int64_t)B * g.nsub, g.M, 1, gs, g.nt, g, 1.0f / (float)g.L, st);
+  e = sum_and_irfft(part, sa, f.nsk, g.nsub, B, bp, nullptr, gh, gs, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: output transform");
   return S2W_OK;
 }
@@ -967,9 +975,8 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
                       sg16 ? tau_down : nullptr, nullptr, 0, 0, part, (int64_t)g.M * h.nsq * prow,
                       (int64_t)h.nsq * prow, prow, B, bp, g.M, sa, st);
   if (e == hipSuccess) e = mark(p->ev_end, st);
-  if (e == hipSuccess) e = launch_sum_f(part, sa, g.M, h.nsq, g.nsub, B, bp, nullptr, gh, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: elastic matrix-core stage");
-  e = launch_irfft_rows(gh, (int64_t)B * g.nsub, g.M, 1, gs, g.nt, g, 1.0f / (float)g.L, st);
+  e = sum_and_irfft(part, sa, h.nsq, g.nsub, B, bp, nullptr, gh, gs, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: output transform");
   return S2W_OK;
 }
@@ -1451,9 +1458,8 @@ s2w_status s2w_bltt_apply(s2w_bltt* p, const float* x, int32_t B, float* y, void
   e = launch_cgemm32(cfg, false, false, Fs, (int64_t)g.M * p->ncol_k, 1, p->ncol_k, nrow, nrow, p->ncol_k, p->ncol_k,
                      S, bp, (int64_t)p->ncol_k * bp, p->ncol_k, B, bp, part, prow, (int64_t)p->nrow_k * prow,
                      (int64_t)g.M * p->nrow_k * prow, g.M, splits, st);
-  if (e == hipSuccess) e = launch_sum_f(part, splits, g.M, p->nrow_k, nrow, B, bp, nullptr, yh, st);
   if (e != hipSuccess) return bhip(p, e, "apply: matrix-core product");
-  e = launch_irfft_rows(yh, (int64_t)B * nrow, g.M, 1, y, g.nt, g, 1.0f / (float)g.L, st);
+  e = sum_and_irfft(part, splits, p->nrow_k, nrow, B, bp, nullptr, yh, y, g, st);
   if (e != hipSuccess) return bhip(p, e, "apply: output transform");
   return S2W_OK;
 }
@@ -1480,9 +1486,8 @@ s2w_status s2w_bltt_adjoint(s2w_bltt* p, const float* y, int32_t B, float* x, vo
   e = launch_cgemm32(cfg, true, true, Fs, 1, (int64_t)g.M * p->ncol_k, p->ncol_k, ncol, p->ncol_k, nrow, p->nrow_k, R,
                      bp, (int64_t)p->nrow_k * bp, p->nrow_k, B, bp, part, prow, (int64_t)p->ncol_k * prow,
                      (int64_t)g.M * p->ncol_k * prow, g.M, splits, st);
-  if (e == hipSuccess) e = launch_sum_f(part, splits, g.M, p->ncol_k, ncol, B, bp, nullptr, xh, st);
   if (e != hipSuccess) return bhip(p, e, "adjoint: matrix-core product");
-  e = launch_irfft_rows(xh, (int64_t)B * ncol, g.M, 1, x, g.nt, g, 1.0f / (float)g.L, st);
+  e = sum_and_irfft(part, splits, p->ncol_k, ncol, B, bp, nullptr, xh, x, g, st);
   if (e != hipSuccess) return bhip(p, e, "adjoint: output transform");
   return S2W_OK;
 }

@@ -649,6 +649,94 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
   }
 }
 
+// Sum of the split partials of a batched product and the inverse real FFT of the result, for
+// M = 256: part[s][l][o][2 bp] (complex per rupture, s < splits) -> out[b][o][n], n < nt.
+// A unit is one output row o and 16 ruptures; the partials are read as 128-byte runs (16
+// ruptures of one slot), summed in split order, scaled by tau_down[l][b] when given, and
+// transposed through LDS; the inverse transform (Alg. 2 steps 4-5) is the two 16-point passes of
+// the mid-chain, and each row's samples go out as 128-byte runs.  The launcher checks the
+// sizes; the grid is persistent.
+__global__ __launch_bounds__(256) void k_sum_irfft256(const float2* __restrict__ part, int splits, int noq, int nrows,
+                                                      int B, int bp, const float* __restrict__ tau_down,
+                                                      float* __restrict__ out, int nt, float scale) {
+  constexpr int M = 256, R = 16, LD = 257;
+  __shared__ float2 X[R * LD];
+  __shared__ float2 T[R * 16 * 17];
+  __shared__ float2 twb[2 * M];
+  const Twiddles tw = lds_twiddles(twb, M);
+  const int tid = threadIdx.x;
+  const int r = tid % R, lq = tid / R;  // gather: rupture r of the unit, slots lq + 16 k
+  const int fr = tid >> 4, c = tid & 15;  // transform: row fr, column c
+  float2 twA[15], twR[16];
+  passA_twiddles(tw.c, c, twA);
+  real_twiddles(tw.r, c, twR);
+  const int nbb = (B + R - 1) / R;
+  const int units = nrows * nbb;
+  const int64_t s_stride = (int64_t)M * noq * bp;  // complex values per split
+  for (int u = blockIdx.x; u < units; u += gridDim.x) {
+    const int o = u / nbb, b0 = (u % nbb) * R;
+    {
+      const int b = b0 + r;
+      const int bc = b < B ? b : B - 1;  // loads unconditional, ruptures past B zeroed
+      const float2* src = part + (int64_t)o * bp + bc;
+#pragma unroll 4
+      for (int k = 0; k < 16; ++k) {
+        const int l = lq + 16 * k;
+        const float2* p = src + (int64_t)l * noq * bp;
+        float re = 0.f, im = 0.f;
+        for (int s = 0; s < splits; ++s) {
+          const float2 v = p[s * s_stride];
+          re += v.x;
+          im += v.y;
+        }
+        const float td = tau_down ? tau_down[(int64_t)l * bp + bc] : 1.f;
+        X[r * LD + l] = b < B ? make_float2(re * td, im * td) : make_float2(0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    float2 v[16];
+    const float2* Xr = X + fr * LD;
+    float2* Tr = T + fr * (16 * 17);
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) v[n1] = irfft_pre_w(Xr, 16 * n1 + c, M, twR[n1]);
+    fft256_passA<+1>(v, twA);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Tr[k1 * 17 + c] = v[k1];
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) v[n2] = Tr[c * 17 + n2];
+    dft16<+1>(v);
+    // v[k2] = L (x[2n] + i x[2n+1]) for n = c + 16 k2; nt <= 256 needs n < 128
+    const int b = b0 + fr;
+    if (b < B) {
+      float* dst = out + ((int64_t)b * nrows + o) * nt;
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) {
+        const int m0 = 2 * (c + 16 * k2);
+        if (m0 + 1 < nt && !(nt & 1)) {
+          *reinterpret_cast<float2*>(dst + m0) = make_float2(v[k2].x * scale, v[k2].y * scale);
+        } else {
+          if (m0 < nt) dst[m0] = v[k2].x * scale;
+          if (m0 + 1 < nt) dst[m0 + 1] = v[k2].y * scale;
+        }
+      }
+    }
+    __syncthreads();  // X and T are refilled by the next unit
+  }
+}
+
+hipError_t launch_sum_irfft256(const float* part, int splits, int noq, int nrows, int B, int bp,
+                               const float* tau_down, float* out, int nt, float scale, hipStream_t st) {
+  if (B == 0 || nrows == 0) return hipSuccess;
+  if (B < 0 || nrows < 0 || splits < 1 || noq < nrows || bp < B || nt < 1 || nt > 256) return hipErrorInvalidValue;
+  const int64_t units = (int64_t)nrows * ((B + 15) / 16);
+  if (units > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t nblk = std::min<int64_t>(units, 256 * 8);
+  hipLaunchKernelGGL(k_sum_irfft256, dim3((unsigned)nblk), dim3(256), 0, st, (const float2*)part, splits, noq, nrows,
+                     B, bp, tau_down, out, nt, scale);
+  return hipGetLastError();
+}
+
 hipError_t launch_mid_batch(float2* U, const float* sF, int B, int bp, bool adjoint, bool pack_bf16,
                             const Geometry& g, hipStream_t st, int rupts, float* cmax, int64_t cmax_floats,
                             int* cmax_groups, const DispOut* disp) {

@@ -131,6 +131,9 @@ hipError_t launch_col_scale(const float2* V, int ngrid, int M, int B, int bp, fl
                             float* part, int64_t part_floats, hipStream_t st);
 hipError_t launch_sum_f(const float* part, int splits, int M, int noq, int nobs, int B, int bp, const float* tau_down,
                         float2* yh, hipStream_t st);
+// Sum of split partials part[s][l][o][2 bp] and inverse real FFT into out[b][o][n] (M = 256 only).
+hipError_t launch_sum_irfft256(const float* part, int splits, int noq, int nrows, int B, int bp,
+                               const float* tau_down, float* out, int nt, float scale, hipStream_t st);
 hipError_t launch_zero_strided(uint32_t* out, int64_t n, int64_t stride, int width, hipStream_t st);
 hipError_t launch_act_scale(const float2* S, int M, int nk, int nkp, int B, int bp, float* sig_up, float* sig_down,
                             hipStream_t st);
