@@ -53,7 +53,7 @@ KERNEL_SOURCES = {
     "k_gemm_f2": ["s2w_mfma_kernels.hip", "s2w_half.h"],
     "k_gemm_t2": ["s2w_mfma_adj_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
     "k_gemm_fw": ["s2w_mfma_fw_kernels.hip", "s2w_half.h", "s2w_half_re.h"],
-    "k_cgemm32": ["s2w_mfma32_kernels.hip"],
+    "k_cgemm32d": ["s2w_mfma32_kernels.hip"],
     "k_direct": ["s2w_direct_kernels.hip"],
 }
 
@@ -410,7 +410,7 @@ def main():
         ms_step = total_ms / args.steps
         kmean = float(np.mean(kern_ms))
         flops_g = 8.0 * bcfg.ngrid * bcfg.nsub * bcfg.nt * B
-        fp32b = {"tuning": tuning, "ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "kernel": "k_cgemm32",
+        fp32b = {"tuning": tuning, "ruptures_per_s": 1000.0 * B / ms_step, "ms_per_step": ms_step, "B": B, "kernel": "k_cgemm32d",
                  "kernel_ms": kmean, "kernel_ms_min": float(np.min(kern_ms)), "algorithmic_flops": flops_g,
                  "achieved_TFLOPs": flops_g / (kmean * 1e9),
                  "mfma_frac": flops_g / (kmean * 1e9) / MFMA_PEAK["f32"], "setup_s": setup_s}
@@ -541,7 +541,7 @@ def main():
         return res
 
     if "adj" in paths:
-        result["adj"] = adj_path(args.batch_adj, "f32", "fp32 batched", "k_cgemm32 (transposed elastic)",
+        result["adj"] = adj_path(args.batch_adj, "f32", "fp32 batched", "k_cgemm32d (transposed elastic)",
                                  MFMA_PEAK["f32"], layout="batched")
     if "hadj" in paths:
         result["hadj"] = adj_path(args.batch, "bf16", "bf16 batched", "k_gemm_t2 (transposed elastic)",
@@ -631,7 +631,7 @@ def main():
         workload = f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, fp32 single rupture"
     else:
         roof = {"bound": "mfma", "achieved": fp32b["achieved_TFLOPs"], "peak": MFMA_PEAK["f32"], "unit": "TFLOP/s",
-                "frac": fp32b["mfma_frac"], "traffic": traffic_for("k_cgemm32")}
+                "frac": fp32b["mfma_frac"], "traffic": traffic_for("k_cgemm32d")}
         workload = f"cascadia share {cfg.nsub}x{cfg.ngrid}x{cfg.nobs}x{cfg.nt}, fp32 batched B={fp32b['B']}"
     out = {
         "metric": METRIC,

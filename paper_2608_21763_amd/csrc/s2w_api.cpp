@@ -899,7 +899,9 @@ static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs,
   e = launch_mid_batch(W, nullptr, B, bp, true, false, g, st, p->tune.mid_rupts);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(Gs[g][l][j]) W'[g][l][b]
-  const int c3 = b32_cfg(p, B, true);
+  // the tuned reduction tile, else 128 x 32 tiles from B = 9 to 64 (the subfault rows are many
+  // more than the forward reduction's observer rows)
+  const int c3 = p->tune.gemm32_cfg_k >= 0 ? p->tune.gemm32_cfg_k : (B <= 8 ? 2 : (B <= 64 ? 1 : 0));
   const int sa = b32_splits(p->tune.adj32_splits, f.splits_a_max, g.M, g.nsub, B, c3);
   const int64_t prow = 2 * (int64_t)bp;
   e = mark(p->ev_begin, st);

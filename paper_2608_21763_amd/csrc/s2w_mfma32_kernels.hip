@@ -65,177 +65,28 @@ struct CGemmArgs {
   int M, nrt, nct, splits;
 };
 
-// Workgroup = 4 waves in a WR x WC grid; wave tile MF x NF fragments of 16 x 16.
-// Tile: RT = WR*MF*16 rows x NRT = WC*NF*8 ruptures; K in chunks of 8 complex values, the
-// operator and activation tiles of the next chunk loaded while the current one is consumed
-// from LDS (double buffer).  Blocks are decoded so that all tiles of slot l run on XCD l mod 8
-// (workgroups are dealt to the eight XCDs round-robin), keeping a slot's activation panel in
-// one L2.
-template <int MF, int NF, int WR, int WC, bool RCONT, bool CONJ>
-__global__ __launch_bounds__(256, 2) void k_cgemm32(const CGemmArgs p) {
-  static_assert(WR * WC == 4, "four waves");
-  constexpr int RT = WR * MF * 16;
-  constexpr int NRT = WC * NF * 8;
-  constexpr int LDX = NRT + 4;             // padded activation row (float2); even
-  constexpr int A_F4 = RT * 4;             // operator tile: RT rows x 8 complex
-  constexpr int X_F4 = 8 * NRT / 2;        // activation tile: 8 k x NRT ruptures
-  constexpr int T_F4 = A_F4 + X_F4;
-  constexpr int PER_T = (T_F4 + 255) / 256;
-  constexpr int LDS_X = 8 * LDX / 2;
-  __shared__ float4 lds[2][A_F4 + LDS_X];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave / WC, wc = wave % WC;
-  const int ci = lane & 1, kq = lane >> 4;
-  const int x = blockIdx.x & 7, q = blockIdx.x >> 3;
-  const int per_slot = p.nrt * p.nct * p.splits;
-  const int l = x + 8 * (q / per_slot);
-  int rem = q % per_slot;
-  const int split = rem % p.splits;
-  rem /= p.splits;
-  const int ct = rem % p.nct, rt = rem / p.nct;
-  const bool dc = (l == 0);
-  const int c0 = (int)((int64_t)p.nchunks * split / p.splits);
-  const int c1 = (int)((int64_t)p.nchunks * (split + 1) / p.splits);
-  const int row0 = rt * RT, b0 = ct * NRT;
-
-  const float2* Al = p.A + (int64_t)l * p.a_slot;
-  const float2* Xl = p.X + (int64_t)l * p.x_slot;
-
-  // loader: item k of this thread (float4 units), for chunk c
-  auto load = [&](int c, float4 (&st)[PER_T]) {
-#pragma unroll
-    for (int it = 0; it < PER_T; ++it) {
-      const int i = tid + 256 * it;
-      if (i >= T_F4) break;
-      if (i < A_F4) {
-        if (!RCONT) {
-          const int r = i >> 2, cc = i & 3;
-          const int row = min(row0 + r, p.rows_alloc - 1);
-          st[it] = *reinterpret_cast<const float4*>(Al + (int64_t)row * p.a_row + 8 * c + 2 * cc);
-        } else {
-          const int kk = i / (RT / 2), rp = i % (RT / 2);
-          const int k = 8 * c + kk;
-          const int row = min(row0 + 2 * rp, p.rows_alloc - 2);
-          float4 v = *reinterpret_cast<const float4*>(Al + (int64_t)min(k, p.kvalid - 1) * p.a_k + row);
-          if (k >= p.kvalid) v = make_float4(0.f, 0.f, 0.f, 0.f);
-          st[it] = v;
-        }
-      } else {
-        const int j = i - A_F4;
-        const int kk = j / (NRT / 2), qq = j % (NRT / 2);
-        const int k = 8 * c + kk;
-        const int b = min(b0 + 2 * qq, p.bp - 2);
-        float4 v = *reinterpret_cast<const float4*>(Xl + (int64_t)min(k, p.xk_alloc - 1) * p.x_k + b);
-        if (k >= p.kvalid) v = make_float4(0.f, 0.f, 0.f, 0.f);
-        st[it] = v;
-      }
-    }
-  };
-  auto put = [&](int buf, const float4 (&st)[PER_T]) {
-#pragma unroll
-    for (int it = 0; it < PER_T; ++it) {
-      const int i = tid + 256 * it;
-      if (i >= T_F4) break;
-      if (i < A_F4) {
-        if (!RCONT) {
-          lds[buf][swz32(i >> 2, i & 3)] = st[it];
-        } else {
-          const int kk = i / (RT / 2), rp = i % (RT / 2);
-          float2* la = reinterpret_cast<float2*>(&lds[buf][0]);
-          la[2 * swz32(2 * rp, kk >> 1) + (kk & 1)] = make_float2(st[it].x, st[it].y);
-          la[2 * swz32(2 * rp + 1, kk >> 1) + (kk & 1)] = make_float2(st[it].z, st[it].w);
-        }
-      } else {
-        const int j = i - A_F4;
-        const int kk = j / (NRT / 2), qq = j % (NRT / 2);
-        lds[buf][A_F4 + (kk * LDX) / 2 + qq] = st[it];
-      }
-    }
-  };
-
-  f32x4 acc[MF][NF];
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[a][f] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  // products of chunk c from LDS buffer cur
-  auto compute = [&](int cur) {
-    const float4* la = &lds[cur][0];
-    const float2* lx = reinterpret_cast<const float2*>(&lds[cur][A_F4]);
-    float4 av[MF];
-#pragma unroll
-    for (int a = 0; a < MF; ++a) av[a] = la[swz32(wr * MF * 16 + 16 * a + (lane & 15), kq)];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      const int rl = wc * NF * 8 + f * 8 + ((lane & 15) >> 1);
-      const float2 x0 = lx[(2 * kq) * LDX + rl];
-      const float2 x1 = lx[(2 * kq + 1) * LDX + rl];
-      float bv[4];
-      embed32<CONJ>(x0, ci, dc, bv[0], bv[1]);
-      embed32<CONJ>(x1, ci, dc, bv[2], bv[3]);
-#pragma unroll
-      for (int a = 0; a < MF; ++a) {
-        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[0], acc[a][f], 0, 0, 0);
-        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].y, bv[1], acc[a][f], 0, 0, 0);
-        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].z, bv[2], acc[a][f], 0, 0, 0);
-        acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].w, bv[3], acc[a][f], 0, 0, 0);
-      }
-    }
-  };
-  // two chunks in flight: chunk c + 2 is loaded into registers while chunk c is consumed from
-  // LDS and chunk c + 1 (loaded one step earlier) waits to be stored to the other buffer; the
-  // two register sets alternate, so the loop body is written for a pair of chunks
-  if (c0 < c1) {
-    float4 sa[PER_T], sb[PER_T];
-    load(c0, sa);
-    if (c0 + 1 < c1) load(c0 + 1, sb);
-    put(0, sa);
-    __syncthreads();
-    for (int c = c0; c < c1; c += 2) {
-      // chunk c (buffer 0) ready; sb holds chunk c + 1
-      if (c + 2 < c1) load(c + 2, sa);
-      compute(0);
-      if (c + 1 < c1) put(1, sb);
-      __syncthreads();
-      if (c + 1 >= c1) break;
-      // chunk c + 1 (buffer 1) ready; sa holds chunk c + 2
-      if (c + 3 < c1) load(c + 3, sb);
-      compute(1);
-      if (c + 2 < c1) put(0, sa);
-      __syncthreads();
-    }
-  }
-  float* ow = p.out + (int64_t)split * p.o_split + (int64_t)l * p.o_slot;
-#pragma unroll
-  for (int a = 0; a < MF; ++a)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wr * MF * 16 + 16 * a + 4 * kq + r;
-      if (row >= p.nrows) continue;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        const int n = 2 * b0 + wc * NF * 16 + 16 * f + (lane & 15);
-        if (n < p.ncols) ow[(int64_t)row * p.o_row + n] = acc[a][f][r];
-      }
-    }
-}
-
-// Copies of chunk c of the float32 forward products into one LDS stage (see k_cgemm32d).
+// Copies of chunk c of a float32 product into one LDS stage (see k_cgemm32d).
 template <int NRT>
 __device__ __forceinline__ int c32d_xsw(int kk) {
   return NRT >= 32 ? ((kk >> 1) & 3) * 4 : 0;
 }
 
-template <int NRT, int A_PER_W, int X_PER_W, int X_LANES>
-__device__ __forceinline__ void c32d_issue(const float2* const (&asrc)[A_PER_W], const float2* Xl,
-                                           const CGemmArgs& p, int b0, int c, float4* a_dst, float4* x_dst,
-                                           int wave, int lane) {
+// XOR of the row-pair units of operator k row kk (row-contiguous operators, RT >= 64)
+__device__ __forceinline__ int c32d_asw(int kk) { return ((kk >> 1) & 3) * 8; }
+
+// Operator copy q of a wave: k-contiguous operators take asrc[q] + 8 c (asrc already holds the
+// row and 16-byte unit of the lane); row-contiguous ones take k row 8 c + akk[q] (clamped below
+// kvalid: k rows past it need not exist and their products are zeroed through the activation)
+// at the row pair held in asrc[q].
+template <int NRT, int A_PER_W, int X_PER_W, int X_LANES, bool RCONT>
+__device__ __forceinline__ void c32d_issue(const float2* const (&asrc)[A_PER_W], const int (&akk)[A_PER_W],
+                                           const float2* Xl, const CGemmArgs& p, int b0, int c, float4* a_dst,
+                                           float4* x_dst, int wave, int lane) {
 #pragma unroll
-  for (int qq = 0; qq < A_PER_W; ++qq)
-    __builtin_amdgcn_global_load_lds(asrc[qq] + 8 * c, (__attribute__((address_space(3))) void*)(a_dst + 256 * qq),
-                                     16, 0, 0);
+  for (int qq = 0; qq < A_PER_W; ++qq) {
+    const float2* src = RCONT ? asrc[qq] + (int64_t)min(8 * c + akk[qq], p.kvalid - 1) * p.a_k : asrc[qq] + 8 * c;
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(a_dst + 256 * qq), 16, 0, 0);
+  }
   // all 64 lanes copy (no branch: a divergent copy makes the compiler drain every copy in
   // flight at the loop head); lane j >= X_LANES writes the unit that belongs at its position,
   // the same bytes as the wave that owns it, or past the block into padding
@@ -251,14 +102,20 @@ __device__ __forceinline__ void c32d_issue(const float2* const (&asrc)[A_PER_W],
   }
 }
 
-// The same products for k-contiguous operators without conjugation (the forward products)
-// with the tiles copied straight from global memory into LDS (global_load_lds_dwordx4, no
+// Workgroup = 4 waves in a WR x WC grid; wave tile MF x NF fragments of 16 x 16.  Tile: RT =
+// WR*MF*16 rows x NRT = WC*NF*8 ruptures; K in chunks of 8 complex values.  Blocks are decoded
+// so that all tiles of slot l run on XCD l mod 8 (workgroups are dealt to the eight XCDs
+// round-robin), keeping a slot's activation panel in one L2.
+// The tiles are copied straight from global memory into LDS (global_load_lds_dwordx4, no
 // register staging) in NS stages: register-staged copies cap a streaming kernel near half the
-// HBM bandwidth.  Each wave copies RT/64 operator blocks (16 rows x 64 bytes, the lanes
-// assigned so that the linear LDS placement is the swz32 layout) and a quarter of the
+// HBM bandwidth.  Each wave copies RT/64 operator blocks of 1 KB and a quarter of the
 // activation block (the 8 k x NRT ruptures of a chunk, NRT float2 per k row, NRT/16 KB) per
-// chunk; activation entries k >= kvalid are zeroed in registers.
-template <int MF, int NF, int WR, int WC, int NS>
+// chunk.  A k-contiguous operator block is 16 rows x 64 bytes, the lanes assigned so that the
+// linear LDS placement is the swz32 layout; a row-contiguous operator is held k-major (RT
+// complex per k row, row pairs XOR-swizzled by c32d_asw) and its fragment is read as two 8-byte
+// halves.  Entries k >= kvalid are zeroed in the activation, in registers (operator values
+// there are finite: rows past kvalid are clamped to existing ones).
+template <int MF, int NF, int WR, int WC, int NS, bool RCONT, bool CONJ>
 __global__ __launch_bounds__(256, 2) void k_cgemm32d(const CGemmArgs p) {
   static_assert(WR * WC == 4, "four waves");
   constexpr int RT = WR * MF * 16;
@@ -293,23 +150,33 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32d(const CGemmArgs p) {
   const int row0 = rt * RT, b0 = ct * NRT;
   const float2* Al = p.A + (int64_t)l * p.a_slot;
   const float2* Xl = p.X + (int64_t)l * p.x_slot;
-  // operator copy slot q of this wave: 16 rows of block wave + 4 q; lane -> row rr = lane / 4,
-  // 16-byte unit cc such that the linear LDS slot is swz32(row, cc)
-  const int a_rr = lane >> 2;
+  // operator copy q of this wave fills 1 KB block wave + 4 q of the stage.  k-contiguous: 16 rows,
+  // lane -> row lane / 4 and the 16-byte unit cc whose linear LDS slot is swz32(row, cc).
+  // Row-contiguous: unit u = 64 (wave + 4 q) + lane is slot s = u % (RT / 2) of k row
+  // kk = u / (RT / 2) and holds row pair s ^ c32d_asw(kk).
   const float2* asrc[A_PER_W];
+  int akk[A_PER_W];
 #pragma unroll
   for (int qq = 0; qq < A_PER_W; ++qq) {
-    const int r = 16 * (wave + 4 * qq) + a_rr;
-    const int cc = (lane & 3) ^ ((r >> 1) & 3);
-    asrc[qq] = Al + (int64_t)min(row0 + r, p.rows_alloc - 1) * p.a_row + 2 * cc;
+    if (!RCONT) {
+      const int r = 16 * (wave + 4 * qq) + (lane >> 2);
+      const int cc = (lane & 3) ^ ((r >> 1) & 3);
+      asrc[qq] = Al + (int64_t)min(row0 + r, p.rows_alloc - 1) * p.a_row + 2 * cc;
+      akk[qq] = 0;
+    } else {
+      const int u = 64 * (wave + 4 * qq) + lane;
+      akk[qq] = u / (RT / 2);
+      const int rp = (u % (RT / 2)) ^ c32d_asw(akk[qq]);
+      asrc[qq] = Al + min(row0 + 2 * rp, p.rows_alloc - 2);
+    }
   }
   // activation copy: unit u = (wave * X_PER_W + t) * X_LANES + lane is slot s = u % (NRT / 2) of k
   // row kk = u / (NRT / 2) and holds rupture pair s ^ c32d_xsw(kk): the XOR spreads the four k
   // rows read together by a wave over distinct LDS banks.  Past the range, a copy of the last
   // chunk is issued (never read), so that every step has the same number of copies in flight.
   auto issue = [&](int c, float4* stage) {
-    c32d_issue<NRT, A_PER_W, X_PER_W, X_LANES>(asrc, Xl, p, b0, min(c, c1 - 1), stage + wave * 64,
-                                                stage + A_BLK * 64, wave, lane);
+    c32d_issue<NRT, A_PER_W, X_PER_W, X_LANES, RCONT>(asrc, akk, Xl, p, b0, min(c, c1 - 1), stage + wave * 64,
+                                                       stage + A_BLK * 64, wave, lane);
   };
 
   f32x4 acc[MF][NF];
@@ -322,7 +189,18 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32d(const CGemmArgs p) {
     const float2* lx = reinterpret_cast<const float2*>(cur + A_BLK * 64);
     float4 av[MF];
 #pragma unroll
-    for (int a = 0; a < MF; ++a) av[a] = cur[swz32(wr * MF * 16 + 16 * a + (lane & 15), kq)];
+    for (int a = 0; a < MF; ++a) {
+      const int row = wr * MF * 16 + 16 * a + (lane & 15);
+      if (!RCONT) {
+        av[a] = cur[swz32(row, kq)];
+      } else {
+        // complex (k, row) at k * RT + 2 ((row / 2) ^ c32d_asw(k)) + row % 2; k = 2 kq, 2 kq + 1
+        const float2* la = reinterpret_cast<const float2*>(cur);
+        const int ra = 2 * ((row >> 1) ^ c32d_asw(2 * kq)) + (row & 1);  // same XOR for both k rows
+        const float2 a0 = la[(2 * kq) * RT + ra], a1 = la[(2 * kq + 1) * RT + ra];
+        av[a] = make_float4(a0.x, a0.y, a1.x, a1.y);
+      }
+    }
     // K entries of this lane: complex k = 8 c + 2 kq (+1); activation rows past kvalid are zero
     const bool k0ok = 8 * c + 2 * kq < p.kvalid, k1ok = 8 * c + 2 * kq + 1 < p.kvalid;
 #pragma unroll
@@ -334,8 +212,8 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32d(const CGemmArgs p) {
       if (!k0ok) x0 = make_float2(0.f, 0.f);
       if (!k1ok) x1 = make_float2(0.f, 0.f);
       float bv[4];
-      embed32<false>(x0, ci, dc, bv[0], bv[1]);
-      embed32<false>(x1, ci, dc, bv[2], bv[3]);
+      embed32<CONJ>(x0, ci, dc, bv[0], bv[1]);
+      embed32<CONJ>(x1, ci, dc, bv[2], bv[3]);
 #pragma unroll
       for (int a = 0; a < MF; ++a) {
         acc[a][f] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a].x, bv[0], acc[a][f], 0, 0, 0);
@@ -399,22 +277,13 @@ __global__ __launch_bounds__(256, 2) void k_cgemm32d(const CGemmArgs p) {
 int cgemm32_rows(int cfg) { return cfg == 0 ? 64 : cfg == 1 ? 128 : cfg == 2 ? 256 : 64; }
 int cgemm32_ruptures(int cfg) { return cfg == 0 ? 128 : cfg == 1 ? 32 : cfg == 2 ? 8 : 64; }
 
+template <bool RCONT, bool CONJ>
 static void cgemm32d_dispatch(int cfg, dim3 grid, hipStream_t st, const CGemmArgs& a) {
   switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_cgemm32d<2, 8, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_cgemm32d<4, 2, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_cgemm32d<4, 1, 4, 1, 4>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_cgemm32d<2, 4, 2, 2, 3>), grid, dim3(256), 0, st, a); break;
-  }
-}
-
-template <bool RCONT, bool CONJ>
-static void cgemm32_dispatch(int cfg, dim3 grid, hipStream_t st, const CGemmArgs& a) {
-  switch (cfg) {
-    case 0: hipLaunchKernelGGL((k_cgemm32<2, 8, 2, 2, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
-    case 1: hipLaunchKernelGGL((k_cgemm32<4, 2, 2, 2, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_cgemm32<4, 1, 4, 1, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_cgemm32<2, 4, 2, 2, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    case 0: hipLaunchKernelGGL((k_cgemm32d<2, 8, 2, 2, 3, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    case 1: hipLaunchKernelGGL((k_cgemm32d<4, 2, 2, 2, 3, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_cgemm32d<4, 1, 4, 1, 4, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_cgemm32d<2, 4, 2, 2, 3, RCONT, CONJ>), grid, dim3(256), 0, st, a); break;
   }
 }
 
@@ -450,10 +319,10 @@ hipError_t launch_cgemm32(int cfg, bool rcont, bool conj, const float2* A, int64
   const int64_t blocks = (int64_t)M * a.nrt * a.nct * splits;
   if (blocks <= 0 || blocks > 0x7fffffff) return hipErrorInvalidValue;
   const dim3 grid((unsigned)blocks);
-  if (!rcont && !conj) cgemm32d_dispatch(cfg, grid, st, a);
-  else if (!rcont && conj) cgemm32_dispatch<false, true>(cfg, grid, st, a);
-  else if (rcont && !conj) cgemm32_dispatch<true, false>(cfg, grid, st, a);
-  else cgemm32_dispatch<true, true>(cfg, grid, st, a);
+  if (!rcont && !conj) cgemm32d_dispatch<false, false>(cfg, grid, st, a);
+  else if (!rcont && conj) cgemm32d_dispatch<false, true>(cfg, grid, st, a);
+  else if (rcont && !conj) cgemm32d_dispatch<true, false>(cfg, grid, st, a);
+  else cgemm32d_dispatch<true, true>(cfg, grid, st, a);
   return hipGetLastError();
 }
 
