@@ -198,7 +198,7 @@ def main():
     ap.add_argument("--steps", type=int, default=64)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batch", type=int, default=256, help="ruptures per call on the batched half path")
-    ap.add_argument("--paths", default="fp32,direct,fp32b,half,halfh,half16,halfmix,adj,hadj,bltt,strong,weak",
+    ap.add_argument("--paths", default="fp32,direct,fp32b,half,halfh,half16,halfmix,x2,adj,hadj,bltt,strong,weak",
                     help="fp32 (single rupture), fp32b (batched float32), half (batched half precision, --half-dtype), "
                          "halfh (bfloat16 stores with bfloat16 products on high and low activation terms), "
                          "half16 (batched float16 stores), halfmix (bfloat16 elastic and float16 acoustic stores), "
@@ -206,7 +206,8 @@ def main():
                          "--batch residuals), "
                          "direct (time-domain evaluation of eq. 4 on the float32 matrix cores, single rupture), "
                          "bltt (elastic operator alone: seafloor displacement), strong / weak (the float32 "
-                         "single-rupture path on the strong- and weak-scaling per-GPU shares)")
+                         "single-rupture path on the strong- and weak-scaling per-GPU shares), x2 (bfloat16 and "
+                         "float16 stores at the doubled 963 x 75,520 share, B = 1 and 64)")
     ap.add_argument("--batch32", type=int, default=256, help="ruptures per call on the batched float32 path")
     ap.add_argument("--direct-steps", type=int, default=16, help="timed single-rupture calls of the direct path")
     ap.add_argument("--batch-adj", type=int, default=64, help="residuals per call on the batched float32 adjoint")
@@ -500,6 +501,33 @@ def main():
         result["half16"] = half_path("f16", "f16", args.batch)
     if "halfmix" in paths:
         result["halfmix"] = half_path("bf16", "f16", args.batch)
+
+    # ---------------- doubled share, half-precision stores, B = 1 and 64 ----------------
+    if "x2" in paths:
+        xcfg = synth.workload("cascadia_x2")
+        result["x2"] = {}
+        for dt in ("bf16", "f16"):
+            op = S2WOperator(xcfg.nsub, xcfg.ngrid, xcfg.nobs, xcfg.nt, max_batch=64, dt=xcfg.dt, device=0,
+                             g_dtype=dt, f_dtype=dt)
+            t = time.perf_counter()
+            op.load_operators(*host_generators(xcfg), chunk_rows=1024)
+            setup_s = time.perf_counter() - t
+            s_host = synth.gen_slip_batch(xcfg, 0, 128)
+            hbytes = algorithmic_bytes(xcfg.nsub, xcfg.nobs, xcfg.ngrid, xcfg.nt, 2)
+            for B in (1, 64):
+                s_dev = torch.tensor(s_host[:2 * B], device=dev).reshape(2, B, xcfg.nsub, xcfg.nt)
+                total_ms, kern_ms, _ = time_path(op, s_dev, args.steps, args.warmup, B)
+                ms = total_ms / args.steps
+                kmean = float(np.mean(kern_ms))
+                flops_g = 8.0 * xcfg.ngrid * xcfg.nsub * xcfg.nt * B
+                r = {"ms_per_step": ms, "ruptures_per_s": 1000.0 * B / ms, "kernel_ms": kmean,
+                     "achieved_TFLOPs": flops_g / (kmean * 1e9), "call_GBs": hbytes / (ms * 1e6), "setup_s": setup_s}
+                result["x2"][f"{dt}_B{B}"] = r
+                log(f"doubled share {dt} B={B}: {ms:.3f} ms/call, {r['ruptures_per_s']:.0f} ruptures/s, elastic GEMM "
+                    f"{kmean:.3f} ms = {r['achieved_TFLOPs']:.0f} TFLOP/s; operator bytes over the call "
+                    f"{r['call_GBs']:.0f} GB/s")
+            del op
+            torch.cuda.empty_cache()
 
     # ---------------- misfit gradients: batched adjoints ----------------
     def adj_path(B, gdt, label, kernel, peak, **kw):

@@ -231,7 +231,9 @@ typedef struct s2w_tuning {
   int32_t gemm32_cfg;        /* batched float32 GEMMs over grid rows (forward elastic, adjoint acoustic): tile,
                                 -1 automatic, 1..4 = rows x ruptures 64 x 128, 128 x 32, 256 x 8, 64 x 64 */
   int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint
-                                elastic): tile, same values */
+                                elastic): tile, same values (automatic: 256 x 8 for B <= 8; above, the
+                                forward acoustic GEMM takes 64 x 64 up to B = 64 and 64 x 128 beyond,
+                                the adjoint elastic GEMM 128 x 32 up to B = 64 and 64 x 128 beyond) */
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
   int32_t adj32_splits;      /* batched adjoint (float32 and half stores), transposed elastic GEMM: grid-row
                                 splits (1..8; half stores may clamp to what the partial region holds) */
