@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define S2W_ABI_VERSION 5
+#define S2W_ABI_VERSION 6
 
 typedef struct s2w_plan s2w_plan;
 
@@ -230,10 +230,9 @@ typedef struct s2w_tuning {
                                 activations where its tile fits (else, and for float16 products, as 3) */
   int32_t gemm32_cfg;        /* batched float32 GEMMs over grid rows (forward elastic, adjoint acoustic): tile,
                                 -1 automatic, 1..4 = rows x ruptures 64 x 128, 128 x 32, 256 x 8, 64 x 64 */
-  int32_t gemm32_cfg_k;      /* batched float32 GEMMs reducing over grid rows (forward acoustic, adjoint
-                                elastic): tile, same values (automatic: 256 x 8 for B <= 8; above, the
-                                forward acoustic GEMM takes 64 x 64 up to B = 64 and 64 x 128 beyond,
-                                the adjoint elastic GEMM 128 x 32 up to B = 64 and 64 x 128 beyond) */
+  int32_t gemm32_cfg_k;      /* batched float32 forward acoustic GEMM (reduces over grid rows): tile, same
+                                values (automatic: 256 x 8 for B <= 8, 64 x 64 up to B = 64, 64 x 128
+                                beyond) */
   int32_t gemm32_splits;     /* batched float32 acoustic GEMM: grid-row splits (1..16) */
   int32_t adj32_splits;      /* batched adjoint (float32 and half stores), transposed elastic GEMM: grid-row
                                 splits (1..8; half stores may clamp to what the partial region holds) */
@@ -243,6 +242,9 @@ typedef struct s2w_tuning {
                                 real-column activation fragments in LDS (same results bit for bit) */
   int32_t hadj_tile_g;       /* half-precision adjoint, transposed elastic GEMM tile: same values */
   int32_t mid_rupts;         /* batched mid-chain (Nt = 256): ruptures per work unit, 16 or 32 */
+  int32_t adj32_cfg;         /* batched float32 adjoint, transposed elastic GEMM (reduces over grid rows):
+                                tile, values as gemm32_cfg (automatic: 256 x 8 for B <= 8, 128 x 32 up
+                                to B = 64, 64 x 128 beyond) */
 } s2w_tuning;
 
 s2w_status s2w_set_tuning(s2w_plan* plan, const s2w_tuning* t);

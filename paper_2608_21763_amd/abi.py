@@ -44,7 +44,8 @@ class Tuning(ctypes.Structure):
                 ("adj_splits", ctypes.c_int32), ("batch_path_min_b", ctypes.c_int32), ("gemm_cfg", ctypes.c_int32),
                 ("fgemm_splits", ctypes.c_int32), ("fgemm_lds", ctypes.c_int32), ("gemm32_cfg", ctypes.c_int32),
                 ("gemm32_cfg_k", ctypes.c_int32), ("gemm32_splits", ctypes.c_int32), ("adj32_splits", ctypes.c_int32),
-                ("hadj_tile_f", ctypes.c_int32), ("hadj_tile_g", ctypes.c_int32), ("mid_rupts", ctypes.c_int32)]
+                ("hadj_tile_f", ctypes.c_int32), ("hadj_tile_g", ctypes.c_int32), ("mid_rupts", ctypes.c_int32),
+                ("adj32_cfg", ctypes.c_int32)]
 
 
 EXPORTS = ["s2w_abi_version", "s2w_status_string", "s2w_last_error", "s2w_plan_create", "s2w_plan_destroy",

@@ -35,7 +35,7 @@ def candidates(op, adjoint: bool = False) -> list[dict]:
         if op.g_dtype != "f32":
             return [{"hadj_tile_f": a, "hadj_tile_g": b} for a, b in itertools.product((3, 4, 6, 7, 8), repeat=2)]
         if op.plan_layout() == "batched":
-            return [{"gemm32_cfg": a, "gemm32_cfg_k": b} for a, b in itertools.product((1, 2, 3, 4), repeat=2)]
+            return [{"adj32_cfg": a} for a in (1, 2, 3, 4)]
         return [{"fused_rows": r, "fused_wg_per_cu": w} for r in (4, 8) for w in (1, 2)]
     if op.g_dtype != "f32":
         return [{"gemm_cfg": g, "fgemm_lds": f} for g in (4, 10, 12, 16, 17, 18, 24) for f in (3, 4, 2)]
@@ -69,8 +69,8 @@ def autotune(op, B: int, reps: int = 3, adjoint: bool | None = None, cache_path:
     """Pick the fastest tile shapes of ``op`` for batches of B and apply them.
 
     The objective is the time of one forward call, plus one adjoint call when ``adjoint``
-    is true (the default; half-precision stores tune the adjoint's own tiles on the adjoint's
-    time).  Returns
+    is true (the default); the adjoint's own tiles (half-precision stores: both products;
+    float32 batched layout: the transposed elastic product) are tuned on the adjoint's time.  Returns
     ``{"best": tuning, "ms": time, "results": [(tuning, ms), ...], "cached": bool}``.
     """
     if not 1 <= B <= op.max_batch:
@@ -103,11 +103,15 @@ def autotune(op, B: int, reps: int = 3, adjoint: bool | None = None, cache_path:
         fwd()
         adj()
 
-    if op.g_dtype != "f32" and adjoint:
+    if adjoint and op.g_dtype != "f32":
         # the half-precision adjoint has tile controls of its own: tune the two calls apart
         phases = [(candidates(op), fwd), (candidates(op, adjoint=True), adj)]
+    elif adjoint and op.plan_layout() == "batched":
+        # float32: the grid-row tile serves the forward elastic and the adjoint acoustic product,
+        # so it is tuned on both calls; the adjoint's elastic product then on the adjoint alone
+        phases = [(candidates(op), both), (candidates(op, adjoint=True), adj)]
     else:
-        # the float32 tile controls serve the forward and the adjoint products alike
+        # the single layout's controls serve the forward and the adjoint alike
         phases = [(candidates(op), both if adjoint else fwd)]
     results, best, ms = [], {}, 0.0
     for cands, call in phases:

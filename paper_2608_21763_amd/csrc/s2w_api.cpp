@@ -430,6 +430,7 @@ s2w_status s2w_plan_create(const s2w_desc* desc, int32_t device, s2w_plan** out)
   p->tune.hadj_tile_f = -1;
   p->tune.hadj_tile_g = -1;
   p->tune.mid_rupts = 16;
+  p->tune.adj32_cfg = -1;
   p->row_set.assign((size_t)d.ngrid, 0);
   p->rows_missing = d.ngrid;
   {
@@ -558,6 +559,10 @@ s2w_status s2w_set_tuning(s2w_plan* p, const s2w_tuning* t) {
       return fail(p, S2W_EINVAL, "tuning: hadj_tile_f must be -1, 3, 4, 6, 7 or 8");
     n.hadj_tile_f = t->hadj_tile_f < 0 ? -1 : t->hadj_tile_f - 1;
   }
+  if (t->adj32_cfg) {
+    if (t->adj32_cfg < -1 || t->adj32_cfg > 4) return fail(p, S2W_EINVAL, "tuning: adj32_cfg");
+    n.adj32_cfg = t->adj32_cfg < 0 ? -1 : t->adj32_cfg - 1;
+  }
   if (t->mid_rupts) {
     if (t->mid_rupts != 16 && t->mid_rupts != 32) return fail(p, S2W_EINVAL, "tuning: mid_rupts must be 16 or 32");
     n.mid_rupts = t->mid_rupts;
@@ -580,6 +585,7 @@ s2w_status s2w_get_tuning(const s2w_plan* p, s2w_tuning* t) {
   t->batch_path_min_b = 0;
   t->gemm32_cfg = p->tune.gemm32_cfg < 0 ? -1 : p->tune.gemm32_cfg + 1;
   t->gemm32_cfg_k = p->tune.gemm32_cfg_k < 0 ? -1 : p->tune.gemm32_cfg_k + 1;
+  t->adj32_cfg = p->tune.adj32_cfg < 0 ? -1 : p->tune.adj32_cfg + 1;
   t->hadj_tile_f = p->tune.hadj_tile_f < 0 ? -1 : p->tune.hadj_tile_f + 1;
   t->hadj_tile_g = p->tune.hadj_tile_g < 0 ? -1 : p->tune.hadj_tile_g + 1;
   return S2W_OK;
@@ -899,9 +905,9 @@ static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs,
   e = launch_mid_batch(W, nullptr, B, bp, true, false, g, st, p->tune.mid_rupts);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: mid-chain");
   // part[split][l][j][n] = sum_{g in split} conj(Gs[g][l][j]) W'[g][l][b]
-  // the tuned reduction tile, else 128 x 32 tiles from B = 9 to 64 (the subfault rows are many
-  // more than the forward reduction's observer rows)
-  const int c3 = p->tune.gemm32_cfg_k >= 0 ? p->tune.gemm32_cfg_k : (B <= 8 ? 2 : (B <= 64 ? 1 : 0));
+  // its own tile: by default 128 x 32 tiles from B = 9 to 64 (the subfault rows are many more
+  // than the forward reduction's observer rows)
+  const int c3 = p->tune.adj32_cfg >= 0 ? p->tune.adj32_cfg : (B <= 8 ? 2 : (B <= 64 ? 1 : 0));
   const int sa = b32_splits(p->tune.adj32_splits, f.splits_a_max, g.M, g.nsub, B, c3);
   const int64_t prow = 2 * (int64_t)bp;
   e = mark(p->ev_begin, st);

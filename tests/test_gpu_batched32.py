@@ -107,7 +107,7 @@ def test_tile_shapes_bit_identical(B):
     ys, gs = {}, {}
     for c in (1, 2, 3, 4):
         for ck in (1, 2, 3, 4):
-            op.set_tuning(gemm32_cfg=c, gemm32_cfg_k=ck, gemm32_splits=3, adj32_splits=2)
+            op.set_tuning(gemm32_cfg=c, gemm32_cfg_k=ck, adj32_cfg=ck, gemm32_splits=3, adj32_splits=2)
             ys[c, ck] = op.forward(s).clone()
             gs[c, ck] = op.adjoint(r).clone()
     first = (1, 1)

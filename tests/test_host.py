@@ -19,7 +19,7 @@ def test_library_exports_every_declared_symbol():
     for name in sorted(declared):
         assert hasattr(lib, name), f"{name} declared in s2w.h but not exported"
     assert declared == set(abi.EXPORTS)
-    assert abi.load_library().s2w_abi_version() == 5
+    assert abi.load_library().s2w_abi_version() == 6
 
 
 def test_table2_storage_from_byte_calculator():
