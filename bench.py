@@ -425,6 +425,20 @@ def main():
             fp32b["rel_l2_sampled"] = {str(b): e for b, e in zip(pick, errs)}
             fp32b["rel_l2"] = max(errs)
             log(f"fp32 batched rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
+        # the other batch sizes of the ensemble configuration, on the same plan (default tiles)
+        op.set_tuning(gemm32_cfg=-1, gemm32_cfg_k=-1)
+        fp32b["smaller_batches"] = {}
+        for Bs in (8, 64):
+            if Bs >= B:
+                continue
+            t_ms, k_ms, _ = time_path(op, s_dev[:, :Bs], args.steps, args.warmup, Bs)
+            ms_s, km = t_ms / args.steps, float(np.mean(k_ms))
+            fl = 8.0 * bcfg.ngrid * bcfg.nsub * bcfg.nt * Bs
+            fp32b["smaller_batches"][str(Bs)] = {"ms_per_step": ms_s, "ruptures_per_s": 1000.0 * Bs / ms_s,
+                                                 "kernel_ms": km, "achieved_TFLOPs": fl / (km * 1e9),
+                                                 "operator_GBs": bcfg.ngrid * bcfg.nsub * bcfg.nt * 8 / (km * 1e6)}
+            log(f"fp32 batched B={Bs}: {ms_s:.3f} ms/call, {1000.0 * Bs / ms_s:.0f} ruptures/s, elastic GEMM {km:.3f} ms "
+                f"= {fl / (km * 1e9):.1f} TFLOP/s, its operator read at {bcfg.ngrid * bcfg.nsub * bcfg.nt * 8 / (km * 1e6):.0f} GB/s")
         result["fp32b"] = fp32b
         del op
         torch.cuda.empty_cache()
@@ -488,6 +502,16 @@ def main():
             res["rel_l2_sampled"] = {str(b): e for b, e in zip(pick, errs)}
             res["rel_l2"] = max(errs)
             log(f"half {label} rel-L2 on ruptures {pick}: " + " ".join(f"{e:.2e}" for e in errs))
+        if B > 64 and not bf16_products:
+            # B = 64 on the same plan (default tiles)
+            op.set_tuning(gemm_cfg=-1, fgemm_lds=1)
+            t_ms, k_ms, _ = time_path(op, s_dev[:, :64], args.steps, args.warmup, 64)
+            ms_s, km = t_ms / args.steps, float(np.mean(k_ms))
+            fl = 8.0 * bcfg.ngrid * bcfg.nsub * bcfg.nt * 64
+            res["B64"] = {"ms_per_step": ms_s, "ruptures_per_s": 64000.0 / ms_s, "kernel_ms": km,
+                          "achieved_TFLOPs": fl / (km * 1e9)}
+            log(f"half {label} B=64: {ms_s:.3f} ms/call, {64000.0 / ms_s:.0f} ruptures/s, elastic GEMM {km:.3f} ms "
+                f"= {fl / (km * 1e9):.0f} TFLOP/s")
         del op
         torch.cuda.empty_cache()
         return res
