@@ -141,3 +141,27 @@ def test_autograd_batched():
     g = s.grad.cpu().numpy().astype(np.float64)
     g_ref = oracle.adjoint(G, F, oracle.forward(G, F, s_np) - y_obs)
     assert oracle.rel_l2(g, g_ref) <= TOL
+
+
+@pytest.mark.parametrize("nt", [201, 255])
+@pytest.mark.parametrize("layout,dtype", [("batched", "f32"), ("batched", "f16")])
+def test_steps_below_256_on_256_bins(nt, layout, dtype):
+    # 2 nt padded to 512 gives 256 packed bins, the fused split sum and inverse transform and the
+    # register mid-chain, with nt < 256 (odd: the output rows are not 8-byte aligned) and a
+    # ragged batch, forward and adjoint
+    cfg = synth.SynthConfig(nsub=11, ngrid=70, nobs=9, nt=nt, seed=83, slip_seed=84, op_kind="dense",
+                            slip_mode="dense")
+    log_case("b32_nt_256_bins", nt=nt, dtype=dtype)
+    B = 19
+    kw = {"layout": layout} if dtype == "f32" else {"g_dtype": dtype, "f_dtype": dtype}
+    op = make_operator(cfg, max_batch=B, dt=0.5, chunk_rows=23, **kw)
+    s = synth.gen_slip_batch(cfg, 0, B)
+    r = synth.normals(8, "r", 0, (B, cfg.nobs, nt))
+    y = op.forward(to_dev(s)).cpu().numpy()
+    gs = op.adjoint(to_dev(r)).cpu().numpy()
+    G, F = _oracle_ops(cfg)
+    ey = oracle.rel_l2_per_rupture(y, oracle.forward(G, F, s, dt=0.5))
+    eg = oracle.rel_l2_per_rupture(gs, oracle.adjoint(G, F, r, dt=0.5))
+    tol = TOL if dtype == "f32" else 2e-3
+    print(dtype, nt, "forward", ey.max(), "adjoint", eg.max())
+    assert ey.max() <= tol and eg.max() <= tol
