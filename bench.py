@@ -20,7 +20,7 @@ slip histories are already resident in HBM.  Paths timed:
 The headline value is the half path's ruptures/s when it is available.
 Operator setup (generation, upload, transforms) is excluded, as in the paper.
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library computes one GPU's share.
 """
 from __future__ import annotations
 

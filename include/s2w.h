@@ -52,7 +52,7 @@ typedef enum s2w_status {
   S2W_EINVAL = 1,        /* bad argument: null/misaligned pointer, size, batch out of range */
   S2W_ENOMEM = 2,        /* bound operator store or workspace smaller than s2w_query_sizes asks */
   S2W_ESTATE = 3,        /* call out of order: memory not bound, operators not fully set */
-  S2W_EUNSUPPORTED = 4,  /* valid request this build does not implement (dtype, size limit) */
+  S2W_EUNSUPPORTED = 4,  /* valid request the library does not implement (dtype, size limit) */
   S2W_EHIP = 5           /* a HIP runtime call or kernel launch failed; see s2w_last_error */
 } s2w_status;
 
@@ -103,7 +103,7 @@ typedef enum s2w_layout {
   S2W_LAYOUT_DIRECT = 3
 } s2w_layout;
 
-/* Problem description.  Limits of this build: 1 <= nt <= 512, 1 <= nsub <= 1024,
+/* Problem description.  Limits of the library: 1 <= nt <= 512, 1 <= nsub <= 1024,
  * 1 <= nobs <= 256, 1 <= ngrid, 0 <= max_batch <= 1024. */
 typedef struct s2w_desc {
   int32_t nsub;       /* Nf: fault subfaults (columns of F_{G,k}) */
