@@ -6,12 +6,12 @@ and the largest active set).
 The oracle's waveforms for those ruptures are stored in tests/golden/headline_ref.npz, written
 by tests/golden/make_headline_ref.py, which calls only the oracle and the seeded generator (a
 whole run of the oracle over 34 ruptures of this share takes tens of minutes of CPU time).
-Per-rupture rel-L2 and element-wise errors are printed (max, p95, median).  Float16 stores are
-held to the half-precision bound 2e-3 on every sampled rupture (measured max 3.4e-4).
-Bfloat16 stores do NOT meet 2e-3 on every sampled rupture (measured max 2.15e-3 on rupture 56,
-p95 1.90e-3, median 1.59e-3): they are held to the regression ceiling gpu_util.BF16_CEILING and
-the printed line says whether 2e-3 is met.  The mixed store (bfloat16 elastic, float16
-acoustic spectra) is reported the same way.
+Per-rupture rel-L2 and element-wise errors are printed (max, p95, median).  Float16 stores and
+the timed store (bfloat16 elastic, float16 acoustic spectra) are held to the half-precision bound
+2e-3 on every sampled rupture (measured max 3.4e-4 and 1.70e-3).  Bfloat16 stores for both
+operators do NOT meet 2e-3 on every sampled rupture (measured max 2.15e-3 on rupture 56, p95
+1.90e-3, median 1.59e-3): they are held to the regression ceiling gpu_util.BF16_CEILING and the
+printed line says whether 2e-3 is met.
 """
 import os
 
@@ -21,7 +21,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import half_limit, log_case, make_operator, report_half, to_dev
+from gpu_util import HALF_BOUND, half_limit, log_case, make_operator, report_half, to_dev
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "headline_ref.npz")
@@ -58,7 +58,9 @@ def test_headline_batch256(dtypes):
           f"p95 {np.percentile(rel, 95):.3e}, median {np.median(rel):.3e}; min-K rupture {idx[np.argmin(act)]} "
           f"{rel[np.argmin(act)]:.3e}, max-K rupture {idx[np.argmax(act)]} {rel[np.argmax(act)]:.3e}", flush=True)
     report_half(f"{dtype} B={B}", rel, mabs)
-    limit = half_limit(gdt, fdt)
+    # the timed store meets the bound on this workload (not on dense iid operators, where the
+    # bfloat16 elastic store alone adds about as much rounding: tests/test_gpu_half.py)
+    limit = HALF_BOUND if (gdt, fdt) == ("bf16", "f16") else half_limit(gdt, fdt)
     assert rel.max() <= limit and mabs.max() <= limit
     del op
     torch.cuda.empty_cache()
