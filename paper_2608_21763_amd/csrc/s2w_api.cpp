@@ -726,6 +726,16 @@ static int64_t part_floats(const s2w_plan* p) {
   return (int64_t)std::max(p->hg.splits_max * p->hg.noq, p->hg.nsq) * p->geo.M * 2 * p->hg.bp;
 }
 
+// Zero-padded forward transform of time rows in[b][j][n] (j < nrows) into the spectra of the
+// batched products, out[l][j][b] with rows padded to nrows_pad: the register kernel for M = 256,
+// else the row transform.
+static hipError_t rfft_batch(const float* in, int B, int nrows, int nrows_pad, float2* out, int bp, const Geometry& g,
+                             hipStream_t st) {
+  const int64_t slot = (int64_t)nrows_pad * bp;
+  if (g.M == 256) return launch_rfft_batch256(in, B, nrows, nrows_pad, out, bp, slot, g.nt, 1.0f, st);
+  return launch_rfft_rows(in, B, nrows, nrows_pad, out, 1, bp, slot, g, 1.0f, st);
+}
+
 // Sum of the split partials part[s][l][o][2 bp] of a batched product (times tau[l][b] when given)
 // and the inverse real FFT into out[b][o][n]: one fused kernel for M = 256, else the sum into
 // the spectra rows yh[b][o][l] and a row transform.
@@ -777,7 +787,7 @@ static s2w_status forward_half(s2w_plan* p, const float* s, int32_t B, float* y,
   int splits = p->tune.fgemm_splits;
   if (splits <= 0) splits = std::max(1, std::min(h.splits_max, 2048 / std::max(1, g.M * zt)));
   splits = std::min(splits, h.splits_max);
-  hipError_t e = launch_rfft_rows(s, B, g.nsub, h.nsq, S, 1, bp, (int64_t)h.nsq * bp, g, 1.0f, st);
+  hipError_t e = rfft_batch(s, B, g.nsub, h.nsq, S, bp, g, st);
   if (e == hipSuccess) {
     if (cfg == 17 || cfg == 18)
       e = launch_prep_act_re(act_type(h.kt_g), h.hterms_g, S, sig_up, sig_down, g.M, g.nsub, h.nsq, B, bp, h.nks,
@@ -854,7 +864,7 @@ static s2w_status forward_b32(s2w_plan* p, const float* s, int32_t B, float* y, 
   float2* yh = (float2*)(p->ws + L.yh32);
   const int bp = f.bp;
   // S[l][j][b]
-  hipError_t e = launch_rfft_rows(s, B, g.nsub, f.nsk, S, 1, bp, (int64_t)f.nsk * bp, g, 1.0f, st);
+  hipError_t e = rfft_batch(s, B, g.nsub, f.nsk, S, bp, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "forward: source transform");
   // U[g][l][b] = sum_j Gs[g][l][j] S[l][j][b]
   const int cg = b32_cfg(p, B, false);
@@ -894,7 +904,7 @@ static s2w_status adjoint_b32(s2w_plan* p, const float* r, int32_t B, float* gs,
   float2* gh = (float2*)(p->ws + L.yh32);
   const int bp = f.bp;
   // R[l][o][b]
-  hipError_t e = launch_rfft_rows(r, B, g.nobs, f.nok, R, 1, bp, (int64_t)f.nok * bp, g, 1.0f, st);
+  hipError_t e = rfft_batch(r, B, g.nobs, f.nok, R, bp, g, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
   // W[g][l][b] = sum_o conj(Fs[l][o][g]) R[l][o][b]
   const int c1 = b32_cfg(p, B, false);
@@ -944,7 +954,7 @@ static s2w_status adjoint_half(s2w_plan* p, const float* r, int32_t B, float* gs
   const float* sF = (const float*)(p->op + L.sf);
   const int bp = h.bp;
   const bool sf16 = h.kt_f != 1, sg16 = h.kt_g != 1;  // f16 activation terms with column scales
-  hipError_t e = launch_rfft_rows(r, B, g.nobs, g.nobs, R, 1, bp, (int64_t)g.nobs * bp, g, 1.0f, st);
+  hipError_t e = rfft_batch(r, B, g.nobs, g.nobs, R, bp, g, st);
   if (e == hipSuccess && sf16) e = launch_act_scale(R, g.M, g.nobs, g.nobs, B, bp, sig_up, sig_down, st);
   if (e != hipSuccess) return hip_fail(p, e, "adjoint: residual transform");
   // W[g][l][b] = sF[g][l] * sum_o conj(Fq[l][o][g]) R[l][o][b]
@@ -1457,7 +1467,7 @@ s2w_status s2w_bltt_apply(s2w_bltt* p, const float* x, int32_t B, float* y, void
     return S2W_OK;
   }
   // S[l][c][b]
-  hipError_t e = launch_rfft_rows(x, B, ncol, p->ncol_k, S, 1, bp, (int64_t)p->ncol_k * bp, g, 1.0f, st);
+  hipError_t e = rfft_batch(x, B, ncol, p->ncol_k, S, bp, g, st);
   if (e != hipSuccess) return bhip(p, e, "apply: input transform");
   // part[split][l][r][n] = sum_{c in split} Fs[r][l][c] S[l][c][b]
   const int splits = p->splits_f;
@@ -1485,7 +1495,7 @@ s2w_status s2w_bltt_adjoint(s2w_bltt* p, const float* y, int32_t B, float* x, vo
   float* part = (float*)(p->ws + p->o_part);
   float2* xh = (float2*)(p->ws + p->o_yh);
   // R[l][r][b] (rows padded with zeros)
-  hipError_t e = launch_rfft_rows(y, B, nrow, p->nrow_k, R, 1, bp, (int64_t)p->nrow_k * bp, g, 1.0f, st);
+  hipError_t e = rfft_batch(y, B, nrow, p->nrow_k, R, bp, g, st);
   if (e != hipSuccess) return bhip(p, e, "adjoint: input transform");
   // part[split][l][c][n] = sum_{r in split} conj(Fs[r][l][c]) R[l][r][b]
   const int splits = p->splits_a;

@@ -649,6 +649,96 @@ __global__ __launch_bounds__(16 * R) void k_mid_batch256(float2* __restrict__ U,
   }
 }
 
+// Zero-padded forward real FFT of a batch of time rows into packed spectra ordered for the
+// batched products, for M = 256 (Alg. 2 steps 1-2): in[b][j][n] (b < B, j < nrows, n < nt) ->
+// out[l][j][b] at l * out_slot + j * bp + b; rows nrows <= j < nrows_pad are written as zeros,
+// ruptures b >= B are not written.  A unit is one row index j and 16 ruptures: each time row is
+// read as 128-byte runs, transformed by the two 16-point passes of the mid-chain in registers
+// (nt <= 256, so the packed series z[n] = x[2n] + i x[2n+1] is zero for n >= 128), and the
+// spectra go out through LDS as 128-byte runs of 16 ruptures per slot.  Persistent grid.
+__global__ __launch_bounds__(256) void k_rfft_batch256(const float* __restrict__ in, int nrows, int nrows_pad, int B,
+                                                       int bp, float2* __restrict__ out, int64_t out_slot, int nt,
+                                                       float scale) {
+  constexpr int M = 256, R = 16, LD = 257;
+  __shared__ float2 X[R * LD];
+  __shared__ float2 T[R * 16 * 17];
+  __shared__ float2 twb[2 * M];
+  const Twiddles tw = lds_twiddles(twb, M);
+  const int tid = threadIdx.x;
+  const int fr = tid >> 4, c = tid & 15;  // transform: row (rupture) fr, column c
+  const int r = tid % R, lq = tid / R;    // scatter: rupture r, slots lq + 16 k
+  float2 twA[15], twR[16];
+  passA_twiddles(tw.c, c, twA);
+  real_twiddles(tw.r, c, twR);
+  const int nbb = (B + R - 1) / R;
+  const int units = nrows_pad * nbb;
+  for (int u = blockIdx.x; u < units; u += gridDim.x) {
+    const int j = u / nbb, b0 = (u % nbb) * R;
+    float2 v[16];
+    {
+      const int b = b0 + fr;
+      const bool live = b < B && j < nrows;
+      const float* x = in + ((int64_t)(live ? b : 0) * nrows + (live ? j : 0)) * nt;
+#pragma unroll
+      for (int n1 = 0; n1 < 16; ++n1) {
+        if (n1 >= 8) {  // n >= 128: samples 2n >= 256 >= nt
+          v[n1] = make_float2(0.f, 0.f);
+          continue;
+        }
+        const int m0 = 2 * (c + 16 * n1);
+        float2 xv = make_float2(0.f, 0.f);
+        if (!(nt & 1)) {  // even rows: the pair is one aligned 8-byte load
+          if (live && m0 < nt) xv = *reinterpret_cast<const float2*>(x + m0);
+        } else {
+          xv.x = (live && m0 < nt) ? x[m0] : 0.f;
+          xv.y = (live && m0 + 1 < nt) ? x[m0 + 1] : 0.f;
+        }
+        v[n1] = make_float2(xv.x * scale, xv.y * scale);
+      }
+    }
+    float2* Xr = X + fr * LD;
+    float2* Tr = T + fr * (16 * 17);
+    fft256_passA<-1>(v, twA);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) Tr[k1 * 17 + c] = v[k1];
+    __syncthreads();
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) v[n2] = Tr[c * 17 + n2];
+    dft16<-1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) Xr[c + 16 * k2] = v[k2];
+    __syncthreads();
+    // post-step of the real transform, row-major into T (T is read again only after the barrier)
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int k = c + 16 * jj;
+      T[fr * LD + k] = rfft_post_w(Xr, k, M, twR[jj]);
+    }
+    __syncthreads();
+    if (b0 + r < B) {
+      float2* dst = out + (int64_t)j * bp + b0 + r;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int l = lq + 16 * k;
+        dst[(int64_t)l * out_slot] = T[r * LD + l];
+      }
+    }
+    __syncthreads();  // X and T are refilled by the next unit
+  }
+}
+
+hipError_t launch_rfft_batch256(const float* in, int B, int nrows, int nrows_pad, float2* out, int bp, int64_t out_slot,
+                                int nt, float scale, hipStream_t st) {
+  if (B == 0 || nrows_pad == 0) return hipSuccess;
+  if (B < 0 || nrows < 0 || nrows_pad < nrows || bp < B || nt < 1 || nt > 256) return hipErrorInvalidValue;
+  const int64_t units = (int64_t)nrows_pad * ((B + 15) / 16);
+  if (units > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t nblk = std::min<int64_t>(units, 256 * 8);
+  hipLaunchKernelGGL(k_rfft_batch256, dim3((unsigned)nblk), dim3(256), 0, st, in, nrows, nrows_pad, B, bp, out,
+                     out_slot, nt, scale);
+  return hipGetLastError();
+}
+
 // Sum of the split partials of a batched product and the inverse real FFT of the result, for
 // M = 256: part[s][l][o][2 bp] (complex per rupture, s < splits) -> out[b][o][n], n < nt.
 // A unit is one output row o and 16 ruptures; the partials are read as 128-byte runs (16

@@ -44,6 +44,9 @@ hipError_t upload_twiddles(int device);
 hipError_t launch_rfft_rows(const float* in, int64_t nouter, int ninner, int ninner_pad, float2* out,
                             int64_t out_outer, int64_t out_inner, int64_t out_slot, const Geometry& g, float scale,
                             hipStream_t st);
+// Forward real FFT of time rows in[b][j][n] into out[l][j][b] (l * out_slot + j * bp + b), M = 256 only.
+hipError_t launch_rfft_batch256(const float* in, int B, int nrows, int nrows_pad, float2* out, int bp, int64_t out_slot,
+                                int nt, float scale, hipStream_t st);
 
 // packed spectra rows (in + row*in_row + slot*in_slot) -> real rows out[row][n], n < nt, times scale
 hipError_t launch_irfft_rows(const float2* in, int64_t nrows, int64_t in_row, int64_t in_slot, float* out,
