@@ -523,9 +523,11 @@ __global__ __launch_bounds__(64 * WR * WC, MINB) void k_gemm_g4(const uint4* __r
   const int a_rr = lane >> 2, a_c = (lane & 3) ^ ((a_rr >> 1) & 3);
   // start skew: every workgroup runs the same sequence of equal tiles, so without it all of them
   // reach their epilogue (the U stores of a tile) at the same moment; sixteen start offsets of
-  // about 4 us spread those store bursts over the read stream of the other workgroups
-  // (0.4 ms less per call at B = 256, tile 24, same box alternating).  At most about 50 us.
-  for (int i = 0; i < (wi & 15); ++i) __builtin_amdgcn_s_sleep(127);
+  // about 4 us spread those store bursts over the read stream of the other workgroups (0.3-0.4 ms
+  // less per call at B = 256, tile 24, same box alternating).  Workgroups 2m and 2m + 1 of an
+  // XCD, which take the two column tiles of the same operator rows, keep one offset, so that the
+  // second still finds those rows in L2.  At most about 50 us.
+  for (int i = 0; i < ((wi >> 1) & 15); ++i) __builtin_amdgcn_s_sleep(127);
   for (int64_t it = wi; it < items; it += nwx) {
     const int l = x + nx * (int)(it / per_slot);
     const int64_t rem = it % per_slot;
