@@ -165,3 +165,22 @@ def test_steps_below_256_on_256_bins(nt, layout, dtype):
     tol = TOL if dtype == "f32" else 2e-3
     print(dtype, nt, "forward", ey.max(), "adjoint", eg.max())
     assert ey.max() <= tol and eg.max() <= tol
+
+
+def test_adjoint_tile_control_round_trip():
+    # adj32_cfg sets the adjoint's elastic reduction tile on its own: out-of-range ids are
+    # refused, and get -> set keeps the public values
+    from paper_2608_21763_amd import S2WError
+    cfg = synth.workload("small_dense")
+    log_case("b32_adj32_cfg")
+    op = make_operator(cfg, max_batch=4, layout="batched")
+    for bad in (5, -2):
+        with pytest.raises(S2WError):
+            op.set_tuning(adj32_cfg=bad)
+    op.set_tuning(adj32_cfg=2, gemm32_cfg_k=4)
+    t = op.get_tuning()
+    assert t["adj32_cfg"] == 2 and t["gemm32_cfg_k"] == 4
+    op.set_tuning(**t)
+    assert op.get_tuning() == t
+    op.set_tuning(adj32_cfg=-1)
+    assert op.get_tuning()["adj32_cfg"] == -1
